@@ -1,0 +1,472 @@
+/*
+ * l1line_oracle.c -- exact CPU oracle for the sparse robust l1 best-fit line
+ * (Ling & Brooks, "l1-Norm Regularized l1-Norm Best-Fit Lines").
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this file.  It shares no code with the
+ * GPU library and is written to be checked against the paper by eye: plain
+ * loops, a library sort, no blocking or fusion.
+ *
+ * WHAT IT COMPUTES
+ *   X is n x m, column-major (x(i,k) = X[i + k*ld]); rows i are points,
+ *   columns are coordinates.  For a preserved coordinate j (the paper's
+ *   j-hat) the LP (3) of Sec. 2 splits, by the proof of Lemma 1, into one
+ *   problem per other column k:
+ *       g_jk(v) = sum_{i: x_ij != 0} |x_ij| * |r_i - v|  +  lambda |v|
+ *                 + sum_{i: x_ij == 0} |x_ik|,      r_i = x_ik / x_ij.
+ *   g_jk is convex and piecewise linear; its minimisers are weighted medians
+ *   of the points r_i (weights |x_ij|) together with the point 0 (weight
+ *   lambda).  Algorithm 1 then sets v_j = 1, takes every v_k, scores
+ *       z_j = sum_i sum_k |x_ik - v_k x_ij|  +  lambda sum_k |v_k|
+ *   (the penalty includes |v_j| = 1) and keeps the j with the smallest z_j,
+ *   the first one on ties (strict "<" over ascending j).
+ *
+ * READINGS WHERE THE PAPER LEAVES A CHOICE
+ *   ratios   r_i = fl(x_ik / x_ij) + 0.0: IEEE double division, round to
+ *            nearest, then -0 turned into +0.  Points are ordered by
+ *            (r_i, i) ascending.
+ *   exact    every sum of weights and every comparison of such sums with
+ *            lambda is EXACT: a finite double is an integer multiple of
+ *            2^-1074, so sums are held as big integers in those units.  The
+ *            selection is therefore the real-number weighted median, free of
+ *            any summation order.
+ *   tie rule Lemma 1 accepts every point that meets its condition
+ *            (solncond); several points (or 0) can be minimisers when
+ *            g_jk has a flat piece.  Rule R3: v_k = 0 when 0 minimises g_jk,
+ *            else the minimiser closest to 0.  With S_p the exact sum of the
+ *            first p weights in sorted order, W = S_n', A = S_N (N points
+ *            below 0), B = S_{N+Z} (Z points equal to 0):
+ *              zero      if 2A <= W + lambda  and  W <= 2B + lambda
+ *              negative  if 2A >  W + lambda: first p <= N with 2 S_p > W + lambda
+ *              positive  otherwise:           first p >  N+Z with 2 S_p + lambda >= W
+ *            tie_rule = 1 instead runs the test of Algorithm 1 verbatim
+ *            (half-open interval, last match wins, default 0), reading the
+ *            unbound index in its sgn(.) as the tested point.
+ *   zero column  a column j with no nonzero entry gives v = e_j (v_j = 1,
+ *            every other v_k = 0), as Algorithm 1 does.
+ *   floating sums  the reported sums (column mass, residual e_jk, E_j, P_j)
+ *            use the fixed order R64: term t goes to partial t mod 64 (each
+ *            partial summed in increasing t from +0.0), then
+ *            p[l] = p[l] + p[l+d] for d = 32,16,8,4,2,1 and l < d; result p[0].
+ *            The residual term is |x_ik - fl(v_k * x_ij)| with three separate
+ *            roundings (no fused multiply-add).
+ *
+ * STATUS CODES (returned by every entry point)
+ *    0  ok
+ *   -1  invalid argument (n < 1, m < 1, ld < n, L < 1, lambda < 0 or NaN,
+ *       null pointer, j or k out of range)
+ *   -3  X holds a NaN or an infinity
+ *   -4  a selected ratio overflowed to +-inf (results then unspecified)
+ *   -5  out of host memory
+ *
+ * PINS (tests/test_oracle_*.py): the worked example of Sec. 3.1 (Table I,
+ * Fig. 1 lines, the breakpoints and the maximum useful lambda), exact
+ * rational brute force over every breakpoint on tiny inputs, an LP solver on
+ * LP (4), the dual certificate of Lemma 1's proof, the closed form for the
+ * smallest lambda that zeroes v_k (Lemma 1's proof, Algorithm 2), lambda = 0
+ * as plain weighted-median (LAD) regression, and exact invariances.
+ */
+#include <math.h>
+#include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENONFINITE (-3)
+#define OR_ERANGE (-4)
+#define OR_ENOMEM (-5)
+
+/* ------------------------------------------------------------------ big */
+/* Non-negative integers in units of 2^-1074, 64-bit limbs, little endian.
+ * A finite double is below 2^1024 = 2^2098 units; sums of up to 2^31 terms
+ * and their doubles stay below 2^2131, so 36 limbs (2304 bits) suffice. */
+#define NLIMB 36
+typedef struct { uint64_t d[NLIMB]; } big;
+
+static void big_zero(big *a) { memset(a, 0, sizeof *a); }
+
+/* a += |x| for a finite double x */
+static void big_add_double(big *a, double x)
+{
+    uint64_t bits;
+    memcpy(&bits, &x, sizeof bits);
+    uint64_t bexp = (bits >> 52) & 0x7ff;
+    uint64_t mant = bits & ((1ull << 52) - 1);
+    uint64_t shift;
+    if (bexp == 0) {              /* subnormal or zero: mant * 2^-1074 */
+        shift = 0;
+    } else {                      /* normal: (2^52 + mant) * 2^(bexp-1075) */
+        mant |= 1ull << 52;
+        shift = bexp - 1;
+    }
+    if (mant == 0) return;
+    unsigned limb = (unsigned)(shift / 64), off = (unsigned)(shift % 64);
+    uint64_t lo = mant << off;
+    uint64_t hi = off ? (mant >> (64 - off)) : 0;
+    unsigned __int128 c = (unsigned __int128)a->d[limb] + lo;
+    a->d[limb] = (uint64_t)c;
+    c = (unsigned __int128)a->d[limb + 1] + hi + (uint64_t)(c >> 64);
+    a->d[limb + 1] = (uint64_t)c;
+    uint64_t carry = (uint64_t)(c >> 64);
+    for (unsigned t = limb + 2; carry && t < NLIMB; ++t) {
+        c = (unsigned __int128)a->d[t] + carry;
+        a->d[t] = (uint64_t)c;
+        carry = (uint64_t)(c >> 64);
+    }
+}
+
+/* r = a + b */
+static void big_add(big *r, const big *a, const big *b)
+{
+    uint64_t carry = 0;
+    for (int t = 0; t < NLIMB; ++t) {
+        unsigned __int128 c = (unsigned __int128)a->d[t] + b->d[t] + carry;
+        r->d[t] = (uint64_t)c;
+        carry = (uint64_t)(c >> 64);
+    }
+}
+
+/* r = 2a */
+static void big_twice(big *r, const big *a) { big_add(r, a, a); }
+
+static int big_cmp(const big *a, const big *b)
+{
+    for (int t = NLIMB - 1; t >= 0; --t) {
+        if (a->d[t] != b->d[t]) return a->d[t] < b->d[t] ? -1 : 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ R64 */
+static double r64_sum(const double *terms, int64_t count)
+{
+    double p[64];
+    for (int l = 0; l < 64; ++l) p[l] = 0.0;
+    for (int64_t t = 0; t < count; ++t) p[t % 64] = p[t % 64] + terms[t];
+    for (int d = 32; d >= 1; d /= 2)
+        for (int l = 0; l < d; ++l) p[l] = p[l] + p[l + d];
+    return p[0];
+}
+
+/* --------------------------------------------------------------- points */
+typedef struct {
+    double r;      /* fl(x_ik / x_ij) + 0.0 */
+    int64_t row;   /* i */
+    double w;      /* |x_ij| */
+} point;
+
+static int point_cmp(const void *pa, const void *pb)
+{
+    const point *a = (const point *)pa, *b = (const point *)pb;
+    if (a->r < b->r) return -1;
+    if (a->r > b->r) return 1;
+    if (a->row < b->row) return -1;
+    if (a->row > b->row) return 1;
+    return 0;
+}
+
+#define XAT(X, ld, i, k) ((X)[(i) + (k) * (ld)])
+
+/* Sorted ratio list of segment (j, k): fills pts (capacity n), returns n'. */
+static int64_t build_points(const double *X, int64_t n, int64_t ld, int64_t j,
+                           int64_t k, point *pts)
+{
+    int64_t np = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double xj = XAT(X, ld, i, j);
+        if (xj == 0.0) continue;
+        double r = XAT(X, ld, i, k) / xj;
+        pts[np].r = r + 0.0;
+        pts[np].row = i;
+        pts[np].w = fabs(xj);
+        ++np;
+    }
+    qsort(pts, (size_t)np, sizeof(point), point_cmp);
+    return np;
+}
+
+/* Selection for one lambda on a sorted list (rule R3 or Algorithm 1).
+ * Returns the position (0-based) of the chosen point, or -1 for v = 0. */
+static int64_t select_point(const point *pts, int64_t np, double lambda,
+                            int tie_rule)
+{
+    big W, lam, S, twoS, rhs, lhs;
+    big_zero(&W);
+    for (int64_t p = 0; p < np; ++p) big_add_double(&W, pts[p].w);
+    big_zero(&lam);
+    big_add_double(&lam, lambda);
+
+    if (tie_rule == 1) {
+        /* Algorithm 1 verbatim: for each point in sorted order, accept it when
+         * sgn(r) * lambda lies in (W - 2 S_p, W - 2 S_{p-1}]; last one wins. */
+        int64_t chosen = -1;
+        big Sprev;
+        big_zero(&Sprev);
+        for (int64_t p = 0; p < np; ++p) {
+            S = Sprev;
+            big_add_double(&S, pts[p].w);          /* S = S_p, p 1-based */
+            big twoSprev;
+            big_twice(&twoSprev, &Sprev);
+            big_twice(&twoS, &S);
+            int ok;
+            if (pts[p].r > 0.0) {          /* 2 S_{p-1} + lam <= W < 2 S_p + lam */
+                big_add(&lhs, &twoSprev, &lam);
+                big_add(&rhs, &twoS, &lam);
+                ok = big_cmp(&lhs, &W) <= 0 && big_cmp(&W, &rhs) < 0;
+            } else if (pts[p].r < 0.0) {   /* 2 S_{p-1} <= W + lam < 2 S_p */
+                big_add(&rhs, &W, &lam);
+                ok = big_cmp(&twoSprev, &rhs) <= 0 && big_cmp(&rhs, &twoS) < 0;
+            } else {                       /* 2 S_{p-1} <= W < 2 S_p */
+                ok = big_cmp(&twoSprev, &W) <= 0 && big_cmp(&W, &twoS) < 0;
+            }
+            if (ok) chosen = p;
+            Sprev = S;
+        }
+        return chosen;
+    }
+
+    /* Rule R3. */
+    int64_t N = 0, Z = 0;
+    while (N < np && pts[N].r < 0.0) ++N;
+    while (N + Z < np && pts[N + Z].r == 0.0) ++Z;
+    big A, B, twoA, twoB, WpL;
+    big_zero(&A);
+    for (int64_t p = 0; p < N; ++p) big_add_double(&A, pts[p].w);
+    B = A;
+    for (int64_t p = N; p < N + Z; ++p) big_add_double(&B, pts[p].w);
+    big_twice(&twoA, &A);
+    big_twice(&twoB, &B);
+    big_add(&WpL, &W, &lam);
+    big twoBpL;
+    big_add(&twoBpL, &twoB, &lam);
+
+    if (big_cmp(&twoA, &WpL) <= 0 && big_cmp(&W, &twoBpL) <= 0)
+        return -1;                                   /* 0 is a minimiser */
+    big_zero(&S);
+    if (big_cmp(&twoA, &WpL) > 0) {                  /* minimiser below 0 */
+        for (int64_t p = 0; p < N; ++p) {
+            big_add_double(&S, pts[p].w);
+            big_twice(&twoS, &S);
+            if (big_cmp(&twoS, &WpL) > 0) return p;
+        }
+        return -2;                                   /* unreachable */
+    }
+    S = B;                                           /* minimiser above 0 */
+    for (int64_t p = N + Z; p < np; ++p) {
+        big_add_double(&S, pts[p].w);
+        big_twice(&twoS, &S);
+        big_add(&lhs, &twoS, &lam);
+        if (big_cmp(&lhs, &W) >= 0) return p;
+    }
+    return -2;                                       /* unreachable */
+}
+
+/* e_jk = R64 over i of |x_ik - fl(v * x_ij)|; terms is scratch of length n */
+static double residual(const double *X, int64_t n, int64_t ld, int64_t j,
+                       int64_t k, double v, double *terms)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double prod = v * XAT(X, ld, i, j);
+        double diff = XAT(X, ld, i, k) - prod;
+        terms[i] = fabs(diff);
+    }
+    return r64_sum(terms, n);
+}
+
+static int check_x(const double *X, int64_t n, int64_t m, int64_t ld)
+{
+    if (!X || n < 1 || m < 1 || ld < n) return OR_EINVAL;
+    for (int64_t k = 0; k < m; ++k)
+        for (int64_t i = 0; i < n; ++i)
+            if (!isfinite(XAT(X, ld, i, k))) return OR_ENONFINITE;
+    return OR_OK;
+}
+
+static int check_lambdas(const double *lam, int64_t L)
+{
+    if (!lam || L < 1) return OR_EINVAL;
+    for (int64_t t = 0; t < L; ++t)
+        if (!(lam[t] >= 0.0) || isinf(lam[t])) return OR_EINVAL;
+    return OR_OK;
+}
+
+/* ============================================================ entry points */
+
+/* Column mass W_j = R64_i |x_ij| and zero count Z_j = #{i : x_ij == 0}. */
+int oracle_column_stats(const double *X, int64_t n, int64_t m, int64_t ld,
+                        double *W, int64_t *zeros)
+{
+    int st = check_x(X, n, m, ld);
+    if (st) return st;
+    double *terms = (double *)malloc((size_t)n * sizeof(double));
+    if (!terms) return OR_ENOMEM;
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t z = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            terms[i] = fabs(XAT(X, ld, i, k));
+            if (XAT(X, ld, i, k) == 0.0) ++z;
+        }
+        if (W) W[k] = r64_sum(terms, n);
+        if (zeros) zeros[k] = z;
+    }
+    free(terms);
+    return OR_OK;
+}
+
+/* One segment (j, k != j) for L penalties: v[t], row[t] (-1 when v = 0) and
+ * e[t] = e_jk(lambda_t).  Sorts once and reuses the list for every lambda. */
+int oracle_segment(const double *X, int64_t n, int64_t m, int64_t ld,
+                   int64_t j, int64_t k, const double *lambdas, int64_t L,
+                   int tie_rule, double *v, int32_t *row, double *e)
+{
+    int st = check_x(X, n, m, ld);
+    if (st) return st;
+    st = check_lambdas(lambdas, L);
+    if (st) return st;
+    if (j < 0 || j >= m || k < 0 || k >= m || j == k || !v) return OR_EINVAL;
+    point *pts = (point *)malloc((size_t)n * sizeof(point));
+    double *terms = (double *)malloc((size_t)n * sizeof(double));
+    if (!pts || !terms) { free(pts); free(terms); return OR_ENOMEM; }
+    int64_t np = build_points(X, n, ld, j, k, pts);
+    int status = OR_OK;
+    for (int64_t t = 0; t < L; ++t) {
+        int64_t p = select_point(pts, np, lambdas[t], tie_rule);
+        double vk = p >= 0 ? pts[p].r : 0.0;
+        if (isinf(vk)) status = OR_ERANGE;
+        v[t] = vk;
+        if (row) row[t] = p >= 0 ? (int32_t)pts[p].row : -1;
+        if (e) e[t] = residual(X, n, ld, j, k, vk, terms);
+    }
+    free(pts);
+    free(terms);
+    return status;
+}
+
+/* Everything for one preserved coordinate j and L penalties:
+ *   V[t*m + k] = v_k, ROW[t*m + k] (-1 for v_k = 0 and for k = j),
+ *   EJK[t*m + k] = e_jk (e_jj = +0), and per lambda
+ *   EJ[t] = R64_k e_jk, PJ[t] = R64_k |v_k|, ZJ[t] = EJ + fl(lambda * PJ).
+ * Any output pointer may be NULL. */
+int oracle_fit_j(const double *X, int64_t n, int64_t m, int64_t ld, int64_t j,
+                 const double *lambdas, int64_t L, int tie_rule, double *V,
+                 int32_t *ROW, double *EJK, double *EJ, double *PJ, double *ZJ)
+{
+    int st = check_x(X, n, m, ld);
+    if (st) return st;
+    st = check_lambdas(lambdas, L);
+    if (st) return st;
+    if (j < 0 || j >= m) return OR_EINVAL;
+    point *pts = (point *)malloc((size_t)n * sizeof(point));
+    double *terms = (double *)malloc((size_t)(n > m ? n : m) * sizeof(double));
+    double *vv = (double *)malloc((size_t)(L * m) * sizeof(double));
+    double *ee = (double *)malloc((size_t)(L * m) * sizeof(double));
+    int32_t *rr = (int32_t *)malloc((size_t)(L * m) * sizeof(int32_t));
+    if (!pts || !terms || !vv || !ee || !rr) {
+        free(pts); free(terms); free(vv); free(ee); free(rr);
+        return OR_ENOMEM;
+    }
+    int status = OR_OK;
+    for (int64_t k = 0; k < m; ++k) {
+        if (k == j) {
+            for (int64_t t = 0; t < L; ++t) {
+                vv[t * m + k] = 1.0;
+                ee[t * m + k] = 0.0;
+                rr[t * m + k] = -1;
+            }
+            continue;
+        }
+        int64_t np = build_points(X, n, ld, j, k, pts);
+        for (int64_t t = 0; t < L; ++t) {
+            int64_t p = select_point(pts, np, lambdas[t], tie_rule);
+            double vk = p >= 0 ? pts[p].r : 0.0;
+            if (isinf(vk)) status = OR_ERANGE;
+            vv[t * m + k] = vk;
+            rr[t * m + k] = p >= 0 ? (int32_t)pts[p].row : -1;
+            ee[t * m + k] = residual(X, n, ld, j, k, vk, terms);
+        }
+    }
+    for (int64_t t = 0; t < L; ++t) {
+        double E = r64_sum(ee + t * m, m);
+        for (int64_t k = 0; k < m; ++k) terms[k] = fabs(vv[t * m + k]);
+        double P = r64_sum(terms, m);
+        double pen = lambdas[t] * P;
+        double z = E + pen;
+        if (EJ) EJ[t] = E;
+        if (PJ) PJ[t] = P;
+        if (ZJ) ZJ[t] = z;
+    }
+    if (V) memcpy(V, vv, (size_t)(L * m) * sizeof(double));
+    if (EJK) memcpy(EJK, ee, (size_t)(L * m) * sizeof(double));
+    if (ROW) memcpy(ROW, rr, (size_t)(L * m) * sizeof(int32_t));
+    free(pts); free(terms); free(vv); free(ee); free(rr);
+    return status;
+}
+
+/* Algorithm 1 over a path of L penalties (L = 1 is a single fit):
+ *   V[t*m + k] = v*_k(lambda_t), J[t] = j*, OBJ[t] = z_{j*},
+ *   ROW[t*m + k] = sorted-point row that gave v*_k (-1 if v*_k = 0 or k = j*),
+ *   ZALL[t*m + j] = z_j(lambda_t) for every j.
+ * Candidates j run in parallel (OpenMP, `nthreads` threads, <= 0: default);
+ * each j is computed independently and the argmin is taken serially. */
+int oracle_fit_path(const double *X, int64_t n, int64_t m, int64_t ld,
+                    const double *lambdas, int64_t L, int tie_rule,
+                    int nthreads, double *V, int64_t *J, double *OBJ,
+                    int32_t *ROW, double *ZALL)
+{
+    int st = check_x(X, n, m, ld);
+    if (st) return st;
+    st = check_lambdas(lambdas, L);
+    if (st) return st;
+    if (!V || !J || !OBJ) return OR_EINVAL;
+    double *Vall = (double *)malloc((size_t)(m * L * m) * sizeof(double));
+    int32_t *Rall = (int32_t *)malloc((size_t)(m * L * m) * sizeof(int32_t));
+    double *Z = (double *)malloc((size_t)(m * L) * sizeof(double));
+    int *stj = (int *)calloc((size_t)m, sizeof(int));
+    if (!Vall || !Rall || !Z || !stj) {
+        free(Vall); free(Rall); free(Z); free(stj);
+        return OR_ENOMEM;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t j = 0; j < m; ++j) {
+        stj[j] = oracle_fit_j(X, n, m, ld, j, lambdas, L, tie_rule,
+                              Vall + j * L * m, Rall + j * L * m, NULL, NULL,
+                              NULL, Z + j * L);
+    }
+    int status = OR_OK;
+    for (int64_t j = 0; j < m; ++j)
+        if (stj[j] && (status == OR_OK || stj[j] != OR_ERANGE)) status = stj[j];
+    if (status != OR_OK && status != OR_ERANGE) {
+        free(Vall); free(Rall); free(Z); free(stj);
+        return status;
+    }
+    for (int64_t t = 0; t < L; ++t) {
+        int64_t best = 0;
+        for (int64_t j = 1; j < m; ++j)
+            if (Z[j * L + t] < Z[best * L + t]) best = j;
+        J[t] = best;
+        OBJ[t] = Z[best * L + t];
+        memcpy(V + t * m, Vall + best * L * m + t * m, (size_t)m * sizeof(double));
+        if (ROW) memcpy(ROW + t * m, Rall + best * L * m + t * m, (size_t)m * sizeof(int32_t));
+        if (ZALL)
+            for (int64_t j = 0; j < m; ++j) ZALL[t * m + j] = Z[j * L + t];
+    }
+    free(Vall); free(Rall); free(Z); free(stj);
+    return status;
+}
+
+/* Threads OpenMP will use for oracle_fit_path (1 without OpenMP). */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

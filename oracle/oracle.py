@@ -1,0 +1,149 @@
+"""ctypes front end of the exact CPU oracle (l1line_oracle.c).
+
+TEST INFRASTRUCTURE: only tests/, the smoke check and the benchmark's CPU
+baseline leg import this module.  It never touches the GPU library.
+
+All arrays are numpy; X is n x m FP64 and may be C- or F-ordered (it is
+copied to column-major).  Indices are 0-based.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "l1line_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+OK, EINVAL, ENONFINITE, ERANGE, ENOMEM = 0, -1, -3, -4, -5
+
+TIE_R3 = 0     # zero if zero minimises, else the minimiser closest to zero
+TIE_ALG1 = 1   # Algorithm 1's interval test verbatim (last match wins)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                        "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        I = ctypes.c_int
+        lib.oracle_column_stats.argtypes = [P, I64, I64, I64, P, P]
+        lib.oracle_segment.argtypes = [P, I64, I64, I64, I64, I64, P, I64, I, P, P, P]
+        lib.oracle_fit_j.argtypes = [P, I64, I64, I64, I64, P, I64, I, P, P, P, P, P, P]
+        lib.oracle_fit_path.argtypes = [P, I64, I64, I64, P, I64, I, I, P, P, P, P, P]
+        for f in (lib.oracle_column_stats, lib.oracle_segment, lib.oracle_fit_j,
+                  lib.oracle_fit_path):
+            f.restype = ctypes.c_int
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _prep(X):
+    X = np.asfortranarray(np.asarray(X, dtype=np.float64))
+    if X.ndim != 2:
+        raise ValueError("X must be 2-D")
+    return X, X.shape[0], X.shape[1]
+
+
+def _lams(lambdas):
+    return np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+
+
+def _check(code, what, allow_erange=False):
+    if code != OK and not (allow_erange and code == ERANGE):
+        raise OracleError(code, what)
+    return code
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def column_stats(X):
+    """(W, zeros): W_j = R64-ordered sum_i |x_ij|, zeros_j = #{x_ij == 0}."""
+    X, n, m = _prep(X)
+    W = np.empty(m)
+    Z = np.empty(m, dtype=np.int64)
+    _check(_load().oracle_column_stats(_ptr(X), n, m, n, _ptr(W), _ptr(Z)), "column_stats")
+    return W, Z
+
+
+def segment(X, j, k, lambdas, tie_rule=TIE_R3):
+    """Per lambda: (v_k, row, e_jk) of the single problem (j, k)."""
+    X, n, m = _prep(X)
+    lam = _lams(lambdas)
+    L = lam.size
+    v = np.empty(L)
+    row = np.empty(L, dtype=np.int32)
+    e = np.empty(L)
+    code = _load().oracle_segment(_ptr(X), n, m, n, int(j), int(k), _ptr(lam), L,
+                                  int(tie_rule), _ptr(v), _ptr(row), _ptr(e))
+    _check(code, "segment", allow_erange=True)
+    return v, row, e
+
+
+def fit_j(X, j, lambdas, tie_rule=TIE_R3):
+    """Everything for one preserved coordinate j: dict of V, ROW, EJK (L x m)
+    and EJ, PJ, ZJ (L)."""
+    X, n, m = _prep(X)
+    lam = _lams(lambdas)
+    L = lam.size
+    out = dict(V=np.empty((L, m)), ROW=np.empty((L, m), dtype=np.int32),
+               EJK=np.empty((L, m)), EJ=np.empty(L), PJ=np.empty(L), ZJ=np.empty(L))
+    code = _load().oracle_fit_j(_ptr(X), n, m, n, int(j), _ptr(lam), L, int(tie_rule),
+                                _ptr(out["V"]), _ptr(out["ROW"]), _ptr(out["EJK"]),
+                                _ptr(out["EJ"]), _ptr(out["PJ"]), _ptr(out["ZJ"]))
+    out["status"] = _check(code, "fit_j", allow_erange=True)
+    return out
+
+
+def fit_path(X, lambdas, tie_rule=TIE_R3, nthreads=0):
+    """Algorithm 1 for each lambda: dict V (L x m), J (L), OBJ (L),
+    ROW (L x m), ZALL (L x m)."""
+    X, n, m = _prep(X)
+    lam = _lams(lambdas)
+    L = lam.size
+    out = dict(V=np.empty((L, m)), J=np.empty(L, dtype=np.int64), OBJ=np.empty(L),
+               ROW=np.empty((L, m), dtype=np.int32), ZALL=np.empty((L, m)))
+    code = _load().oracle_fit_path(_ptr(X), n, m, n, _ptr(lam), L, int(tie_rule), int(nthreads),
+                                   _ptr(out["V"]), _ptr(out["J"]), _ptr(out["OBJ"]),
+                                   _ptr(out["ROW"]), _ptr(out["ZALL"]))
+    out["status"] = _check(code, "fit_path", allow_erange=True)
+    return out
+
+
+def fit(X, lam, tie_rule=TIE_R3, nthreads=0):
+    """Algorithm 1 for one lambda: dict v (m), j, obj, row (m), z_all (m)."""
+    r = fit_path(X, [lam], tie_rule, nthreads)
+    return dict(v=r["V"][0], j=int(r["J"][0]), obj=float(r["OBJ"][0]), row=r["ROW"][0],
+                z_all=r["ZALL"][0], status=r["status"])
