@@ -1,0 +1,184 @@
+"""Benchmark: exhaustive fits of the sparse robust l1 line on one GPU.
+
+One step = one call of the whole hot path (column prep, every (j, k)
+weighted median with its residual, the per-j objectives, the argmin) on a
+2000 x 2000 FP64 matrix resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU lane-op issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (= the 78.6 TFLOP/s FP64 vector peak with an FMA counted as 2 flops).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU operations per ratio element of the segment kernel (see
+# DESIGN.md, "Roofline"): IEEE FP64 divide (10), key + sign classification
+# (4), exact 128-bit weight accumulation (4), residual mul/sub/add (3).
+OPS_PER_ELEMENT = 21
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    ap.add_argument("--cpu-columns", type=int, default=0, help="oracle sample size (columns j)")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2402_16712_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_key):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != _source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(p, lam, z_gpu, columns):
+    """Time the oracle on a bounded sample of candidate columns j (all k for
+    each), on every host core via a thread pool; check each sampled z_j
+    against the GPU bit for bit."""
+    from oracle import oracle as O
+    O.build()
+    cores = max(1, min(os.cpu_count() or 1, 32))
+    m = p.X.shape[1]
+    if columns <= 0:
+        columns = 2 * cores
+    rng = np.random.default_rng(1)
+    js = sorted(rng.choice(m, size=min(columns, m), replace=False).tolist())
+    X = np.asfortranarray(p.X)
+
+    def one(j):
+        return j, O.fit_j(X, j, [lam])["ZJ"][0]
+
+    O.fit_j(X, js[0], [lam])   # warm-up (page-in, library load)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        res = list(ex.map(one, js))
+    dt = time.perf_counter() - t0
+    mism = [j for j, z in res if np.float64(z).tobytes() != np.float64(z_gpu[j]).tobytes()]
+    fits_per_s = (len(js) / m) / dt
+    return dict(value=fits_per_s, unit="fits/s", cores=cores, kind="oracle",
+                sample=f"{len(js)} of {m} candidate columns j (all k each) of the timed "
+                       f"workload, {dt:.1f} s wall on {cores} threads; fits/s = "
+                       f"(columns/m)/seconds",
+                z_mismatches=len(mism))
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    p = wl.large_fit(a.seed)
+    n, m = p.X.shape
+    lam = float(p.lambdas[0])
+    ctx = B.Context(0)
+    X = B.device_matrix(p.X)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(a.warmup):
+        out = ctx.fit(X, lam)
+    torch.cuda.synchronize()
+    st = int(out["status"].item())
+    if st != 0:
+        raise SystemExit(f"fit status {st}: {B.strerror(st)}")
+
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(a.steps):
+        out = ctx.fit(X, lam)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kern = {}
+    for name in ("colprep", "fit_seg", "reduce", "argmin"):
+        ms, cnt = ctx.profile_read(name)
+        kern[name] = ms / max(cnt, 1)
+    ctx.profile_read(reset=True)
+    ctx.profile(False)
+
+    ms_per_step = total_ms / a.steps
+    fits_per_s = 1000.0 / ms_per_step
+    medians = m * (m - 1)
+    z_gpu = out["z_all"].cpu().numpy()
+    j_star = int(out["j"].item())
+
+    # roofline of the dominant kernel (one launch = one fit's m(m-1) segments)
+    nnz = np.count_nonzero(p.X, axis=0)
+    elements = float(nnz.sum()) * (m - 1)          # ratio elements per launch
+    seg_s = kern["fit_seg"] / 1000.0
+    achieved = elements * OPS_PER_ELEMENT / seg_s
+    roof = {"bound": "alu", "kernel": "k_fit_seg", "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
+            "frac": achieved / VALU_PEAK_OPS, "traffic": _traffic("fit_seg_2000x2000"),
+            "ops_per_element": OPS_PER_ELEMENT, "elements_per_launch": elements,
+            "avg_launch_ms": kern["fit_seg"]}
+
+    line = {
+        "metric": "fits/s & weighted-medians/s, 2000x2000 FP64; learned top-K vs exhaustive",
+        "value": fits_per_s,
+        "unit": "fits/s",
+        "medians_per_s": fits_per_s * medians,
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"exhaustive fit {n}x{m} FP64 (rank-one signal, Laplace noise, "
+                               f"10% outlier rows, 1% zeros), lambda = 0.05 * max column mass, "
+                               f"all {m} candidate j", "n": n, "m": m, "L": 1, "seed": a.seed},
+        "kernels_ms": kern,
+        "roofline": roof,
+        "j_star": j_star,
+    }
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(p, lam, z_gpu, a.cpu_columns)
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,138 @@
+/*
+ * l1line.h -- C ABI of the MI355X (gfx950) library for the sparse robust
+ * l1 best-fit line of Ling & Brooks, "l1-Norm Regularized l1-Norm Best-Fit
+ * Lines" (Sec. 2: LP (3), Lemma 1, Algorithm 1).
+ *
+ * THE METHOD
+ *   X is n x m (rows = points, columns = coordinates).  For every preserved
+ *   coordinate j the LP (3) separates (proof of Lemma 1, LP (4)) into m-1
+ *   one-dimensional problems, one per other column k:
+ *     v_k = argmin_v  sum_{i: x_ij != 0} |x_ij| |x_ik/x_ij - v| + lambda |v|
+ *   -- a weighted median of the n ratios plus the point 0 with weight lambda.
+ *   Algorithm 1 sets v_j = 1, scores
+ *     z_j = sum_i sum_k |x_ik - v_k x_ij| + lambda sum_k |v_k|
+ *   and returns the v of the smallest z_j.
+ *
+ * CONVENTIONS (identical in every entry point)
+ *   - X is column-major: x(i,k) = X[i + k*ld], ld >= n, FP64, a DEVICE
+ *     pointer.  Every other array argument is a DEVICE pointer too unless
+ *     its comment says HOST.  The caller allocates and frees all of them;
+ *     the library only owns the workspace inside its context.
+ *   - Indices are 0-based.  Penalties lambda are FP64, finite and >= 0.
+ *   - Ratios are r_i = fl(x_ik / x_ij) (IEEE division, round to nearest),
+ *     -0 taken as +0, ordered by (r_i, i).
+ *   - Every weight sum and every comparison of such sums with lambda is
+ *     exact (128-bit fixed point per column), so v_k is the exact weighted
+ *     median of the rounded ratios.  Among equal minimisers: v_k = 0 when 0
+ *     is a minimiser, else the minimiser closest to 0; the reported median
+ *     row is the position meeting Lemma 1's condition that lies nearest 0.
+ *   - Reported sums (z_j, e_jk, column masses) use the fixed order R64:
+ *     term t added to partial (t mod 64) in increasing t, then
+ *     p[l] += p[l+d] for d = 32..1; residual terms |x_ik - fl(v_k x_ij)|
+ *     with no fused multiply-add.  z_j = E_j + fl(lambda * P_j).
+ *   - j* = the smallest index among the minimal z_j (Algorithm 1's strict
+ *     "<" over ascending j).
+ *   - All calls are asynchronous on `stream` (a hipStream_t; NULL = the
+ *     default stream) and copy nothing back to the host.  Calls on one
+ *     context must be issued on one stream (or serialised by the caller):
+ *     they share the context's workspace.
+ *
+ * ERRORS
+ *   Every entry point returns an int: 0 on success, a negative code below.
+ *   Argument errors are found on the host, before anything is launched.
+ *   Data-dependent conditions are found on the device and written to the
+ *   optional `status` output (one int32, device memory): 0, or the first
+ *   that applies of ENONFINITE, EWIDE, EINTERNAL, ERANGE.  With a nonzero
+ *   status the other outputs are unspecified.
+ */
+#ifndef L1LINE_H
+#define L1LINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define L1LINE_OK 0
+#define L1LINE_EINVAL (-1)     /* bad argument (host check)                          */
+#define L1LINE_EHIP (-2)       /* a HIP runtime call failed                          */
+#define L1LINE_ENONFINITE (-3) /* X holds a NaN or an infinity (device check)        */
+#define L1LINE_ERANGE (-4)     /* a selected ratio overflowed to +-inf (device)      */
+#define L1LINE_ENOMEM (-5)     /* workspace allocation failed                        */
+#define L1LINE_EWIDE (-6)      /* a column's nonzero magnitudes span too many binades
+                                  for exact 128-bit weight sums: (highest bit - lowest
+                                  bit + 1) + bitlength(#nonzeros) > 124 (device)     */
+#define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N (host check)                  */
+#define L1LINE_EINTERNAL (-8)  /* a selection exceeded its round bound (device)      */
+
+#define L1LINE_MAX_N 4096          /* rows per matrix handled by this build       */
+#define L1LINE_MAX_LAMBDAS 128     /* penalties per call (passed by value)        */
+
+typedef struct l1line_ctx_s *l1line_ctx;
+
+/* Create a context on HIP device `device` (its workspace starts empty and
+ * grows on demand).  *ctx receives the handle.  Returns EINVAL for a bad
+ * device or null ctx, EHIP if the device cannot be selected. */
+int l1line_create(l1line_ctx *ctx, int device);
+
+/* Free the context's workspace (synchronises its device first). */
+int l1line_destroy(l1line_ctx ctx);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *l1line_strerror(int code);
+
+/* Column statistics (feed the penalty scale Lambda = max_j W_j):
+ *   W[j]     = R64 sum over i of |x_ij|           (m doubles, nullable)
+ *   zeros[j] = #{i : x_ij == 0}                    (m int32, nullable)
+ *   status   = 0 or ENONFINITE                     (nullable) */
+int l1line_column_stats(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                        int64_t ld, double *W, int32_t *zeros, int32_t *status,
+                        void *stream);
+
+/* Algorithm 1 for one penalty (Sec. 2, Algorithm 1; Lemma 1 per column).
+ *   lambda       HOST value, finite, >= 0
+ *   v            [m]  v* with v[j*] = 1 exactly
+ *   j            [1]  j* (int64)
+ *   obj          [1]  z_{j*}
+ *   median_row   [m]  row i whose ratio gave v*_k; -1 when v*_k = 0 and at
+ *                     k = j* (nullable)
+ *   z_all        [m]  z_j for every candidate j (nullable)
+ *   status       [1]  device status (nullable)
+ * Host errors: EINVAL (n<1, m<1, ld<n, null X/v/j/obj, bad lambda), ESIZE
+ * (n > L1LINE_MAX_N), ENOMEM, EHIP. */
+int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+               int64_t ld, double lambda, double *v, int64_t *j, double *obj,
+               int32_t *median_row, double *z_all, int32_t *status,
+               void *stream);
+
+/* Algorithm 1 along a path of L penalties, each ratio list built once per
+ * (j, k) and reused for every lambda (the solution for each lambda is the
+ * one l1line_fit returns for it, bit for bit).
+ *   lambdas  HOST array of L values (1 <= L <= L1LINE_MAX_LAMBDAS)
+ *   V        [L*m]  row t = v*(lambda_t)
+ *   J        [L]    j*(lambda_t)
+ *   OBJ      [L]    z_{j*}(lambda_t)
+ *   ROW      [L*m]  median rows (nullable)
+ *   ZALL     [L*m]  row t = z_j(lambda_t) for every j (nullable)
+ *   status   [1]    (nullable) */
+int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                    int64_t ld, const double *lambdas, int64_t L, double *V,
+                    int64_t *J, double *OBJ, int32_t *ROW, double *ZALL,
+                    int32_t *status, void *stream);
+
+/* Kernel timing for measurement tools.  While enabled, every kernel the
+ * context launches is bracketed by HIP events on its stream.
+ * l1line_profile_read waits for the recorded events, returns the summed
+ * duration (ms) and launch count of the kernels whose name is `kernel`
+ * ("colprep", "fit_seg", "reduce", "argmin"; NULL = all), and with reset != 0
+ * forgets every record.  Outputs are HOST pointers (nullable). */
+int l1line_profile(l1line_ctx ctx, int enable);
+int l1line_profile_read(l1line_ctx ctx, const char *kernel, double *total_ms,
+                        int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* L1LINE_H */

@@ -1,0 +1,186 @@
+"""Thin ctypes binding of the C ABI in include/l1line.h.
+
+Argument marshalling only: device memory and the current stream come from
+PyTorch, every step of the method runs in the library's HIP kernels.  There
+is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_build", "libl1line.so")
+
+OK, EINVAL, EHIP, ENONFINITE, ERANGE, ENOMEM, EWIDE, ESIZE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
+MAX_N = 4096
+MAX_LAMBDAS = 128
+
+EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_column_stats",
+           "l1line_fit", "l1line_fit_path", "l1line_profile", "l1line_profile_read"]
+
+
+class L1LineError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built library (build it with paper_2402_16712_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python -m paper_2402_16712_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.l1line_create.argtypes = [ctypes.POINTER(P), I32]
+        L.l1line_destroy.argtypes = [P]
+        L.l1line_strerror.argtypes = [I32]
+        L.l1line_strerror.restype = ctypes.c_char_p
+        L.l1line_column_stats.argtypes = [P, P, I64, I64, I64, P, P, P, P]
+        L.l1line_fit.argtypes = [P, P, I64, I64, I64, D, P, P, P, P, P, P, P]
+        L.l1line_fit_path.argtypes = [P, P, I64, I64, I64, P, I64, P, P, P, P, P, P, P]
+        L.l1line_profile.argtypes = [P, I32]
+        L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),
+                                          ctypes.POINTER(I64), I32]
+        for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit",
+                  "l1line_fit_path", "l1line_profile", "l1line_profile_read"):
+            getattr(L, f).restype = I32
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().l1line_strerror(int(code)).decode()
+    except RuntimeError:
+        return f"status {code}"
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise L1LineError(code, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def device_matrix(X: np.ndarray, device="cuda:0"):
+    """Copy an n x m numpy matrix to a column-major FP64 device tensor
+    (strides (1, n)), the layout the library takes."""
+    torch = _torch()
+    X = np.asfortranarray(np.asarray(X, dtype=np.float64))
+    n, m = X.shape
+    t = torch.empty_strided((n, m), (1, max(n, 1)), dtype=torch.float64, device=device)
+    t.copy_(torch.from_numpy(X))
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_matrix(X):
+    torch = _torch()
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2:
+        raise TypeError("X must be a 2-D float64 CUDA tensor")
+    n, m = X.shape
+    if X.stride(0) != 1 or (m > 1 and X.stride(1) < n):
+        raise ValueError("X must be column-major: stride(0) == 1, stride(1) >= n")
+    ld = X.stride(1) if m > 1 else max(n, 1)
+    return n, m, max(ld, n)
+
+
+class Context:
+    """One library context (workspace) on one device."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = int(device)
+        self._torch_device = torch.device("cuda", self.device)
+        h = ctypes.c_void_p()
+        _check(lib().l1line_create(ctypes.byref(h), self.device), "l1line_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().l1line_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool):
+        _check(lib().l1line_profile(self._h, int(bool(enable))), "l1line_profile")
+
+    def profile_read(self, kernel=None, reset=False):
+        """(total ms, launches) of the recorded launches of `kernel`."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().l1line_profile_read(self._h, None if kernel is None else kernel.encode(),
+                                         ctypes.byref(ms), ctypes.byref(cnt), int(bool(reset))),
+               "l1line_profile_read")
+        return ms.value, cnt.value
+
+    def _stream(self):
+        return ctypes.c_void_p(_torch().cuda.current_stream(self._torch_device).cuda_stream)
+
+    def _empty(self, shape, dtype):
+        return _torch().empty(shape, dtype=dtype, device=self._torch_device)
+
+    def column_stats(self, X):
+        """(W [m] fp64, zeros [m] int32, status [1] int32) on the device."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        W = self._empty((m,), torch.float64)
+        Z = self._empty((m,), torch.int32)
+        st = self._empty((1,), torch.int32)
+        _check(lib().l1line_column_stats(self._h, _ptr(X), n, m, ld, _ptr(W), _ptr(Z), _ptr(st),
+                                         self._stream()), "l1line_column_stats")
+        return W, Z, st
+
+    def fit(self, X, lam: float, rows: bool = True, z_all: bool = True):
+        """Algorithm 1 for one penalty: dict of device tensors v, j, obj,
+        row, z_all, status."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        out = dict(v=self._empty((m,), torch.float64), j=self._empty((1,), torch.int64),
+                   obj=self._empty((1,), torch.float64),
+                   row=self._empty((m,), torch.int32) if rows else None,
+                   z_all=self._empty((m,), torch.float64) if z_all else None,
+                   status=self._empty((1,), torch.int32))
+        _check(lib().l1line_fit(self._h, _ptr(X), n, m, ld, float(lam), _ptr(out["v"]), _ptr(out["j"]),
+                                _ptr(out["obj"]), _ptr(out["row"]), _ptr(out["z_all"]),
+                                _ptr(out["status"]), self._stream()), "l1line_fit")
+        return out
+
+    def fit_path(self, X, lambdas, rows: bool = True, z_all: bool = True):
+        """Algorithm 1 along a path: dict V [L,m], J [L], OBJ [L], ROW [L,m],
+        ZALL [L,m], status."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+        L = lam.size
+        out = dict(V=self._empty((L, m), torch.float64), J=self._empty((L,), torch.int64),
+                   OBJ=self._empty((L,), torch.float64),
+                   ROW=self._empty((L, m), torch.int32) if rows else None,
+                   ZALL=self._empty((L, m), torch.float64) if z_all else None,
+                   status=self._empty((1,), torch.int32))
+        _check(lib().l1line_fit_path(self._h, _ptr(X), n, m, ld,
+                                     lam.ctypes.data_as(ctypes.c_void_p), L, _ptr(out["V"]),
+                                     _ptr(out["J"]), _ptr(out["OBJ"]), _ptr(out["ROW"]),
+                                     _ptr(out["ZALL"]), _ptr(out["status"]), self._stream()),
+               "l1line_fit_path")
+        return out

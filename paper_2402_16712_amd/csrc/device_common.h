@@ -1,0 +1,238 @@
+// device_common.h -- wave64 primitives, order-preserving keys and exact
+// 128-bit fixed-point weights shared by the l1line kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned __int128 u128;
+
+#define L1_WAVE 64
+
+// Order-preserving map from a non-NaN double to uint64: a < b  <=>  key(a) < key(b).
+// Callers pass canonical zeros (+0.0), so every zero ratio has the same key.
+constexpr uint64_t KEY_ZERO = 0x8000000000000000ull;   // key(+0.0)
+constexpr uint64_t KEY_NONE = ~0ull;                   // "no element" (above +inf)
+
+__device__ __forceinline__ uint64_t key_of(double r) {
+  uint64_t b = (uint64_t)__double_as_longlong(r);
+  return (b >> 63) ? ~b : (b | KEY_ZERO);
+}
+
+__device__ __forceinline__ double ratio_of_key(uint64_t k) {
+  uint64_t b = (k >> 63) ? (k & ~KEY_ZERO) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+// ---------------------------------------------------------------- fixed point
+// A finite nonzero |x| is M * 2^E with M < 2^53 (E = -1074 for subnormals).
+__device__ __forceinline__ void dbl_parts(double a, uint64_t &M, int &E) {
+  uint64_t b = (uint64_t)__double_as_longlong(a) & ~KEY_ZERO;
+  int be = (int)(b >> 52);
+  M = b & 0xFFFFFFFFFFFFFull;
+  if (be) {
+    M |= 1ull << 52;
+    E = be - 1075;
+  } else {
+    E = -1074;
+  }
+}
+
+__device__ __forceinline__ int lowest_bit_exp(double a) {
+  uint64_t M; int E;
+  dbl_parts(a, M, E);
+  return E + __builtin_ctzll(M);
+}
+
+__device__ __forceinline__ int highest_bit_exp(double a) {
+  uint64_t M; int E;
+  dbl_parts(a, M, E);
+  return E + 63 - __builtin_clzll(M);
+}
+
+// |x| / 2^e0 as an exact integer; e0 <= lowest_bit_exp(|x|) and the column
+// range check keep the result below 2^124.
+__device__ __forceinline__ u128 fixed_of(double a, int e0) {
+  uint64_t M; int E;
+  dbl_parts(a, M, E);
+  int sh = E - e0;
+  if (sh >= 0) return ((u128)M) << sh;
+  return (u128)(M >> (-sh));   // only trailing zero bits are shifted out
+}
+
+// floor(lambda / 2^e0), saturated at 2^126 (beyond every weight sum of a
+// column that passed the range check, so it acts as +infinity).
+__device__ __forceinline__ u128 lambda_fixed(double lam, int e0) {
+  if (!(lam > 0.0)) return 0;
+  uint64_t M; int E;
+  dbl_parts(lam, M, E);
+  int hb = E + 63 - __builtin_clzll(M);
+  if (hb - e0 >= 126) return ((u128)1) << 126;
+  int sh = E - e0;
+  if (sh >= 0) return ((u128)M) << sh;
+  if (-sh >= 64) return 0;
+  return (u128)(M >> (-sh));
+}
+
+__device__ __forceinline__ double u128_to_double_approx(u128 x) {
+  return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
+}
+
+// ------------------------------------------------------------ wave primitives
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
+  return (uint64_t)__shfl_xor((unsigned long long)x, m);
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
+  return (uint64_t)__shfl((unsigned long long)x, src);
+}
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t x, int d) {
+  return (uint64_t)__shfl_up((unsigned long long)x, d);
+}
+
+__device__ __forceinline__ u128 shfl_u128(u128 x, int src) {
+  uint64_t lo = shfl_u64((uint64_t)x, src), hi = shfl_u64((uint64_t)(x >> 64), src);
+  return (((u128)hi) << 64) | lo;
+}
+
+// Values equal on every lane, moved to scalar registers.
+__device__ __forceinline__ int uni_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni_u64(uint64_t x) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ u128 uni_u128(u128 x) {
+  return (((u128)uni_u64((uint64_t)(x >> 64))) << 64) | uni_u64((uint64_t)x);
+}
+
+// Exact sum over the wave (integer adds: any order gives the same result).
+__device__ __forceinline__ u128 wave_sum_u128(u128 x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint64_t lo = shfl_xor_u64((uint64_t)x, d), hi = shfl_xor_u64((uint64_t)(x >> 64), d);
+    x += (((u128)hi) << 64) | lo;
+  }
+  return uni_u128(x);
+}
+
+__device__ __forceinline__ int wave_sum_int(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return uni_int(x);
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint64_t o = shfl_xor_u64(x, d);
+    x = o < x ? o : x;
+  }
+  return uni_u64(x);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint64_t o = shfl_xor_u64(x, d);
+    x = o > x ? o : x;
+  }
+  return uni_u64(x);
+}
+
+__device__ __forceinline__ int wave_min_int(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d));
+  return uni_int(x);
+}
+
+__device__ __forceinline__ int wave_max_int(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d));
+  return uni_int(x);
+}
+
+// Inclusive scans across the 64 lanes.
+__device__ __forceinline__ u128 wave_incl_scan_u128(u128 x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t lo = shfl_up_u64((uint64_t)x, d), hi = shfl_up_u64((uint64_t)(x >> 64), d);
+    if (lane >= d) x += (((u128)hi) << 64) | lo;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int wave_excl_scan_int(int x, int lane) {
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int o = __shfl_up(incl, d);
+    if (lane >= d) incl += o;
+  }
+  return incl - x;
+}
+
+__device__ __forceinline__ double wave_incl_scan_dbl(double x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double o = __shfl_up(x, d);
+    if (lane >= d) x = x + o;
+  }
+  return x;
+}
+
+// R64 tree: p[l] = p[l] + p[l+d] for d = 32..1; the result is in lane 0.
+__device__ __forceinline__ double wave_r64_tree(double p) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    double o = __shfl_down(p, d);
+    p = p + o;
+  }
+  return p;
+}
+
+// Bitonic sort of one (key, payload) pair per lane, ascending by key then row.
+__device__ __forceinline__ void wave_sort_key_row(uint64_t &key, int &row, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      uint64_t ok = shfl_xor_u64(key, stride);
+      int orow = __shfl_xor(row, stride);
+      bool up = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      bool other_less = ok < key || (ok == key && orow < row);
+      bool other_greater = ok > key || (ok == key && orow > row);
+      bool take = (lower == up) ? other_less : other_greater;
+      if (take) { key = ok; row = orow; }
+    }
+  }
+}
+
+// Bitonic sort of (key, weight) by key only (order among equal keys is fixed
+// by the network; used for pivot sampling only).
+__device__ __forceinline__ void wave_sort_key_dbl(uint64_t &key, double &w, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      uint64_t ok = shfl_xor_u64(key, stride);
+      double ow = __shfl_xor(w, stride);
+      bool up = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      bool take = (lower == up) ? (ok < key) : (ok > key);
+      if (take) { key = ok; w = ow; }
+    }
+  }
+}
+
+// Keep the scheduler from hoisting every load of an unrolled slot loop (each
+// weight is 4 VGPRs): fence after every 4 slots.
+#define L1_SLOT_FENCE(t) \
+  do {                    \
+    if (((t) & 3) == 3) __builtin_amdgcn_sched_barrier(0); \
+  } while (0)
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}

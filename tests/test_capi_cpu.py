@@ -1,0 +1,107 @@
+"""C ABI checks that need no GPU: the built library loads, exports every
+symbol the header declares, and rejects bad arguments on the host before
+any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2402_16712_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^(?:int|const char \*)\s*(l1line_\w+)\s*\(", text, re.M)
+    return names
+
+
+def test_library_loads_and_exports_header_symbols():
+    lib = B.lib()
+    names = _declared()
+    assert len(names) >= 6
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert set(B.EXPORTS) <= set(names)
+
+
+def test_strerror_names_every_code():
+    for c in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert B.strerror(c) != "unknown status"
+    assert B.strerror(-99) == "unknown status"
+
+
+def test_header_constants_match_binding():
+    text = open(os.path.join(ROOT, "include", "l1line.h")).read()
+    consts = dict(re.findall(r"#define (L1LINE_\w+) \(?(-?\d+)\)?", text))
+    assert int(consts["L1LINE_MAX_N"]) == B.MAX_N
+    assert int(consts["L1LINE_MAX_LAMBDAS"]) == B.MAX_LAMBDAS
+    assert int(consts["L1LINE_EWIDE"]) == B.EWIDE and int(consts["L1LINE_ERANGE"]) == B.ERANGE
+
+
+class _Fake:
+    """A non-null context pointer: argument checks run before it is used."""
+
+    def __init__(self):
+        self.buf = ctypes.create_string_buffer(64)
+        self.h = ctypes.cast(self.buf, ctypes.c_void_p)
+
+
+def _fit(h, X, n, m, ld, lam, v=1, j=1, obj=1):
+    P = ctypes.c_void_p
+    return B.lib().l1line_fit(h, P(X), n, m, ld, lam, P(v) if v else None, P(j) if j else None,
+                              P(obj) if obj else None, None, None, None, None)
+
+
+def test_fit_host_argument_checks():
+    f = _Fake()
+    assert _fit(None, 1, 10, 4, 10, 0.5) == B.EINVAL
+    assert _fit(f.h, 0, 10, 4, 10, 0.5) == B.EINVAL          # null X
+    assert _fit(f.h, 1, 0, 4, 10, 0.5) == B.EINVAL           # n < 1
+    assert _fit(f.h, 1, 10, 0, 10, 0.5) == B.EINVAL          # m < 1
+    assert _fit(f.h, 1, 10, 4, 9, 0.5) == B.EINVAL           # ld < n
+    assert _fit(f.h, 1, 10, 4, 10, -1.0) == B.EINVAL         # lambda < 0
+    assert _fit(f.h, 1, 10, 4, 10, float("nan")) == B.EINVAL
+    assert _fit(f.h, 1, 10, 4, 10, float("inf")) == B.EINVAL
+    assert _fit(f.h, 1, 10, 4, 10, 0.5, v=0) == B.EINVAL     # null output
+    assert _fit(f.h, 1, B.MAX_N + 1, 4, B.MAX_N + 1, 0.5) == B.ESIZE
+
+
+def test_path_host_argument_checks():
+    f = _Fake()
+    P = ctypes.c_void_p
+    lib = B.lib()
+    lam = np.array([0.1, 0.2, -0.3])
+
+    def call(lams, L):
+        return lib.l1line_fit_path(f.h, P(1), 10, 4, 10, lams.ctypes.data_as(P), L, P(1), P(1), P(1),
+                                   None, None, None, None)
+    assert call(lam, 3) == B.EINVAL                          # negative lambda
+    assert call(lam, 0) == B.EINVAL                          # L < 1
+    big = np.full(B.MAX_LAMBDAS + 1, 0.5)
+    assert call(big, B.MAX_LAMBDAS + 1) == B.EINVAL          # too many lambdas
+    assert lib.l1line_fit_path(f.h, P(1), 10, 4, 10, None, 2, P(1), P(1), P(1),
+                               None, None, None, None) == B.EINVAL
+
+
+def test_stats_and_create_checks():
+    lib = B.lib()
+    P = ctypes.c_void_p
+    assert lib.l1line_column_stats(None, P(1), 5, 5, 5, None, None, None, None) == B.EINVAL
+    f = _Fake()
+    assert lib.l1line_column_stats(f.h, P(1), 5, 5, 4, None, None, None, None) == B.EINVAL
+    assert lib.l1line_create(None, 0) == B.EINVAL
+    assert lib.l1line_destroy(None) == B.EINVAL
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        B.lib()
