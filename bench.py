@@ -38,7 +38,23 @@ def _args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-columns", type=int, default=0, help="oracle sample size (columns j)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 512 MiB device buffer 3 times (scale for HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """Three device-to-device copies of exactly 512 MiB: the FETCH_SIZE /
+    WRITE_SIZE counters of these dispatches give the counters' scale."""
+    import torch
+    nbytes = 512 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
 
 
 def _source_hash():
@@ -97,6 +113,9 @@ def cpu_baseline(p, lam, z_gpu, columns):
 
 def main():
     a = _args()
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
@@ -119,9 +138,6 @@ def main():
     for _ in range(a.warmup):
         out = ctx.fit(X, lam)
     torch.cuda.synchronize()
-    st = int(out["status"].item())
-    if st != 0:
-        raise SystemExit(f"fit status {st}: {B.strerror(st)}")
 
     ctx.profile(True)
     ctx.profile_read(reset=True)
@@ -141,6 +157,9 @@ def main():
     ctx.profile_read(reset=True)
     ctx.profile(False)
 
+    st = int(out["status"].item())
+    if st != 0:
+        raise SystemExit(f"fit status {st}: {B.strerror(st)}")
     ms_per_step = total_ms / a.steps
     fits_per_s = 1000.0 / ms_per_step
     medians = m * (m - 1)

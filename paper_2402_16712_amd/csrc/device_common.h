@@ -55,9 +55,10 @@ __device__ __forceinline__ int highest_bit_exp(double a) {
 __device__ __forceinline__ u128 fixed_of(double a, int e0) {
   uint64_t M; int E;
   dbl_parts(a, M, E);
-  int sh = E - e0;
-  if (sh >= 0) return ((u128)M) << sh;
-  return (u128)(M >> (-sh));   // only trailing zero bits are shifted out
+  const int sh = E - e0;
+  const u128 up = ((u128)M) << (sh & 127);
+  const u128 dn = (u128)(M >> ((-sh) & 63));   // only trailing zero bits are shifted out
+  return (sh >= 0) ? (sh < 128 ? up : (u128)0) : (-sh < 64 ? dn : (u128)0);
 }
 
 // floor(lambda / 2^e0), saturated at 2^126 (beyond every weight sum of a
@@ -137,6 +138,13 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
     x = o > x ? o : x;
   }
   return uni_u64(x);
+}
+
+// Sum over the wave in an unspecified order (for approximate sums only).
+__device__ __forceinline__ double wave_sum_dbl(double x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = x + __shfl_xor(x, d);
+  return __shfl(x, 0);
 }
 
 __device__ __forceinline__ int wave_min_int(int x) {

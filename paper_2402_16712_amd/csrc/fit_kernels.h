@@ -22,6 +22,8 @@ struct ColInfo {
   int nnz;      // nonzeros
   int zeros;    // exact zeros
   int flags;    // COL_*
+  int bemin;    // smallest biased exponent field over nonzero entries
+  int bemax;    // largest biased exponent field over nonzero entries
 };
 
 struct LamArgs {
@@ -38,7 +40,7 @@ k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__r
   const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (col >= m) return;
   const double *x = X + (long long)col * ld;
-  int bad = 0, nnz = 0, zeros = 0, lsb = 1 << 20, hb = -(1 << 20);
+  int bad = 0, nnz = 0, zeros = 0, lsb = 1 << 20, hb = -(1 << 20), bemin = 4096, bemax = -1;
   double part = 0.0;
   for (int i = lane; i < n; i += 64) {
     double v = x[i];
@@ -52,6 +54,9 @@ k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__r
       ++nnz;
       lsb = min(lsb, lowest_bit_exp(a));
       hb = max(hb, highest_bit_exp(a));
+      const int be = (int)((__double_as_longlong(a) >> 52) & 0x7ff);
+      bemin = min(bemin, be);
+      bemax = max(bemax, be);
     }
   }
   double W = wave_r64_tree(part);
@@ -60,6 +65,8 @@ k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__r
   zeros = wave_sum_int(zeros);
   lsb = wave_min_int(lsb);
   hb = wave_max_int(hb);
+  bemin = wave_min_int(bemin);
+  bemax = wave_max_int(bemax);
   int flags = bad ? COL_NONFINITE : 0;
   int e0 = nnz ? lsb : 0;
   if (!bad && nnz) {
@@ -82,29 +89,159 @@ k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__r
     c.nnz = nnz;
     c.zeros = zeros;
     c.flags = flags;
+    c.bemin = bemin;
+    c.bemax = bemax;
     ci[col] = c;
   }
 }
 
-// ---------------------------------------------------------- exact selection
-// Find the first element, in (ratio, row) order, whose inclusive prefix
-// weight reaches tau.  Candidates are the elements with klo < key <= khi;
-// Slo/Clo (Shi/Chi) are the exact weight and count of ALL elements with
-// key <= klo (<= khi).  Element (lane, t) is row lane + 64 t.
-template <int T>
-__device__ __forceinline__ void wave_select(const uint64_t (&keys)[T], const u128 *__restrict__ swf,
-                                            const double *__restrict__ sxj, const double *__restrict__ xk,
-                                            int n, int tmax, uint64_t klo, uint64_t khi,
-                                            u128 Slo, u128 Shi, int Clo, int Chi, u128 tau, int lane,
-                                            uint64_t *__restrict__ wkey, int *__restrict__ wrow,
-                                            uint64_t &okey, int &orow, int &err) {
+// ----------------------------------------------------------- segment access
+// One wave streams over the rows of segment (j, k); row i = lane + 64 t for
+// slot t < T.  Column j sits in LDS, column k is read from global memory
+// (it stays in L2/MALL across the concurrent workgroups).  Nothing per row
+// is kept in registers: every pass recomputes the ratio it needs, which keeps
+// the register count low and the occupancy high.
+struct SegIO {
+  const double *__restrict__ xk;   // column k
+  const double *__restrict__ sxj;  // column j (LDS)
+  int n, T, Tp, e0, lane;          // rows, slots, pow2 >= T, fixed-point exponent
+};
+
+// key of fl(x_ik / x_ij) + 0.0; KEY_NONE outside the matrix or where x_ij = 0
+__device__ __forceinline__ uint64_t seg_key(const SegIO &s, int i) {
+  const bool in = i < s.n;
+  const int ic = in ? i : 0;
+  const double a = s.sxj[ic], b = s.xk[ic];
+  double r = b / a;
+  r = r + 0.0;
+  return (in && a != 0.0) ? key_of(r) : KEY_NONE;
+}
+
+// exact weight |x_ij| / 2^e0 of row i, 0 where !valid
+__device__ __forceinline__ u128 seg_weight(const SegIO &s, int i, bool valid) {
+  const double a = valid ? fabs(s.sxj[valid ? i : 0]) : 0.0;
+  return valid ? fixed_of(a, s.e0) : (u128)0;
+}
+
+__device__ __forceinline__ void take_sample(bool c, int pri, uint64_t key, int t, int &bp, uint64_t &bk,
+                                            int &bt) {
+  const bool better = c && pri < bp;
+  bp = better ? pri : bp;
+  bk = better ? key : bk;
+  bt = better ? t : bt;
+}
+
+// Per-wave LDS area: the elements (key, row) that fall in the key window of
+// the exact pass, and a 64-entry compaction buffer.
+constexpr int WIN_CAP = 512;
+struct WaveScratch {
+  uint64_t wkeys[WIN_CAP];
+  unsigned short wrows[WIN_CAP];
+  uint64_t ckey[64];
+  int crow[64];
+};
+
+// Element sources of the exact selection: every row of the column (ratio
+// recomputed), or the window list in LDS.  Slot t of lane l is element
+// l + 64 t; both enumerate their elements in increasing row order.
+// sbase / cbase: weight and count of the elements below every listed one
+// (the selection's sums and counts are over all elements of the segment).
+struct ColSrc {
+  const SegIO &s;
+  u128 sbase;
+  int cbase;
+  __device__ __forceinline__ int slots() const { return s.T; }
+  __device__ __forceinline__ void at(int t, uint64_t &key, int &row) const {
+    row = s.lane + 64 * t;
+    key = seg_key(s, row);
+  }
+};
+
+struct ListSrc {
+  const SegIO &s;
+  u128 sbase;
+  int cbase;
+  const uint64_t *keys;
+  const unsigned short *rows;
+  int nlist;
+  __device__ __forceinline__ int slots() const { return (nlist + 63) >> 6; }
+  __device__ __forceinline__ void at(int t, uint64_t &key, int &row) const {
+    const int e = s.lane + 64 * t;
+    const bool in = e < nlist;
+    key = in ? keys[e] : KEY_NONE;
+    row = in ? (int)rows[e] : 0;
+  }
+};
+
+// ------------------------------------------------- finishing <= 64 candidates
+// Candidates are the elements with klo < key <= khi (count <= 64); Slo is the
+// exact weight of all elements with key <= klo.  Compact them to LDS, sort by
+// (key, row) across the lanes, scan their exact weights from Slo and take the
+// first whose prefix reaches tau.
+template <class Src>
+__device__ __forceinline__ void wave_finish(const SegIO &s, const Src &src, uint64_t klo, uint64_t khi, int count,
+                                            u128 Slo, u128 tau, WaveScratch *ws, uint64_t &okey, int &orow,
+                                            int &err) {
+  const int lane = s.lane;
+  int base = 0;
+  const int ns = src.slots();
+#pragma unroll 2
+  for (int t = 0; t < ns; ++t) {
+    uint64_t key;
+    int row;
+    src.at(t, key, row);
+    const bool c = key > klo && key <= khi;
+    const uint64_t mask = __ballot(c);
+    const int pos = base + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+    if (c && pos < 64) {
+      ws->ckey[pos] = key;
+      ws->crow[pos] = row;
+    }
+    base += __builtin_popcountll(mask);
+  }
+  wave_lds_sync();
+  uint64_t ck = lane < count ? ws->ckey[lane] : KEY_NONE;
+  int cr = lane < count ? ws->crow[lane] : 0x7fffffff;
+  wave_lds_sync();
+  wave_sort_key_row(ck, cr, lane);
+  const u128 w = seg_weight(s, lane < count ? cr : 0, lane < count);
+  const u128 S = wave_incl_scan_u128(w, lane) + Slo;
+  const uint64_t hit = __ballot(lane < count && S >= tau);
+  if (!hit || base != count) {
+    err |= SEG_INTERNAL;
+    okey = KEY_NONE;
+    orow = -1;
+    return;
+  }
+  const int srcl = __builtin_ctzll(hit);
+  okey = uni_u64(shfl_u64(ck, srcl));
+  orow = uni_int(__shfl(cr, srcl));
+}
+
+// ----------------------------------------------------------- selection rounds
+// Exact selection: find the first element, in (ratio, row) order, whose
+// inclusive prefix weight reaches tau.  Candidates are the elements with
+// klo < key <= khi; Slo/Clo (Shi/Chi) are the exact weight and count of ALL
+// elements with key <= klo (<= khi).  Rounds take two pivots from a weighted
+// sample of the candidates and count exactly; a round without progress
+// switches to key-space bisection; a single repeated key falls back to row
+// order.
+template <class Src>
+__device__ __forceinline__ void wave_select_rounds(const SegIO &s, const Src &src, uint64_t klo, uint64_t khi,
+                                                   u128 Slo, u128 Shi, int Clo, int Chi, u128 tau,
+                                                   WaveScratch *ws, uint64_t &okey, int &orow, int &err) {
   constexpr double DELTA = 0.15;
+  const int lane = s.lane;
+  const int ns = src.slots();
+  int nsp = 1;
+  while (nsp < ns) nsp <<= 1;
   int count = Chi - Clo;
-  bool bisect = false;
+  bool bisect = false, single_key = false;
   int rounds = 0;
+  uint64_t sk = KEY_NONE;
+  int sr = 0;
   okey = KEY_NONE;
   orow = -1;
-  bool single_key = false;
   while (count > 64) {
     if (++rounds > 160) {
       err |= SEG_INTERNAL;
@@ -112,41 +249,27 @@ __device__ __forceinline__ void wave_select(const uint64_t (&keys)[T], const u12
     }
     uint64_t plo, phi;
     if (!bisect) {
-      // one candidate per lane, from a lane/round dependent slot
-      const int start = (lane * 11 + rounds * 5) & (T - 1);
-      uint64_t sk = KEY_NONE;
-      int spri = T, st = 0;
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        bool c = keys[t] > klo && keys[t] <= khi;
-        int pri = (t - start) & (T - 1);
-        if (c && pri < spri) {
-          spri = pri;
-          sk = keys[t];
-          st = t;
-        }
-      }
-      double sw = (sk != KEY_NONE) ? fabs(sxj[lane + 64 * st]) : 0.0;
+      double sw = (sk != KEY_NONE) ? fabs(s.sxj[sr]) : 0.0;
       wave_sort_key_dbl(sk, sw, lane);
-      double cw = wave_incl_scan_dbl(sw, lane);
-      double tot = __shfl(cw, 63);
-      double f = u128_to_double_approx(tau - Slo) / u128_to_double_approx(Shi - Slo);
-      double flo = (f - DELTA) * tot, fhi = (f + DELTA) * tot;
-      uint64_t mlo = __ballot(sk != KEY_NONE && cw <= flo);
-      uint64_t mhi = __ballot(sk != KEY_NONE && cw >= fhi);
+      const double cw = wave_incl_scan_dbl(sw, lane);
+      const double tot = __shfl(cw, 63);
+      const double f = u128_to_double_approx(tau - Slo) / u128_to_double_approx(Shi - Slo);
+      const double flo = (f - DELTA) * tot, fhi = (f + DELTA) * tot;
+      const uint64_t mlo = __ballot(sk != KEY_NONE && cw <= flo);
+      const uint64_t mhi = __ballot(sk != KEY_NONE && cw >= fhi);
       plo = mlo ? uni_u64(shfl_u64(sk, 63 - __builtin_clzll(mlo))) : klo;
       phi = mhi ? uni_u64(shfl_u64(sk, __builtin_ctzll(mhi))) : khi;
       if (phi < plo) phi = plo;
     } else {
-      // key-space bisection between the extreme candidates: always progresses
       uint64_t cmin = KEY_NONE, cmax = 0;
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        bool c = keys[t] > klo && keys[t] <= khi;
-        if (c) {
-          cmin = keys[t] < cmin ? keys[t] : cmin;
-          cmax = keys[t] > cmax ? keys[t] : cmax;
-        }
+#pragma unroll 2
+      for (int t = 0; t < ns; ++t) {
+        uint64_t key;
+        int row;
+        src.at(t, key, row);
+        const bool c = key > klo && key <= khi;
+        cmin = (c && key < cmin) ? key : cmin;
+        cmax = (c && key > cmax) ? key : cmax;
       }
       cmin = wave_min_u64(cmin);
       cmax = wave_max_u64(cmax);
@@ -157,87 +280,68 @@ __device__ __forceinline__ void wave_select(const uint64_t (&keys)[T], const u12
       }
       plo = phi = cmin + ((cmax - cmin) >> 1);
     }
-    // exact weights and counts of all elements at or below each pivot
+    // exact weights and counts at or below each pivot, and one sample per
+    // lane from each of the three sub-intervals
     u128 s1 = 0, s2 = 0;
     int c1 = 0, c2 = 0;
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      uint64_t kk = keys[t];
-      if (kk != KEY_NONE) {
-        u128 w = swf[lane + 64 * t];
-        if (kk <= plo) { s1 += w; ++c1; }
-        if (kk <= phi) { s2 += w; ++c2; }
-      }
-      L1_SLOT_FENCE(t);
+    uint64_t ka = KEY_NONE, kb = KEY_NONE, kc = KEY_NONE;
+    int pa = nsp, pb = nsp, pc = nsp, ra = 0, rb = 0, rc = 0;
+    const int start = (lane * 11 + rounds * 5) & (nsp - 1);
+#pragma unroll 2
+    for (int t = 0; t < ns; ++t) {
+      uint64_t key;
+      int row;
+      src.at(t, key, row);
+      const bool valid = key != KEY_NONE;
+      const u128 w = seg_weight(s, row, valid);
+      const bool le1 = valid && key <= plo, le2 = valid && key <= phi;
+      s1 += le1 ? w : (u128)0;
+      s2 += le2 ? w : (u128)0;
+      c1 += le1 ? 1 : 0;
+      c2 += le2 ? 1 : 0;
+      const int pri = (t - start) & (nsp - 1);
+      take_sample(key > klo && le1, pri, key, row, pa, ka, ra);
+      take_sample(key > plo && le2, pri, key, row, pb, kb, rb);
+      take_sample(key > phi && key <= khi, pri, key, row, pc, kc, rc);
     }
-    s1 = wave_sum_u128(s1);
-    s2 = wave_sum_u128(s2);
-    c1 = wave_sum_int(c1);
-    c2 = wave_sum_int(c2);
+    s1 = wave_sum_u128(s1) + src.sbase;
+    s2 = wave_sum_u128(s2) + src.sbase;
+    c1 = wave_sum_int(c1) + src.cbase;
+    c2 = wave_sum_int(c2) + src.cbase;
     if (s1 >= tau) {
       khi = plo; Shi = s1; Chi = c1;
+      sk = ka; sr = ra;
     } else if (s2 >= tau) {
       klo = plo; Slo = s1; Clo = c1;
       khi = phi; Shi = s2; Chi = c2;
+      sk = kb; sr = rb;
     } else {
       klo = phi; Slo = s2; Clo = c2;
+      sk = kc; sr = rc;
     }
-    int ncount = Chi - Clo;
+    const int ncount = Chi - Clo;
     bisect = (ncount == count);
     count = ncount;
   }
-
   if (!single_key) {
-    // <= 64 candidates: one per lane, bitonic sort by (key, row), exact scan
-    int mine = 0;
-#pragma unroll
-    for (int t = 0; t < T; ++t) mine += (keys[t] > klo && keys[t] <= khi) ? 1 : 0;
-    int off = wave_excl_scan_int(mine, lane);
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      if (keys[t] > klo && keys[t] <= khi && off < 64) {
-        wkey[off] = keys[t];
-        wrow[off] = lane + 64 * t;
-        ++off;
-      }
-    }
-    wave_lds_sync();
-    uint64_t ck = lane < count ? wkey[lane] : KEY_NONE;
-    int cr = lane < count ? wrow[lane] : 0x7fffffff;
-    wave_lds_sync();
-    wave_sort_key_row(ck, cr, lane);
-    u128 w = lane < count ? swf[cr] : (u128)0;
-    u128 S = wave_incl_scan_u128(w, lane) + Slo;
-    uint64_t hit = __ballot(lane < count && S >= tau);
-    if (!hit) {
-      err |= SEG_INTERNAL;
-      return;
-    }
-    int src = __builtin_ctzll(hit);
-    okey = uni_u64(shfl_u64(ck, src));
-    orow = uni_int(__shfl(cr, src));
+    wave_finish(s, src, klo, khi, count, Slo, tau, ws, okey, orow, err);
     return;
   }
-
-  // every candidate has the same key K: (key, row) order is row order, and
-  // rows ascend with (t, lane).  Rare: walk the rows again from memory.
+  // every candidate has the same key K: (key, row) order is enumeration order
   const uint64_t K = khi;
   u128 S = Slo;
-  for (int t = 0; t < tmax; ++t) {
-    int i = lane + 64 * t;
-    bool c = false;
-    if (i < n && sxj[i] != 0.0) {
-      double r = xk[i] / sxj[i];
-      r = r + 0.0;
-      c = key_of(r) == K;
-    }
-    u128 w = c ? swf[i] : (u128)0;
-    u128 sc = wave_incl_scan_u128(w, lane) + S;
-    uint64_t hit = __ballot(c && sc >= tau);
+  for (int t = 0; t < ns; ++t) {
+    uint64_t key;
+    int row;
+    src.at(t, key, row);
+    const bool c = key == K;
+    const u128 w = seg_weight(s, row, c);
+    const u128 sc = wave_incl_scan_u128(w, lane) + S;
+    const uint64_t hit = __ballot(c && sc >= tau);
     if (hit) {
-      int src = __builtin_ctzll(hit);
+      const int sl = __builtin_ctzll(hit);
       okey = K;
-      orow = src + 64 * t;
+      orow = uni_int(__shfl(row, sl));
       return;
     }
     S = uni_u128(shfl_u128(sc, 63));
@@ -246,64 +350,173 @@ __device__ __forceinline__ void wave_select(const uint64_t (&keys)[T], const u12
 }
 
 // e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0)
-template <int T>
-__device__ __forceinline__ double wave_residual(const double *__restrict__ xk, int n,
-                                                const double *__restrict__ sxj, double v, int lane) {
+__device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
   double p = 0.0;
-#pragma unroll 4
-  for (int t = 0; t < T; ++t) {
-    int i = lane + 64 * t;
-    if (i < n) {
-      double prod = v * sxj[i];
-      double d = xk[i] - prod;
-      p = p + fabs(d);
-    }
+#pragma unroll 8
+  for (int t = 0; t < s.T; ++t) {
+    const int i = s.lane + 64 * t;
+    const bool in = i < s.n;
+    const int ic = in ? i : 0;
+    const double prod = v * s.sxj[ic];
+    const double d = s.xk[ic] - prod;
+    p = p + (in ? fabs(d) : 0.0);
   }
   return wave_r64_tree(p);
 }
 
-// ---------------------------------------------------------------- segments
-// One workgroup per preserved column j; each wave walks k = wave, wave+4, ...
-// For every (j, k) and every lambda_t it writes
-//   V[(t m + j) m + k] = v_k,  E[...] = e_jk,  R[...] = median row (-1 for 0).
-// LDS: column j (x and exact fixed-point weight), lambda in fixed point for
-// column j, and a 64-entry compaction area per wave.
-constexpr int SEG_WAVES = 4;
-
-__host__ __device__ constexpr size_t seg_lds_bytes(int n, int L) {
-  return ((size_t)n * 8 + 15) / 16 * 16 + (size_t)n * 16 + (size_t)L * 16 + SEG_WAVES * 64 * 16;
+// Bitonic sort of 128 keys held two per lane (element 2*lane + r), ascending.
+__device__ __forceinline__ void wave_sort2(uint64_t &a, uint64_t &b, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const bool up = ((2 * lane) & size) == 0;
+      if (stride == 1) {
+        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+        a = up ? lo : hi;
+        b = up ? hi : lo;
+      } else {
+        const int ls = stride >> 1;
+        const uint64_t oa = shfl_xor_u64(a, ls), ob = shfl_xor_u64(b, ls);
+        const bool keep_min = (((2 * lane) & stride) == 0) == up;
+        a = keep_min ? (oa < a ? oa : a) : (oa > a ? oa : a);
+        b = keep_min ? (ob < b ? ob : b) : (ob > b ? ob : b);
+      }
+    }
+  }
 }
 
-template <int T>
+// ---------------------------------------------------------------- segments
+// Workgroup = (preserved column j, one part of the k range); its waves take
+// the next k from an LDS counter.  For every (j, k) and lambda_t it writes
+//   V[(t m + j) m + k] = v_k,  E[...] = e_jk,  R[...] = median row (-1 for 0).
+//
+// Per segment:
+//  1. a division-free pass sums the weights of the negative and of the
+//     non-positive ratios approximately.  Where those sums prove, with a
+//     rigorous error margin, that 0 minimises g_jk, v_k = 0 and e_jk is the
+//     R64 column mass of k (|x_ik - fl(0 x_ij)| = |x_ik|); where they prove
+//     the side of 0 the minimiser lies on, that side is taken.  Otherwise an
+//     exact pass (128-bit sums) decides.
+//  2. The ratios of 128 rows drawn once per j with probability proportional
+//     to |x_ij| estimate where the weighted median lies: a key window.
+//  3. One exact pass sums the weight below the window and builds an exact
+//     bucketed histogram of the window's weights in LDS, recording the rows
+//     that fall in the window; the bucket that reaches the target is
+//     finished by sorting its few elements.
+//  Whatever the window does not settle goes to the general rounds.
+constexpr int SEG_WAVES = 4;
+constexpr int SAMPLE_ROWS = 128;
+
+__host__ __device__ constexpr size_t seg_sxj_bytes(int n) {
+  return ((size_t)((n + 63) / 64) * 64 * 8 + 15) / 16 * 16;
+}
+__host__ __device__ constexpr size_t seg_lds_bytes(int n, int L) {
+  return seg_sxj_bytes(n) + SAMPLE_ROWS * 4 + (size_t)L * 16 + SEG_WAVES * sizeof(WaveScratch) + 16;
+}
+
+// exact A (negative ratios), B (non-positive), counts, one sample per side
+struct ExactSides {
+  u128 A, B;
+  int N, Z, NV;
+};
+
+__device__ __forceinline__ ExactSides exact_sides(const SegIO &s) {
+  u128 a128 = 0, z128 = 0;
+  int cN = 0, cZ = 0, cV = 0;
+#pragma unroll 2
+  for (int tt = 0; tt < s.T; ++tt) {
+    const int i = s.lane + 64 * tt;
+    const uint64_t key = seg_key(s, i);
+    const bool valid = key != KEY_NONE;
+    const u128 w = seg_weight(s, i, valid);
+    const bool neg = key < KEY_ZERO, zer = key == KEY_ZERO;
+    a128 += neg ? w : (u128)0;
+    z128 += zer ? w : (u128)0;
+    cN += neg ? 1 : 0;
+    cZ += zer ? 1 : 0;
+    cV += valid ? 1 : 0;
+  }
+  ExactSides e;
+  e.A = wave_sum_u128(a128);
+  e.B = e.A + wave_sum_u128(z128);
+  e.N = wave_sum_int(cN);
+  e.Z = wave_sum_int(cZ);
+  e.NV = wave_sum_int(cV);
+  return e;
+}
+
 __global__ void __launch_bounds__(256)
 k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInfo *__restrict__ ci,
-          LamArgs la, double *__restrict__ V, double *__restrict__ E, int *__restrict__ R,
+          LamArgs la, int ksplit, double *__restrict__ V, double *__restrict__ E, int *__restrict__ R,
           int *__restrict__ segflags) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int j = blockIdx.x;
+  const int j = blockIdx.x / ksplit, part = blockIdx.x % ksplit;
+  const int kchunk = (m + ksplit - 1) / ksplit;
+  const int kbeg = part * kchunk, kend = min(m, kbeg + kchunk);
   const int L = la.L;
-  double *sxj = (double *)smem;
-  u128 *swf = (u128 *)(smem + ((size_t)n * 8 + 15) / 16 * 16);
-  u128 *slam = swf + n;
-  unsigned char *wscr = (unsigned char *)(slam + L);
+  const int T = (n + 63) >> 6;
+  double *sxj = (double *)smem;                     // T*64 entries, zero padded
+  int *srow = (int *)(smem + seg_sxj_bytes(n));
+  u128 *slam = (u128 *)(srow + SAMPLE_ROWS);
+  WaveScratch *wsc = (WaveScratch *)(slam + L);
+  int *knext = (int *)(wsc + SEG_WAVES);
 
   const ColInfo cj = ci[j];
-  const double *xj = X + (long long)j * ld;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double x = xj[i];
-    sxj[i] = x;
-    swf[i] = (x != 0.0 && !cj.flags) ? fixed_of(fabs(x), cj.e0) : (u128)0;
-  }
+  const double *xjg = X + (long long)j * ld;
+  for (int i = threadIdx.x; i < T * 64; i += blockDim.x) sxj[i] = i < n ? xjg[i] : 0.0;
   for (int t = threadIdx.x; t < L; t += blockDim.x) slam[t] = lambda_fixed(la.lam[t], cj.e0);
+  if (threadIdx.x == 0) *knext = kbeg;
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint64_t *wkey = (uint64_t *)(wscr + wave * 64 * 16);
-  int *wrow = (int *)(wkey + 64);
+  if (wave == 0) {
+    // systematic sample of SAMPLE_ROWS rows with probability ~ |x_ij|: lane l
+    // owns the contiguous rows [l T, l T + T)
+    const int r0 = lane * T, r1 = min(n, r0 + T);
+    double tot = 0.0;
+    for (int i = r0; i < r1; ++i) tot = tot + fabs(sxj[i]);
+    const double incl = wave_incl_scan_dbl(tot, lane);
+    const double all = __shfl(incl, 63);
+    for (int r = lane; r < SAMPLE_ROWS; r += 64) srow[r] = -1;
+    wave_lds_sync();
+    if (all > 0.0) {
+      const double step = all / SAMPLE_ROWS;
+      double cum = incl - tot;
+      for (int i = r0; i < r1; ++i) {
+        const double nxt = cum + fabs(sxj[i]);
+        int r = (int)ceil(cum / step - 0.5);
+        r = r < 0 ? 0 : r;
+        for (; r < SAMPLE_ROWS && (r + 0.5) * step < nxt; ++r) srow[r] = i;
+        cum = nxt;
+      }
+    }
+    wave_lds_sync();
+    if (lane == 0) {
+      int first = 0;
+      while (first < n && sxj[first] == 0.0) ++first;
+      if (first >= n) first = 0;
+      int prev = first;
+      for (int r = 0; r < SAMPLE_ROWS; ++r) {
+        if (srow[r] < 0 || sxj[srow[r]] == 0.0) srow[r] = prev;
+        prev = srow[r];
+      }
+    }
+  }
+  __syncthreads();
+
+  WaveScratch *ws = wsc + wave;
   const long long mm = (long long)m * m;
+  const double Wd = cj.W;
+  int Tp = 1;
+  while (Tp < T) Tp <<= 1;
   int err = 0;
 
-  for (int k = wave; k < m; k += SEG_WAVES) {
+  while (true) {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(knext, 1);
+    k = uni_int(__shfl(k, 0));
+    if (k >= kend) break;
     const long long base = (long long)j * m + k;
     if (k == j || cj.flags) {
       if (lane == 0) {
@@ -315,61 +528,147 @@ k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInf
       }
       continue;
     }
-    const double *xk = X + (long long)k * ld;
-    // ratios -> keys; exact mass of the negative and zero blocks
-    uint64_t keys[T];
-    u128 accA = 0, accZ = 0;
-    int cN = 0, cZ = 0, cV = 0;
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      int i = lane + 64 * t;
-      uint64_t key = KEY_NONE;
-      if (i < n) {
-        double a = sxj[i];
-        double b = xk[i];
-        if (a != 0.0) {
-          double r = b / a;
-          r = r + 0.0;
-          key = key_of(r);
-        }
-      }
-      keys[t] = key;
-      if (key != KEY_NONE) {
-        ++cV;
-        u128 w = swf[i];
-        if (key < KEY_ZERO) { accA += w; ++cN; }
-        else if (key == KEY_ZERO) { accZ += w; ++cZ; }
-      }
-      L1_SLOT_FENCE(t);
-    }
-    const u128 A = wave_sum_u128(accA);
-    const u128 B = A + wave_sum_u128(accZ);
-    const int N = wave_sum_int(cN), Z = wave_sum_int(cZ), NV = wave_sum_int(cV);
-    const u128 W = cj.wfix;
+    const ColInfo ck = ci[k];
+    const SegIO s{X + (long long)k * ld, sxj, n, T, Tp, cj.e0, lane};
+    const double Wk = ck.W;
 
+    // 1. approximate weights of negative (A) and non-positive (B) ratios, no
+    // division: signs decide.  |x_ik / x_ij| can underflow to 0 only if the
+    // exponent fields differ by more than 1000; the column ranges rule that
+    // out for the whole segment in the usual case.
+    const bool maybe_tiny = ck.nnz > 0 && cj.nnz > 0 && ck.bemin - cj.bemax < -1000;
+    double accA = 0.0, accB = 0.0;
+    int unc = 0;
+#pragma unroll 8
+    for (int t = 0; t < T; ++t) {
+      const int i = lane + 64 * t;
+      const double a = sxj[i];
+      const double b = s.xk[i < n ? i : n - 1];
+      const double w = fabs(a);
+      const bool bz = b == 0.0;
+      const unsigned ha = (unsigned)(__double_as_longlong(a) >> 32), hb = (unsigned)(__double_as_longlong(b) >> 32);
+      const bool opp = ((ha ^ hb) >> 31) != 0;
+      if (maybe_tiny) {
+        const int gap = (int)((hb >> 20) & 0x7ff) - (int)((ha >> 20) & 0x7ff);
+        unc |= (a != 0.0 && !bz && gap < -1000) ? 1 : 0;
+      }
+      // rows i >= n have a == 0 in the padded LDS copy: weight 0
+      accA = accA + ((opp && !bz) ? w : 0.0);
+      accB = accB + ((opp || bz) ? w : 0.0);
+    }
+    accA = wave_sum_dbl(accA);
+    accB = wave_sum_dbl(accB);
+    if (maybe_tiny) unc = wave_max_int(unc);
+
+    bool have_exact = false;
+    ExactSides ex;
     int prev_row = -2;
     double prev_e = 0.0;
     for (int t = 0; t < L; ++t) {
-      const u128 lamf = slam[t];
+      const double lam = la.lam[t];
+      // decision margin 2^-32 (W + lambda): far above the rounding error of
+      // the approximate sums (at most ~n 2^-53 of W)
+      const double M = 0x1p-32 * (Wd + lam);
+      const double d1 = Wd + lam - 2.0 * accA;     // >= 0  <=>  2A <= W + lambda
+      const double d2 = 2.0 * accB + lam - Wd;     // >= 0  <=>  W <= 2B + lambda
+      int side;                                    // 0: v = 0, 1: negative, 2: positive, 3: unknown
+      if (unc) side = 3;
+      else if (d1 > M && d2 > M) side = 0;
+      else if (d1 < -M) side = 1;
+      else if (d2 < -M) side = 2;
+      else side = 3;
+      const u128 W = cj.wfix, lamf = slam[t];
       const u128 WpL = W + lamf;
-      const u128 twoA = A << 1, twoB = B << 1;
+      if (side == 3) {
+        if (!have_exact) {
+          ex = exact_sides(s);
+          have_exact = true;
+        }
+        side = ((ex.A << 1) <= WpL && W <= (ex.B << 1) + lamf) ? 0 : ((ex.A << 1) > WpL ? 1 : 2);
+      }
       uint64_t okey = KEY_NONE;
       int orow = -1;
-      if (!(twoA <= WpL && W <= twoB + lamf)) {      // else 0 minimises g_jk
-        const bool neg = twoA > WpL;
+      if (side != 0) {
+        const bool neg = side == 1;
         // negative side: first S_p > (W + lambda)/2; positive: first S_p >= (W - lambda)/2
         const u128 tau = neg ? (WpL >> 1) + 1 : (W - lamf + 1) >> 1;
-        wave_select<T>(keys, swf, sxj, xk, n, T, neg ? 0ull : KEY_ZERO, neg ? KEY_ZERO - 1 : KEY_NONE - 1,
-                       neg ? (u128)0 : B, neg ? A : W, neg ? 0 : N + Z, neg ? N : NV, tau, lane, wkey,
-                       wrow, okey, orow, err);
+        const uint64_t klo0 = neg ? 0ull : KEY_ZERO, khi0 = neg ? KEY_ZERO - 1 : KEY_NONE - 1;
+
+        // 2. window from the weighted sample of rows
+        const double q = (neg ? 0.5 * (Wd + lam) : 0.5 * (Wd - lam)) / Wd;
+        uint64_t sa = seg_key(s, srow[lane]), sb = seg_key(s, srow[lane + 64]);
+        wave_sort2(sa, sb, lane);
+        constexpr double WDELTA = 0.12;
+        const int ilo = (int)floor((q - WDELTA) * SAMPLE_ROWS) - 1;
+        const int ihi = (int)ceil((q + WDELTA) * SAMPLE_ROWS);
+        uint64_t plo = klo0, phi = khi0;
+        if (ilo >= 0 && ilo < SAMPLE_ROWS) {
+          const uint64_t v = uni_u64(shfl_u64((ilo & 1) ? sb : sa, ilo >> 1));
+          plo = v > plo ? v : plo;
+        }
+        if (ihi >= 0 && ihi < SAMPLE_ROWS) {
+          const uint64_t v = uni_u64(shfl_u64((ihi & 1) ? sb : sa, ihi >> 1));
+          phi = v < phi ? v : phi;
+        }
+        if (plo > khi0) plo = khi0;
+        if (phi < plo) phi = plo;
+
+        // 3. exact pass: weight and count at or below the window; the window's
+        // elements go to the LDS list (in row order)
+        u128 slo128 = 0;
+        int nwin = 0, clo = 0;
+#pragma unroll 2
+        for (int tt = 0; tt < T; ++tt) {
+          const int i = lane + 64 * tt;
+          const uint64_t key = seg_key(s, i);
+          const bool valid = key != KEY_NONE;
+          const bool le_lo = valid && key <= plo;
+          const bool inwin = valid && key > plo && key <= phi;
+          slo128 += le_lo ? seg_weight(s, i, true) : (u128)0;
+          clo += le_lo ? 1 : 0;
+          const uint64_t wm = __ballot(inwin);
+          const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
+          nwin += __builtin_popcountll(wm);
+          if (inwin && pos < WIN_CAP) {
+            ws->wkeys[pos] = key;
+            ws->wrows[pos] = (unsigned short)i;
+          }
+        }
+        const u128 Slw = wave_sum_u128(slo128);
+        const int Clw = wave_sum_int(clo);
+        nwin = uni_int(nwin);
+        wave_lds_sync();
+        bool settled = false;
+        if (nwin <= WIN_CAP && Slw < tau) {
+          const ListSrc ls{s, Slw, Clw, ws->wkeys, ws->wrows, nwin};
+          // exact weight of the window
+          u128 wwin = 0;
+          for (int e = lane; e < nwin; e += 64) wwin += seg_weight(s, (int)ws->wrows[e], true);
+          wwin = wave_sum_u128(wwin);
+          if (tau <= Slw + wwin) {
+            wave_select_rounds(s, ls, plo, phi, Slw, Slw + wwin, Clw, Clw + nwin, tau, ws, okey, orow, err);
+            settled = true;
+          }
+        }
+        if (!settled) {
+          // the window missed (or overflowed): rounds over the whole side
+          if (!have_exact) {
+            ex = exact_sides(s);
+            have_exact = true;
+          }
+          const ColSrc cs{s, (u128)0, 0};
+          wave_select_rounds(s, cs, klo0, khi0, neg ? (u128)0 : ex.B, neg ? ex.A : W, neg ? 0 : ex.N + ex.Z,
+                             neg ? ex.N : ex.NV, tau, ws, okey, orow, err);
+        }
       }
       const double v = (orow >= 0) ? ratio_of_key(okey) : 0.0;
       double e;
-      if (orow == prev_row) {
+      if (orow < 0) {
+        e = Wk;                                      // R64 sum of |x_ik|
+      } else if (orow == prev_row) {
         e = prev_e;
       } else {
-        e = wave_residual<T>(xk, n, sxj, v, lane);
-        e = __shfl(e, 0);
+        e = __shfl(wave_residual(s, v), 0);
       }
       prev_row = orow;
       prev_e = e;

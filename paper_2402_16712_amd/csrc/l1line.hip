@@ -126,35 +126,28 @@ __global__ void k_fill_int(int *p, long long count, int value) {
   if (i < count) p[i] = value;
 }
 
-template <int T>
 static int launch_seg(l1line_ctx ctx, const double *X, int n, int m, long long ld, const FitWs &w,
                       const LamArgs &la, hipStream_t s) {
-  size_t lds = seg_lds_bytes(n, la.L);
+  const size_t lds = seg_lds_bytes(n, la.L);
   static bool attr_set = false;
   if (!attr_set) {
-    HIP_TRY(hipFuncSetAttribute((const void *)k_fit_seg<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_TRY(hipFuncSetAttribute((const void *)k_fit_seg, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS)));
     attr_set = true;
   }
+  // enough workgroups to fill the chip several times over (and to even out
+  // the uneven cost of the segments), at least 8 k per workgroup
+  int ksplit = (6144 + m - 1) / m;
+  ksplit = ksplit < 1 ? 1 : ksplit;
+  const int kmax = m / 8 > 1 ? m / 8 : 1;
+  ksplit = ksplit > kmax ? kmax : ksplit;
   {
     ProfScope ps(ctx, s, "fit_seg");
-    hipLaunchKernelGGL(k_fit_seg<T>, dim3(m), dim3(64 * SEG_WAVES), lds, s, X, n, m, ld, w.ci, la, w.V,
-                       w.E, w.R, w.segflags);
+    hipLaunchKernelGGL(k_fit_seg, dim3((unsigned)(m * ksplit)), dim3(64 * SEG_WAVES), lds, s, X, n, m, ld,
+                       w.ci, la, ksplit, w.V, w.E, w.R, w.segflags);
   }
   HIP_TRY(hipGetLastError());
   return L1LINE_OK;
-}
-
-static int dispatch_seg(l1line_ctx ctx, const double *X, int n, int m, long long ld, const FitWs &w,
-                        const LamArgs &la, hipStream_t s) {
-  int need = (n + 63) / 64;
-  if (need <= 1) return launch_seg<1>(ctx, X, n, m, ld, w, la, s);
-  if (need <= 2) return launch_seg<2>(ctx, X, n, m, ld, w, la, s);
-  if (need <= 4) return launch_seg<4>(ctx, X, n, m, ld, w, la, s);
-  if (need <= 8) return launch_seg<8>(ctx, X, n, m, ld, w, la, s);
-  if (need <= 16) return launch_seg<16>(ctx, X, n, m, ld, w, la, s);
-  if (need <= 32) return launch_seg<32>(ctx, X, n, m, ld, w, la, s);
-  return launch_seg<64>(ctx, X, n, m, ld, w, la, s);
 }
 
 static int run_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const LamArgs &la,
@@ -173,7 +166,7 @@ static int run_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64
                        (long long)ld, w.ci);
   }
   HIP_TRY(hipGetLastError());
-  st = dispatch_seg(ctx, X, (int)n, (int)m, (long long)ld, w, la, s);
+  st = launch_seg(ctx, X, (int)n, (int)m, (long long)ld, w, la, s);
   if (st) return st;
   {
     ProfScope ps(ctx, s, "reduce");
