@@ -66,7 +66,7 @@ extern "C" {
 #define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N (host check)                  */
 #define L1LINE_EINTERNAL (-8)  /* a selection exceeded its round bound (device)      */
 
-#define L1LINE_MAX_N 4096          /* rows per matrix handled by this build       */
+#define L1LINE_MAX_N 16384         /* rows per matrix (column j is held in LDS)   */
 #define L1LINE_MAX_LAMBDAS 128     /* penalties per call (passed by value)        */
 
 typedef struct l1line_ctx_s *l1line_ctx;
@@ -120,6 +120,50 @@ int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                     int64_t ld, const double *lambdas, int64_t L, double *V,
                     int64_t *J, double *OBJ, int32_t *ROW, double *ZALL,
                     int32_t *status, void *stream);
+
+/* One problem of a batch.  Same conventions as l1line_fit_path. */
+typedef struct {
+  const double *X;        /* DEVICE, n x m column-major, leading dimension ld */
+  int64_t n, m, ld;
+  const double *lambdas;  /* HOST, L penalties (1 <= L <= L1LINE_MAX_LAMBDAS) */
+  int64_t L;
+  double *V;              /* DEVICE [L*m]  v*(lambda_t), row t              */
+  int64_t *J;             /* DEVICE [L]    j*(lambda_t)                     */
+  double *OBJ;            /* DEVICE [L]    z_{j*}(lambda_t)                 */
+  int32_t *ROW;           /* DEVICE [L*m]  median rows (nullable)           */
+  double *ZALL;           /* DEVICE [L*m]  z_j(lambda_t) (nullable)         */
+  int32_t *status;        /* DEVICE [1]    device status (nullable)         */
+} l1line_problem;
+
+/* Flag of l1line_fit_batch: capture the launch sequence into a HIP graph the
+ * first time a batch layout (the problems' pointers, sizes and penalties) is
+ * seen, and replay it while the same layout is submitted again.  The first
+ * call with a new layout waits for its metadata copy (host synchronisation). */
+#define L1LINE_BATCH_GRAPH 1
+
+/* Algorithm 1 (with a lambda path each) for B independent matrices of
+ * uneven sizes in one launch sequence: a persistent segment kernel pulls
+ * (matrix, j, k-range) work items, largest first, from a device counter.
+ *   probs  HOST array of B problem descriptors (read during the call only)
+ *   flags  0 or L1LINE_BATCH_GRAPH
+ * Each problem's outputs equal those of l1line_fit_path on it, bit for bit.
+ * Host errors: EINVAL (bad flags, B < 1, any problem failing the checks of
+ * l1line_fit_path), ESIZE, ENOMEM, EHIP. */
+int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
+                     int flags, void *stream);
+
+/* Autotuner: runs the batch under every candidate of a small grid of launch
+ * parameters (persistent workgroups per compute unit, fewest k per work
+ * item, work items per compute unit), times the segment kernel with HIP
+ * events, keeps the fastest in the context and writes it to params_out
+ * (HOST [3], nullable).  Synchronises the stream. */
+int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
+                    void *stream, int32_t *params_out);
+
+/* Read / set the context's launch parameters (HOST [3]: workgroups per CU in
+ * [1, 16], fewest k per item >= 1, items per CU in [1, 4096]). */
+int l1line_tune_get(l1line_ctx ctx, int32_t *params);
+int l1line_tune_set(l1line_ctx ctx, const int32_t *params);
 
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.

@@ -15,11 +15,21 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_build", "libl1line.so")
 
 OK, EINVAL, EHIP, ENONFINITE, ERANGE, ENOMEM, EWIDE, ESIZE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
-MAX_N = 4096
+MAX_N = 16384
 MAX_LAMBDAS = 128
 
 EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_column_stats",
-           "l1line_fit", "l1line_fit_path", "l1line_profile", "l1line_profile_read"]
+           "l1line_fit", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
+           "l1line_tune_set", "l1line_profile", "l1line_profile_read"]
+BATCH_GRAPH = 1
+
+
+class Problem(ctypes.Structure):
+    """l1line_problem of include/l1line.h."""
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("lambdas", ctypes.c_void_p), ("L", ctypes.c_int64),
+                ("V", ctypes.c_void_p), ("J", ctypes.c_void_p), ("OBJ", ctypes.c_void_p),
+                ("ROW", ctypes.c_void_p), ("ZALL", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class L1LineError(RuntimeError):
@@ -47,11 +57,16 @@ def lib() -> ctypes.CDLL:
         L.l1line_column_stats.argtypes = [P, P, I64, I64, I64, P, P, P, P]
         L.l1line_fit.argtypes = [P, P, I64, I64, I64, D, P, P, P, P, P, P, P]
         L.l1line_fit_path.argtypes = [P, P, I64, I64, I64, P, I64, P, P, P, P, P, P, P]
+        L.l1line_fit_batch.argtypes = [P, P, I64, I32, P]
+        L.l1line_autotune.argtypes = [P, P, I64, P, P]
+        L.l1line_tune_get.argtypes = [P, P]
+        L.l1line_tune_set.argtypes = [P, P]
         L.l1line_profile.argtypes = [P, I32]
         L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),
                                           ctypes.POINTER(I64), I32]
         for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit",
-                  "l1line_fit_path", "l1line_profile", "l1line_profile_read"):
+                  "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
+                  "l1line_tune_set", "l1line_profile", "l1line_profile_read"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -184,3 +199,55 @@ class Context:
                                      _ptr(out["ZALL"]), _ptr(out["status"]), self._stream()),
                "l1line_fit_path")
         return out
+
+    # ------------------------------------------------------------- batches
+    def _batch_args(self, problems, rows, z_all):
+        torch = _torch()
+        arr = (Problem * len(problems))()
+        outs, keep = [], []
+        for q, (X, lambdas) in enumerate(problems):
+            n, m, ld = _check_matrix(X)
+            lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+            L = lam.size
+            o = dict(V=self._empty((L, m), torch.float64), J=self._empty((L,), torch.int64),
+                     OBJ=self._empty((L,), torch.float64),
+                     ROW=self._empty((L, m), torch.int32) if rows else None,
+                     ZALL=self._empty((L, m), torch.float64) if z_all else None,
+                     status=self._empty((1,), torch.int32))
+            keep.append(lam)
+            arr[q] = Problem(X.data_ptr(), n, m, ld, lam.ctypes.data, L, o["V"].data_ptr(),
+                             o["J"].data_ptr(), o["OBJ"].data_ptr(),
+                             o["ROW"].data_ptr() if rows else None,
+                             o["ZALL"].data_ptr() if z_all else None, o["status"].data_ptr())
+            outs.append(o)
+        return arr, outs, keep
+
+    def fit_batch(self, problems, graph: bool = False, rows: bool = True, z_all: bool = True):
+        """problems: list of (X device tensor, lambdas).  Returns one dict per
+        problem, as fit_path."""
+        arr, outs, keep = self._batch_args(problems, rows, z_all)
+        _check(lib().l1line_fit_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems),
+                                      BATCH_GRAPH if graph else 0, self._stream()), "l1line_fit_batch")
+        del keep
+        return outs
+
+    def fit_batch_prepared(self, arr, n, graph: bool = False):
+        """Submit an already built Problem array (reuse of the same layout)."""
+        _check(lib().l1line_fit_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), n,
+                                      BATCH_GRAPH if graph else 0, self._stream()), "l1line_fit_batch")
+
+    def autotune(self, problems):
+        arr, outs, keep = self._batch_args(problems, True, True)
+        params = (ctypes.c_int32 * 3)()
+        _check(lib().l1line_autotune(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems),
+                                     self._stream(), params), "l1line_autotune")
+        return list(params)
+
+    def tune_get(self):
+        params = (ctypes.c_int32 * 3)()
+        _check(lib().l1line_tune_get(self._h, params), "l1line_tune_get")
+        return list(params)
+
+    def tune_set(self, params):
+        arr = (ctypes.c_int32 * 3)(*[int(x) for x in params])
+        _check(lib().l1line_tune_set(self._h, arr), "l1line_tune_set")

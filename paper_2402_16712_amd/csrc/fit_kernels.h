@@ -26,20 +26,45 @@ struct ColInfo {
   int bemax;    // largest biased exponent field over nonzero entries
 };
 
-struct LamArgs {
-  int L;
-  double lam[L1LINE_MAX_LAMBDAS];
+// One problem of a batch, as the kernels see it.  Workspace offsets are in
+// elements of the batch-wide arrays.
+struct ProbDesc {
+  const double *X;      // n x m, column-major
+  long long ld;
+  int n, m, L;
+  int lam_off;          // first penalty in the flat penalty array
+  int col_off;          // first column in ColInfo / segflags
+  int out_off;          // first (problem, lambda) slot: sum of L over earlier problems
+  long long ws_off;     // first element of this problem's L*m*m block in V / E / R
+  long long z_off;      // first element of this problem's L*m block in Z / zflag
+  double *Vout;         // L*m
+  long long *Jout;      // L
+  double *OBJout;       // L
+  int *ROWout;          // L*m or null
+  double *ZALLout;      // L*m or null
+  int *status;          // 1 or null
 };
+
+// A workgroup's unit of work: problem b, preserved column j, k in [kbeg, kend).
+struct WorkItem {
+  int b, j, kbeg, kend;
+};
+
+// first index i in [0, count) with prefix[i + 1] > g (prefix has count + 1 entries)
+__device__ __forceinline__ int find_owner(const int *__restrict__ prefix, int count, long long g) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 // ------------------------------------------------------------------ columns
 // One wave per column: finiteness, counts, the fixed-point exponent e0, the
 // range check, the exact fixed-point mass and the R64 column mass.
-__global__ void __launch_bounds__(256)
-k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__restrict__ ci) {
-  const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (col >= m) return;
-  const double *x = X + (long long)col * ld;
+__device__ __forceinline__ void colprep_wave(const double *__restrict__ x, int n, ColInfo *__restrict__ out,
+                                             int lane) {
   int bad = 0, nnz = 0, zeros = 0, lsb = 1 << 20, hb = -(1 << 20), bemin = 4096, bemax = -1;
   double part = 0.0;
   for (int i = lane; i < n; i += 64) {
@@ -91,8 +116,28 @@ k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__r
     c.flags = flags;
     c.bemin = bemin;
     c.bemax = bemax;
-    ci[col] = c;
+    *out = c;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__restrict__ ci) {
+  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (col >= m) return;
+  colprep_wave(X + (long long)col * ld, n, ci + col, threadIdx.x & 63);
+}
+
+// every column of every problem: colstart[b] = first column of problem b
+__global__ void __launch_bounds__(256)
+k_colprep_batch(const ProbDesc *__restrict__ P, const int *__restrict__ colstart, int B, int total_cols,
+                ColInfo *__restrict__ ci, int *__restrict__ segflags) {
+  const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (g >= total_cols) return;
+  const int b = find_owner(colstart, B, g);
+  const ProbDesc d = P[b];
+  const int col = g - colstart[b];
+  colprep_wave(d.X + (long long)col * d.ld, d.n, ci + g, threadIdx.x & 63);
+  if ((threadIdx.x & 63) == 0) segflags[g] = 0;
 }
 
 // ----------------------------------------------------------- segment access
@@ -349,6 +394,71 @@ __device__ __forceinline__ void wave_select_rounds(const SegIO &s, const Src &sr
   err |= SEG_INTERNAL;
 }
 
+// --------------------------------------------------- sorting the window list
+// The window list (nlist <= WIN_CAP entries, row order) is padded to a power
+// of two N >= 64, sorted in place in LDS by (key, row) with a bitonic network
+// (each lane handles N/128 compare-exchanges per stage), then read E = N/64
+// consecutive elements per lane and its exact prefix weights scanned from
+// Slo: the first element whose prefix reaches tau is the answer.
+__device__ __forceinline__ void wave_sort_list(const SegIO &s, WaveScratch *ws, int nlist, u128 Slo, u128 tau,
+                                               uint64_t &okey, int &orow, int &err) {
+  const int lane = s.lane;
+  int N = 64;
+  while (N < nlist) N <<= 1;
+  for (int e = nlist + lane; e < N; e += 64) {
+    ws->wkeys[e] = KEY_NONE;
+    ws->wrows[e] = 0xFFFF;
+  }
+  wave_lds_sync();
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int pidx = lane; pidx < (N >> 1); pidx += 64) {
+        const int e = ((pidx & ~(stride - 1)) << 1) | (pidx & (stride - 1));
+        const int f = e + stride;
+        const uint64_t ke = ws->wkeys[e], kf = ws->wkeys[f];
+        const unsigned re = ws->wrows[e], rf = ws->wrows[f];
+        const bool up = (e & size) == 0;
+        const bool gt = ke > kf || (ke == kf && re > rf);
+        const bool lt = ke < kf || (ke == kf && re < rf);
+        if (up ? gt : lt) {
+          ws->wkeys[e] = kf;
+          ws->wkeys[f] = ke;
+          ws->wrows[e] = (unsigned short)rf;
+          ws->wrows[f] = (unsigned short)re;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  const int E = N >> 6;
+  u128 tot = 0;
+  for (int q = 0; q < E; ++q) {
+    const int e = E * lane + q;
+    const bool valid = ws->wkeys[e] != KEY_NONE;
+    tot += seg_weight(s, valid ? (int)ws->wrows[e] : 0, valid);
+  }
+  const u128 incl = wave_incl_scan_u128(tot, lane);
+  u128 run = Slo + incl - tot;
+  int ehit = -1;
+  for (int q = 0; q < E; ++q) {
+    const int e = E * lane + q;
+    const bool valid = ws->wkeys[e] != KEY_NONE;
+    run += seg_weight(s, valid ? (int)ws->wrows[e] : 0, valid);
+    if (ehit < 0 && valid && run >= tau) ehit = e;
+  }
+  const uint64_t hit = __ballot(ehit >= 0);
+  if (!hit) {
+    err |= SEG_INTERNAL;
+    okey = KEY_NONE;
+    orow = -1;
+    return;
+  }
+  const int e = uni_int(__shfl(ehit, __builtin_ctzll(hit)));
+  okey = ws->wkeys[e];
+  orow = (int)ws->wrows[e];
+  wave_lds_sync();
+}
+
 // e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0)
 __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
   double p = 0.0;
@@ -446,15 +556,13 @@ __device__ __forceinline__ ExactSides exact_sides(const SegIO &s) {
   return e;
 }
 
-__global__ void __launch_bounds__(256)
-k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInfo *__restrict__ ci,
-          LamArgs la, int ksplit, double *__restrict__ V, double *__restrict__ E, int *__restrict__ R,
-          int *__restrict__ segflags) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int j = blockIdx.x / ksplit, part = blockIdx.x % ksplit;
-  const int kchunk = (m + ksplit - 1) / ksplit;
-  const int kbeg = part * kchunk, kend = min(m, kbeg + kchunk);
-  const int L = la.L;
+// One work item, by the whole workgroup (every thread calls it).  ci, V, E,
+// R and segflags are this problem's slices.
+__device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, int m, long long ld,
+                                         const ColInfo *__restrict__ ci, const double *__restrict__ lam, int L,
+                                         int j, int kbeg, int kend, double *__restrict__ V,
+                                         double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
+                                         unsigned char *smem) {
   const int T = (n + 63) >> 6;
   double *sxj = (double *)smem;                     // T*64 entries, zero padded
   int *srow = (int *)(smem + seg_sxj_bytes(n));
@@ -465,7 +573,7 @@ k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInf
   const ColInfo cj = ci[j];
   const double *xjg = X + (long long)j * ld;
   for (int i = threadIdx.x; i < T * 64; i += blockDim.x) sxj[i] = i < n ? xjg[i] : 0.0;
-  for (int t = threadIdx.x; t < L; t += blockDim.x) slam[t] = lambda_fixed(la.lam[t], cj.e0);
+  for (int t = threadIdx.x; t < L; t += blockDim.x) slam[t] = lambda_fixed(lam[t], cj.e0);
   if (threadIdx.x == 0) *knext = kbeg;
   __syncthreads();
 
@@ -565,12 +673,12 @@ k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInf
     int prev_row = -2;
     double prev_e = 0.0;
     for (int t = 0; t < L; ++t) {
-      const double lam = la.lam[t];
+      const double lamt = lam[t];
       // decision margin 2^-32 (W + lambda): far above the rounding error of
       // the approximate sums (at most ~n 2^-53 of W)
-      const double M = 0x1p-32 * (Wd + lam);
-      const double d1 = Wd + lam - 2.0 * accA;     // >= 0  <=>  2A <= W + lambda
-      const double d2 = 2.0 * accB + lam - Wd;     // >= 0  <=>  W <= 2B + lambda
+      const double M = 0x1p-32 * (Wd + lamt);
+      const double d1 = Wd + lamt - 2.0 * accA;     // >= 0  <=>  2A <= W + lambda
+      const double d2 = 2.0 * accB + lamt - Wd;     // >= 0  <=>  W <= 2B + lambda
       int side;                                    // 0: v = 0, 1: negative, 2: positive, 3: unknown
       if (unc) side = 3;
       else if (d1 > M && d2 > M) side = 0;
@@ -595,7 +703,7 @@ k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInf
         const uint64_t klo0 = neg ? 0ull : KEY_ZERO, khi0 = neg ? KEY_ZERO - 1 : KEY_NONE - 1;
 
         // 2. window from the weighted sample of rows
-        const double q = (neg ? 0.5 * (Wd + lam) : 0.5 * (Wd - lam)) / Wd;
+        const double q = (neg ? 0.5 * (Wd + lamt) : 0.5 * (Wd - lamt)) / Wd;
         uint64_t sa = seg_key(s, srow[lane]), sb = seg_key(s, srow[lane + 64]);
         wave_sort2(sa, sb, lane);
         constexpr double WDELTA = 0.12;
@@ -646,7 +754,8 @@ k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInf
           for (int e = lane; e < nwin; e += 64) wwin += seg_weight(s, (int)ws->wrows[e], true);
           wwin = wave_sum_u128(wwin);
           if (tau <= Slw + wwin) {
-            wave_select_rounds(s, ls, plo, phi, Slw, Slw + wwin, Clw, Clw + nwin, tau, ws, okey, orow, err);
+            wave_sort_list(s, ws, nwin, Slw, tau, okey, orow, err);
+            (void)ls;
             settled = true;
           }
         }
@@ -680,21 +789,62 @@ k_fit_seg(const double *__restrict__ X, int n, int m, long long ld, const ColInf
     }
   }
   if (err && lane == 0) atomicOr(segflags + j, err);
+  __syncthreads();   // the LDS is reused by the next item
+}
+
+// Persistent segment kernel: every workgroup pulls work items from a global
+// counter until none is left (items are ordered by decreasing cost).  With
+// items == nullptr the items of problem 0 are implicit: item q covers
+// j = q / ksplit and the (q mod ksplit)-th of ksplit equal k ranges.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int ksplit,
+            int *__restrict__ counter, const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
+            double *__restrict__ V, double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int q = s_item;
+    __syncthreads();
+    if (q >= nitems) break;
+    WorkItem it;
+    if (items) {
+      it = items[q];
+    } else {
+      const int m0 = P[0].m;
+      const int kchunk = (m0 + ksplit - 1) / ksplit;
+      it.b = 0;
+      it.j = q / ksplit;
+      it.kbeg = (q % ksplit) * kchunk;
+      it.kend = min(m0, it.kbeg + kchunk);
+    }
+    const ProbDesc d = P[it.b];
+    seg_item(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, it.j, it.kbeg, it.kend,
+             V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, smem);
+  }
 }
 
 // ------------------------------------------------------------ per-j objective
-// One wave per (j, lambda_t): E_j = R64_k e_jk, P_j = R64_k |v_k|,
+// One wave per (problem, lambda_t, j): E_j = R64_k e_jk, P_j = R64_k |v_k|,
 // z_j = E_j + fl(lambda P_j).  zflag marks an infinite or NaN v_k.
+// zstart[b] = first (t, j) slot of problem b (sum of L m over earlier ones).
 __global__ void __launch_bounds__(64)
-k_reduce(const double *__restrict__ V, const double *__restrict__ E, int m, LamArgs la,
-         double *__restrict__ Z, int *__restrict__ zflag) {
-  const int j = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
-  const long long off = ((long long)t * m + j) * m;
+k_reduce_batch(const ProbDesc *__restrict__ P, const int *__restrict__ zstart, int B,
+               const double *__restrict__ lam_all, const double *__restrict__ V, const double *__restrict__ E,
+               double *__restrict__ Z, int *__restrict__ zflag) {
+  const long long g = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int b = find_owner(zstart, B, g);
+  const ProbDesc d = P[b];
+  const int local = (int)(g - zstart[b]);
+  const int t = local / d.m, j = local % d.m;
+  const long long off = d.ws_off + ((long long)t * d.m + j) * d.m;
   double pe = 0.0, pv = 0.0;
   int bad = 0;
-  for (int k = lane; k < m; k += 64) {
+  for (int k = lane; k < d.m; k += 64) {
     pe = pe + E[off + k];
-    double a = fabs(V[off + k]);
+    const double a = fabs(V[off + k]);
     pv = pv + a;
     bad |= !isfinite(a);
   }
@@ -702,26 +852,31 @@ k_reduce(const double *__restrict__ V, const double *__restrict__ E, int m, LamA
   pv = wave_r64_tree(pv);
   bad = wave_max_int(bad);
   if (lane == 0) {
-    double pen = la.lam[t] * pv;
-    double z = pe + pen;
-    Z[(long long)t * m + j] = z;
-    zflag[(long long)t * m + j] = bad;
+    const double pen = lam_all[d.lam_off + t] * pv;
+    const double z = pe + pen;
+    Z[d.z_off + (long long)t * d.m + j] = z;
+    zflag[d.z_off + (long long)t * d.m + j] = bad;
   }
 }
 
 // -------------------------------------------------------------- argmin/gather
-// One workgroup per lambda_t: j* = lexicographic argmin of (z_j, j); gathers
-// v*, rows, z_all.  Workgroup 0 also folds every flag into the status word.
+// One workgroup per (problem, lambda_t): j* = lexicographic argmin of
+// (z_j, j); gathers v*, rows, z_all.  The workgroup of t = 0 also folds the
+// problem's flags into its status word.  ostart[b] = sum of L over earlier
+// problems.
 __global__ void __launch_bounds__(256)
-k_argmin(const double *__restrict__ V, const int *__restrict__ R, const double *__restrict__ Z,
-         const int *__restrict__ zflag, const ColInfo *__restrict__ ci, const int *__restrict__ segflags,
-         int m, int L, double *__restrict__ vout, int64_t *__restrict__ jout, double *__restrict__ objout,
-         int *__restrict__ rowout, double *__restrict__ zall, int *__restrict__ status) {
+k_argmin_batch(const ProbDesc *__restrict__ P, const int *__restrict__ ostart, int B,
+               const double *__restrict__ V, const int *__restrict__ R, const double *__restrict__ Z,
+               const int *__restrict__ zflag, const ColInfo *__restrict__ ci, const int *__restrict__ segflags) {
   __shared__ double sz[256];
   __shared__ int sj[256];
   __shared__ int sflag[256];
-  const int t = blockIdx.x, tid = threadIdx.x;
-  const double *z = Z + (long long)t * m;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int b = find_owner(ostart, B, g);
+  const ProbDesc d = P[b];
+  const int t = g - ostart[b];
+  const int m = d.m;
+  const double *z = Z + d.z_off + (long long)t * m;
   double bz = 0.0;
   int bj = -1;
   for (int j = tid; j < m; j += blockDim.x) {
@@ -734,8 +889,8 @@ k_argmin(const double *__restrict__ V, const int *__restrict__ R, const double *
   __syncthreads();
   for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
     if (tid < s) {
-      int oj = sj[tid + s];
-      double oz = sz[tid + s];
+      const int oj = sj[tid + s];
+      const double oz = sz[tid + s];
       if (oj >= 0 && (sj[tid] < 0 || oz < sz[tid] || (oz == sz[tid] && oj < sj[tid]))) {
         sz[tid] = oz;
         sj[tid] = oj;
@@ -744,29 +899,28 @@ k_argmin(const double *__restrict__ V, const int *__restrict__ R, const double *
     __syncthreads();
   }
   const int js = sj[0];
-  const long long mm = (long long)m * m;
-  const long long src = t * mm + (long long)js * m;
+  const long long src = d.ws_off + ((long long)t * m + js) * m;
   for (int k = tid; k < m; k += blockDim.x) {
-    vout[(long long)t * m + k] = V[src + k];
-    if (rowout) rowout[(long long)t * m + k] = R[src + k];
-    if (zall) zall[(long long)t * m + k] = z[k];
+    d.Vout[(long long)t * m + k] = V[src + k];
+    if (d.ROWout) d.ROWout[(long long)t * m + k] = R[src + k];
+    if (d.ZALLout) d.ZALLout[(long long)t * m + k] = z[k];
   }
   if (tid == 0) {
-    jout[t] = js;
-    objout[t] = z[js];
+    d.Jout[t] = js;
+    d.OBJout[t] = z[js];
   }
-  if (t == 0 && status) {
+  if (t == 0 && d.status) {
     // condition bits; the status is the first that applies of: non-finite
     // input, too-wide column, selection bound, overflowed ratio
     int f = 0;
     for (int j = tid; j < m; j += blockDim.x) {
-      int cf = ci[j].flags;
+      const int cf = ci[d.col_off + j].flags;
       if (cf & COL_NONFINITE) f |= 1;
       if (cf & COL_WIDE) f |= 2;
-      if (segflags[j]) f |= 4;
+      if (segflags[d.col_off + j]) f |= 4;
     }
-    for (long long q = tid; q < (long long)L * m; q += blockDim.x)
-      if (zflag[q]) f |= 8;
+    for (long long q = tid; q < (long long)d.L * m; q += blockDim.x)
+      if (zflag[d.z_off + q]) f |= 8;
     sflag[tid] = f;
     __syncthreads();
     for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
@@ -774,9 +928,9 @@ k_argmin(const double *__restrict__ V, const int *__restrict__ R, const double *
       __syncthreads();
     }
     if (tid == 0) {
-      int b = sflag[0];
-      *status = (b & 1) ? L1LINE_ENONFINITE : (b & 2) ? L1LINE_EWIDE : (b & 4) ? L1LINE_EINTERNAL
-              : (b & 8) ? L1LINE_ERANGE : L1LINE_OK;
+      const int bb = sflag[0];
+      *d.status = (bb & 1) ? L1LINE_ENONFINITE : (bb & 2) ? L1LINE_EWIDE : (bb & 4) ? L1LINE_EINTERNAL
+                : (bb & 8) ? L1LINE_ERANGE : L1LINE_OK;
     }
   }
 }

@@ -1,32 +1,58 @@
 // l1line.hip -- C ABI (include/l1line.h) and host runtime of the gfx950
-// library: argument checks, the context workspace, kernel dispatch.
+// library: argument checks, the context workspace, batch layout (problem
+// descriptors and work items), kernel dispatch, captured launch graphs, the
+// autotuner and kernel timing.
 #include <hip/hip_runtime.h>
 
 #include <l1line.h>
 
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "fit_kernels.h"
 
+// ------------------------------------------------------------------- context
 struct ProfRec {
   const char *name;
   hipEvent_t start, stop;
 };
 
+struct TuneParams {
+  int blocks_per_cu;   // persistent workgroups per compute unit
+  int kchunk_min;      // fewest k per work item
+  int items_per_cu;    // target number of work items per compute unit
+};
+
 struct l1line_ctx_s {
   int device;
-  void *ws;          // device workspace, grown on demand
+  int num_cu;
+  void *ws;                 // device workspace, grown on demand
   size_t ws_bytes;
+  void *stage;              // pinned host staging of the batch layout
+  size_t stage_bytes;
+  hipEvent_t stage_done;    // the last copy out of `stage` has finished
+  bool stage_pending;
+  hipStream_t cap_stream;   // stream used to capture launch graphs
+  hipGraphExec_t graph;     // cached graph of the last captured batch layout
+  uint64_t graph_key;
+  TuneParams tune;
   bool profiling;
   std::vector<ProfRec> prof;
 };
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return L1LINE_EHIP;           \
+  } while (0)
 
 // Brackets one kernel launch with events when the context is profiling.
 struct ProfScope {
@@ -50,23 +76,26 @@ struct ProfScope {
   }
 };
 
-#define HIP_TRY(expr)                                   \
-  do {                                                  \
-    hipError_t e_ = (expr);                             \
-    if (e_ != hipSuccess) return L1LINE_EHIP;           \
-  } while (0)
-
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static void drop_graph(l1line_ctx ctx) {
+  if (ctx->graph) {
+    (void)hipGraphExecDestroy(ctx->graph);
+    ctx->graph = nullptr;
+  }
+  ctx->graph_key = 0;
+}
 
 static int ensure_ws(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
   if (bytes <= ctx->ws_bytes) return L1LINE_OK;
+  drop_graph(ctx);
   if (ctx->ws) {
     HIP_TRY(hipStreamSynchronize(stream));
     HIP_TRY(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
   }
-  size_t want = align_up(bytes + bytes / 8, 1 << 20);
+  const size_t want = align_up(bytes + bytes / 8, 1 << 20);
   if (hipMalloc(&ctx->ws, want) != hipSuccess) {
     ctx->ws = nullptr;
     (void)hipGetLastError();
@@ -76,6 +105,25 @@ static int ensure_ws(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
   return L1LINE_OK;
 }
 
+static int ensure_stage(l1line_ctx ctx, size_t bytes) {
+  if (ctx->stage_pending) {
+    HIP_TRY(hipEventSynchronize(ctx->stage_done));
+    ctx->stage_pending = false;
+  }
+  if (bytes <= ctx->stage_bytes) return L1LINE_OK;
+  if (ctx->stage) HIP_TRY(hipHostFree(ctx->stage));
+  ctx->stage = nullptr;
+  ctx->stage_bytes = 0;
+  const size_t want = align_up(bytes + bytes / 4, 1 << 16);
+  if (hipHostMalloc(&ctx->stage, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return L1LINE_ENOMEM;
+  }
+  ctx->stage_bytes = want;
+  return L1LINE_OK;
+}
+
+// ---------------------------------------------------------------- validation
 static int check_matrix(const double *X, int64_t n, int64_t m, int64_t ld) {
   if (!X || n < 1 || m < 1 || ld < n) return L1LINE_EINVAL;
   if (m > (1ll << 24) || ld > (1ll << 40)) return L1LINE_EINVAL;
@@ -90,97 +138,281 @@ static int check_lambdas(const double *lam, int64_t L) {
   return L1LINE_OK;
 }
 
-// Workspace layout of one fit / path call.
-struct FitWs {
-  ColInfo *ci;
-  double *V, *E, *Z;
-  int *R, *segflags, *zflag;
-  size_t bytes;
+static int check_problem(const l1line_problem &p) {
+  int st = check_matrix(p.X, p.n, p.m, p.ld);
+  if (st) return st;
+  st = check_lambdas(p.lambdas, p.L);
+  if (st) return st;
+  if (!p.V || !p.J || !p.OBJ) return L1LINE_EINVAL;
+  return L1LINE_OK;
+}
+
+// -------------------------------------------------------------- batch layout
+// Device workspace of one batch call:
+//   meta  (copied from the pinned staging buffer): ProbDesc[B], colstart,
+//         zstart, ostart (B+1 ints each), penalties, work items, counter
+//   data: ColInfo, segflags, V, E, R, Z, zflag
+struct BatchLayout {
+  int B, nitems, ksplit, nmax, Lmax;
+  long long total_cols, total_z, total_out, total_ws, total_lam;
+  size_t o_desc, o_colstart, o_zstart, o_ostart, o_lam, o_items, o_counter, meta_bytes;
+  size_t o_ci, o_segflags, o_V, o_E, o_R, o_Z, o_zflag, bytes;
 };
 
-static FitWs layout_fit(void *base, int64_t m, int64_t L) {
-  FitWs w;
+static void layout_sizes(BatchLayout &Ly) {
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b, 256); return o; };
-  size_t o_ci = take(sizeof(ColInfo) * m);
-  size_t o_v = take(sizeof(double) * L * m * m);
-  size_t o_e = take(sizeof(double) * L * m * m);
-  size_t o_r = take(sizeof(int) * L * m * m);
-  size_t o_z = take(sizeof(double) * L * m);
-  size_t o_sf = take(sizeof(int) * m);
-  size_t o_zf = take(sizeof(int) * L * m);
-  char *b = (char *)base;
-  w.ci = (ColInfo *)(b + o_ci);
-  w.V = (double *)(b + o_v);
-  w.E = (double *)(b + o_e);
-  w.R = (int *)(b + o_r);
-  w.Z = (double *)(b + o_z);
-  w.segflags = (int *)(b + o_sf);
-  w.zflag = (int *)(b + o_zf);
-  w.bytes = off;
-  return w;
+  Ly.o_desc = take(sizeof(ProbDesc) * Ly.B);
+  Ly.o_colstart = take(sizeof(int) * (Ly.B + 1));
+  Ly.o_zstart = take(sizeof(int) * (Ly.B + 1));
+  Ly.o_ostart = take(sizeof(int) * (Ly.B + 1));
+  Ly.o_lam = take(sizeof(double) * Ly.total_lam);
+  Ly.o_items = take(sizeof(WorkItem) * (Ly.ksplit ? 0 : Ly.nitems));
+  Ly.o_counter = take(sizeof(int) * 4);
+  Ly.meta_bytes = off;
+  Ly.o_ci = take(sizeof(ColInfo) * Ly.total_cols);
+  Ly.o_segflags = take(sizeof(int) * Ly.total_cols);
+  Ly.o_V = take(sizeof(double) * Ly.total_ws);
+  Ly.o_E = take(sizeof(double) * Ly.total_ws);
+  Ly.o_R = take(sizeof(int) * Ly.total_ws);
+  Ly.o_Z = take(sizeof(double) * Ly.total_z);
+  Ly.o_zflag = take(sizeof(int) * Ly.total_z);
+  Ly.bytes = off;
 }
 
 __global__ void k_fill_int(int *p, long long count, int value) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;
 }
 
-static int launch_seg(l1line_ctx ctx, const double *X, int n, int m, long long ld, const FitWs &w,
-                      const LamArgs &la, hipStream_t s) {
-  const size_t lds = seg_lds_bytes(n, la.L);
-  static bool attr_set = false;
-  if (!attr_set) {
-    HIP_TRY(hipFuncSetAttribute((const void *)k_fit_seg, hipFuncAttributeMaxDynamicSharedMemorySize,
+static uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
+  const unsigned char *p = (const unsigned char *)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static bool lds_attr_set = false;
+
+// Build the layout, stage the metadata, launch (or replay) the sequence.
+// `only_seg_ms` (autotuner): time the segment kernel alone.
+static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, hipStream_t s,
+                     const TuneParams &tp, float *only_seg_ms) {
+  BatchLayout Ly;
+  memset(&Ly, 0, sizeof Ly);
+  Ly.B = (int)B;
+  Ly.nmax = 1;
+  Ly.Lmax = 1;
+  double total_cost = 0.0;
+  for (int64_t b = 0; b < B; ++b) {
+    const l1line_problem &p = probs[b];
+    Ly.total_cols += p.m;
+    Ly.total_z += p.L * p.m;
+    Ly.total_out += p.L;
+    Ly.total_ws += p.L * p.m * p.m;
+    Ly.total_lam += p.L;
+    Ly.nmax = std::max<int>(Ly.nmax, (int)p.n);
+    Ly.Lmax = std::max<int>(Ly.Lmax, (int)p.L);
+    total_cost += (double)p.n * (double)p.m * (double)p.m;
+  }
+  if (Ly.total_cols > (1ll << 30) || Ly.total_z > (1ll << 30) || Ly.total_out > (1ll << 30))
+    return L1LINE_EINVAL;
+
+  // work items: split every problem's k range so the whole batch offers
+  // about items_per_cu items per compute unit, each with >= kchunk_min k
+  std::vector<WorkItem> items;
+  const double target = (double)tp.items_per_cu * ctx->num_cu;
+  if (B == 1) {
+    const int m = (int)probs[0].m;
+    int ksplit = (int)ceil(target / m);
+    const int kmax = std::max(1, m / tp.kchunk_min);
+    ksplit = std::max(1, std::min(ksplit, kmax));
+    Ly.ksplit = ksplit;
+    Ly.nitems = m * ksplit;
+  } else {
+    for (int64_t b = 0; b < B; ++b) {
+      const int m = (int)probs[b].m;
+      const double share = target * ((double)probs[b].n * m * m) / total_cost;
+      int ksplit = (int)ceil(share / m);
+      const int kmax = std::max(1, m / tp.kchunk_min);
+      ksplit = std::max(1, std::min(ksplit, kmax));
+      const int kchunk = (m + ksplit - 1) / ksplit;
+      for (int j = 0; j < m; ++j)
+        for (int k0 = 0; k0 < m; k0 += kchunk) items.push_back(WorkItem{(int)b, j, k0, std::min(m, k0 + kchunk)});
+    }
+    // longest first: dynamic pulling then approximates LPT scheduling
+    std::stable_sort(items.begin(), items.end(), [&](const WorkItem &x, const WorkItem &y) {
+      const double cx = (double)probs[x.b].n * (x.kend - x.kbeg), cy = (double)probs[y.b].n * (y.kend - y.kbeg);
+      return cx > cy;
+    });
+    Ly.ksplit = 0;
+    Ly.nitems = (int)items.size();
+  }
+  layout_sizes(Ly);
+  int st = ensure_ws(ctx, Ly.bytes, s);
+  if (st) return st;
+  st = ensure_stage(ctx, Ly.meta_bytes);
+  if (st) return st;
+
+  // metadata into the pinned staging buffer
+  char *h = (char *)ctx->stage;
+  char *d = (char *)ctx->ws;
+  memset(h, 0, Ly.meta_bytes);
+  ProbDesc *hd = (ProbDesc *)(h + Ly.o_desc);
+  int *hcol = (int *)(h + Ly.o_colstart), *hz = (int *)(h + Ly.o_zstart), *ho = (int *)(h + Ly.o_ostart);
+  double *hlam = (double *)(h + Ly.o_lam);
+  long long col = 0, z = 0, out = 0, wsoff = 0, lamoff = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    const l1line_problem &p = probs[b];
+    ProbDesc &q = hd[b];
+    q.X = p.X;
+    q.ld = p.ld;
+    q.n = (int)p.n;
+    q.m = (int)p.m;
+    q.L = (int)p.L;
+    q.lam_off = (int)lamoff;
+    q.col_off = (int)col;
+    q.out_off = (int)out;
+    q.ws_off = wsoff;
+    q.z_off = z;
+    q.Vout = p.V;
+    q.Jout = (long long *)p.J;
+    q.OBJout = p.OBJ;
+    q.ROWout = p.ROW;
+    q.ZALLout = p.ZALL;
+    q.status = p.status;
+    hcol[b] = (int)col;
+    hz[b] = (int)z;
+    ho[b] = (int)out;
+    for (int64_t t = 0; t < p.L; ++t) hlam[lamoff + t] = p.lambdas[t];
+    col += p.m;
+    z += p.L * p.m;
+    out += p.L;
+    wsoff += p.L * p.m * p.m;
+    lamoff += p.L;
+  }
+  hcol[B] = (int)col;
+  hz[B] = (int)z;
+  ho[B] = (int)out;
+  if (!items.empty()) memcpy(h + Ly.o_items, items.data(), sizeof(WorkItem) * items.size());
+
+  const ProbDesc *dP = (const ProbDesc *)(d + Ly.o_desc);
+  const int *dcol = (const int *)(d + Ly.o_colstart), *dz = (const int *)(d + Ly.o_zstart),
+            *dout = (const int *)(d + Ly.o_ostart);
+  const double *dlam = (const double *)(d + Ly.o_lam);
+  const WorkItem *ditems = Ly.ksplit ? nullptr : (const WorkItem *)(d + Ly.o_items);
+  int *dcounter = (int *)(d + Ly.o_counter);
+  ColInfo *dci = (ColInfo *)(d + Ly.o_ci);
+  int *dsegflags = (int *)(d + Ly.o_segflags);
+  double *dV = (double *)(d + Ly.o_V), *dE = (double *)(d + Ly.o_E), *dZ = (double *)(d + Ly.o_Z);
+  int *dR = (int *)(d + Ly.o_R), *dzflag = (int *)(d + Ly.o_zflag);
+
+  uint64_t key = fnv1a(h, Ly.meta_bytes, 1469598103934665603ull);
+  key = fnv1a(&tp, sizeof tp, key);
+  key = fnv1a(&ctx->ws, sizeof ctx->ws, key);
+  const bool use_graph = (flags & L1LINE_BATCH_GRAPH) && !ctx->profiling && !only_seg_ms;
+  if (use_graph && ctx->graph && ctx->graph_key == key) {
+    // the device metadata of this layout is still in place: replay
+    HIP_TRY(hipGraphLaunch(ctx->graph, s));
+    return L1LINE_OK;
+  }
+  drop_graph(ctx);
+  HIP_TRY(hipMemcpyAsync(d, h, Ly.meta_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ctx->stage_done, s));
+  ctx->stage_pending = true;
+
+  const size_t lds = seg_lds_bytes(Ly.nmax, Ly.Lmax);
+  if (!lds_attr_set) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS)));
-    attr_set = true;
+    lds_attr_set = true;
   }
-  // enough workgroups to fill the chip several times over (and to even out
-  // the uneven cost of the segments), at least 8 k per workgroup
-  int ksplit = (6144 + m - 1) / m;
-  ksplit = ksplit < 1 ? 1 : ksplit;
-  const int kmax = m / 8 > 1 ? m / 8 : 1;
-  ksplit = ksplit > kmax ? kmax : ksplit;
+  const int grid_seg = std::max(1, std::min(Ly.nitems, tp.blocks_per_cu * ctx->num_cu));
+
+  hipStream_t ls = s;
+  if (use_graph) {
+    // the metadata copy above must land before the captured kernels run on
+    // the capture stream's replay (replays go to `s`, after the copy)
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ls = ctx->cap_stream;
+  }
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   {
-    ProfScope ps(ctx, s, "fit_seg");
-    hipLaunchKernelGGL(k_fit_seg, dim3((unsigned)(m * ksplit)), dim3(64 * SEG_WAVES), lds, s, X, n, m, ld,
-                       w.ci, la, ksplit, w.V, w.E, w.R, w.segflags);
+    ProfScope ps(ctx, ls, "colprep");
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 4ll, 0);
+    hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
+                       (int)B, (int)Ly.total_cols, dci, dsegflags);
   }
-  HIP_TRY(hipGetLastError());
+  if (only_seg_ms) {
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, ls));
+  }
+  {
+    ProfScope ps(ctx, ls, "fit_seg");
+    hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
+                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dV, dE, dR, dsegflags);
+  }
+  if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
+  {
+    ProfScope ps(ctx, ls, "reduce");
+    hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)Ly.total_z), dim3(64), 0, ls, dP, dz, (int)B, dlam, dV, dE,
+                       dZ, dzflag);
+  }
+  {
+    ProfScope ps(ctx, ls, "argmin");
+    hipLaunchKernelGGL(k_argmin_batch, dim3((unsigned)Ly.total_out), dim3(256), 0, ls, dP, dout, (int)B, dV, dR,
+                       dZ, dzflag, dci, dsegflags);
+  }
+  const hipError_t le = hipGetLastError();
+  if (use_graph) {
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return L1LINE_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return L1LINE_EHIP;
+    ctx->graph = ex;
+    ctx->graph_key = key;
+    HIP_TRY(hipGraphLaunch(ctx->graph, s));
+    return L1LINE_OK;
+  }
+  if (le != hipSuccess) return L1LINE_EHIP;
+  if (only_seg_ms) {
+    HIP_TRY(hipEventSynchronize(t1));
+    HIP_TRY(hipEventElapsedTime(only_seg_ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+  }
   return L1LINE_OK;
 }
 
-static int run_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const LamArgs &la,
-                    double *V, int64_t *J, double *OBJ, int32_t *ROW, double *ZALL, int32_t *status,
-                    hipStream_t s) {
-  const int64_t L = la.L;
-  FitWs probe = layout_fit(nullptr, m, L);
-  int st = ensure_ws(ctx, probe.bytes, s);
-  if (st) return st;
-  FitWs w = layout_fit(ctx->ws, m, L);
-  {
-    ProfScope ps(ctx, s, "colprep");
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, w.segflags,
-                       (long long)m, 0);
-    hipLaunchKernelGGL(k_colprep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, X, (int)n, (int)m,
-                       (long long)ld, w.ci);
-  }
-  HIP_TRY(hipGetLastError());
-  st = launch_seg(ctx, X, (int)n, (int)m, (long long)ld, w, la, s);
-  if (st) return st;
-  {
-    ProfScope ps(ctx, s, "reduce");
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)m, (unsigned)L), dim3(64), 0, s, w.V, w.E, (int)m, la, w.Z,
-                       w.zflag);
-  }
-  {
-    ProfScope ps(ctx, s, "argmin");
-    hipLaunchKernelGGL(k_argmin, dim3((unsigned)L), dim3(256), 0, s, w.V, w.R, w.Z, w.zflag, w.ci,
-                       w.segflags, (int)m, (int)L, V, J, OBJ, ROW, ZALL, status);
-  }
-  HIP_TRY(hipGetLastError());
-  return L1LINE_OK;
+static l1line_problem single(const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas, int64_t L,
+                             double *V, int64_t *J, double *OBJ, int32_t *ROW, double *ZALL, int32_t *status) {
+  l1line_problem p;
+  p.X = X;
+  p.n = n;
+  p.m = m;
+  p.ld = ld;
+  p.lambdas = lambdas;
+  p.L = L;
+  p.V = V;
+  p.J = J;
+  p.OBJ = OBJ;
+  p.ROW = ROW;
+  p.ZALL = ZALL;
+  p.status = status;
+  return p;
 }
+
+static const TuneParams kDefaultTune = {3, 8, 24};
 
 extern "C" {
 
@@ -191,12 +423,26 @@ int l1line_create(l1line_ctx *ctx, int device) {
   if (hipGetDeviceCount(&count) != hipSuccess) return L1LINE_EHIP;
   if (device < 0 || device >= count) return L1LINE_EINVAL;
   HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
   l1line_ctx c = new (std::nothrow) l1line_ctx_s();
   if (!c) return L1LINE_ENOMEM;
   c->device = device;
+  c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->ws = nullptr;
   c->ws_bytes = 0;
+  c->stage = nullptr;
+  c->stage_bytes = 0;
+  c->stage_pending = false;
+  c->graph = nullptr;
+  c->graph_key = 0;
+  c->tune = kDefaultTune;
   c->profiling = false;
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return L1LINE_EHIP;
+  }
   *ctx = c;
   return L1LINE_OK;
 }
@@ -214,7 +460,11 @@ int l1line_destroy(l1line_ctx ctx) {
   int st = L1LINE_OK;
   if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) st = L1LINE_EHIP;
   prof_clear(ctx);
+  drop_graph(ctx);
   if (ctx->ws && hipFree(ctx->ws) != hipSuccess) st = L1LINE_EHIP;
+  if (ctx->stage && hipHostFree(ctx->stage) != hipSuccess) st = L1LINE_EHIP;
+  (void)hipEventDestroy(ctx->stage_done);
+  (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return st;
 }
@@ -282,11 +532,8 @@ int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld
   st = check_lambdas(&lambda, 1);
   if (st) return st;
   HIP_TRY(hipSetDevice(ctx->device));
-  LamArgs la;
-  memset(&la, 0, sizeof la);
-  la.L = 1;
-  la.lam[0] = lambda;
-  return run_path(ctx, X, n, m, ld, la, v, j, obj, median_row, z_all, status, (hipStream_t)stream);
+  const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, z_all, status);
+  return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, ctx->tune, nullptr);
 }
 
 int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas,
@@ -298,11 +545,78 @@ int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64
   st = check_lambdas(lambdas, L);
   if (st) return st;
   HIP_TRY(hipSetDevice(ctx->device));
-  LamArgs la;
-  memset(&la, 0, sizeof la);
-  la.L = (int)L;
-  for (int64_t t = 0; t < L; ++t) la.lam[t] = lambdas[t];
-  return run_path(ctx, X, n, m, ld, la, V, J, OBJ, ROW, ZALL, status, (hipStream_t)stream);
+  const l1line_problem p = single(X, n, m, ld, lambdas, L, V, J, OBJ, ROW, ZALL, status);
+  return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, ctx->tune, nullptr);
+}
+
+int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, void *stream) {
+  if (!ctx || !probs || B < 1 || B > (1 << 20)) return L1LINE_EINVAL;
+  if (flags & ~L1LINE_BATCH_GRAPH) return L1LINE_EINVAL;
+  for (int64_t b = 0; b < B; ++b) {
+    const int st = check_problem(probs[b]);
+    if (st) return st;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  return run_batch(ctx, probs, B, flags, (hipStream_t)stream, ctx->tune, nullptr);
+}
+
+int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B, void *stream, int32_t *params_out) {
+  if (!ctx || !probs || B < 1 || B > (1 << 20)) return L1LINE_EINVAL;
+  for (int64_t b = 0; b < B; ++b) {
+    const int st = check_problem(probs[b]);
+    if (st) return st;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const bool was_profiling = ctx->profiling;
+  ctx->profiling = false;
+  TuneParams best = ctx->tune;
+  float best_ms = 1e30f;
+  const int bpc[] = {2, 3, 4};
+  const int kmin[] = {8, 32, 128};
+  const int ipc[] = {12, 24, 48};
+  for (int a : bpc)
+    for (int k : kmin)
+      for (int i : ipc) {
+        const TuneParams tp{a, k, i};
+        float ms = 0.f;
+        const int st = run_batch(ctx, probs, B, 0, s, tp, &ms);
+        if (st) {
+          ctx->profiling = was_profiling;
+          return st;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = tp;
+        }
+      }
+  ctx->tune = best;
+  ctx->profiling = was_profiling;
+  drop_graph(ctx);
+  if (params_out) {
+    params_out[0] = best.blocks_per_cu;
+    params_out[1] = best.kchunk_min;
+    params_out[2] = best.items_per_cu;
+  }
+  return L1LINE_OK;
+}
+
+int l1line_tune_set(l1line_ctx ctx, const int32_t *params) {
+  if (!ctx || !params) return L1LINE_EINVAL;
+  if (params[0] < 1 || params[0] > 16 || params[1] < 1 || params[1] > (1 << 20) || params[2] < 1 ||
+      params[2] > 4096)
+    return L1LINE_EINVAL;
+  ctx->tune = TuneParams{params[0], params[1], params[2]};
+  drop_graph(ctx);
+  return L1LINE_OK;
+}
+
+int l1line_tune_get(l1line_ctx ctx, int32_t *params) {
+  if (!ctx || !params) return L1LINE_EINVAL;
+  params[0] = ctx->tune.blocks_per_cu;
+  params[1] = ctx->tune.kchunk_min;
+  params[2] = ctx->tune.items_per_cu;
+  return L1LINE_OK;
 }
 
 }  // extern "C"

@@ -105,3 +105,27 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         B.lib()
+
+
+def test_batch_host_argument_checks():
+    lib = B.lib()
+    f = _Fake()
+    P = ctypes.c_void_p
+    lam = np.array([0.5, 1.0])
+    good = B.Problem(1, 10, 4, 10, lam.ctypes.data, 2, 1, 1, 1, None, None, None)
+    arr = (B.Problem * 2)(good, good)
+    cast = ctypes.cast(arr, P)
+    assert lib.l1line_fit_batch(f.h, cast, 0, 0, None) == B.EINVAL        # B < 1
+    assert lib.l1line_fit_batch(f.h, None, 2, 0, None) == B.EINVAL        # null array
+    assert lib.l1line_fit_batch(f.h, cast, 2, 4, None) == B.EINVAL        # unknown flag
+    assert lib.l1line_fit_batch(None, cast, 2, 0, None) == B.EINVAL
+    bad = (B.Problem * 2)(good, B.Problem(1, 0, 4, 10, lam.ctypes.data, 2, 1, 1, 1, None, None, None))
+    assert lib.l1line_fit_batch(f.h, ctypes.cast(bad, P), 2, 0, None) == B.EINVAL   # n < 1
+    neg = np.array([0.5, -1.0])
+    bad2 = (B.Problem * 1)(B.Problem(1, 10, 4, 10, neg.ctypes.data, 2, 1, 1, 1, None, None, None))
+    assert lib.l1line_fit_batch(f.h, ctypes.cast(bad2, P), 1, 0, None) == B.EINVAL
+    big = (B.Problem * 1)(B.Problem(1, B.MAX_N + 1, 4, B.MAX_N + 1, lam.ctypes.data, 2, 1, 1, 1, None, None, None))
+    assert lib.l1line_fit_batch(f.h, ctypes.cast(big, P), 1, 0, None) == B.ESIZE
+    assert lib.l1line_autotune(f.h, cast, 0, None, None) == B.EINVAL
+    assert lib.l1line_tune_get(None, None) == B.EINVAL
+    assert lib.l1line_tune_set(None, None) == B.EINVAL

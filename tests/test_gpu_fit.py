@@ -85,7 +85,8 @@ def test_small_fit_workload(ctx, seed):
 
 
 SHAPES = [(1, 1), (1, 5), (5, 1), (7, 3), (63, 4), (64, 5), (65, 6), (127, 9), (128, 3), (129, 17),
-          (200, 20), (333, 33), (640, 7), (1000, 12), (2049, 5), (4096, 3)]
+          (200, 20), (333, 33), (640, 7), (1000, 12), (2049, 5), (4096, 3), (4097, 3), (10000, 4),
+          (16384, 3)]
 
 
 @pytest.mark.parametrize("n,m", SHAPES)
