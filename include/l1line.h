@@ -165,6 +165,66 @@ int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
 int l1line_tune_get(l1line_ctx ctx, int32_t *params);
 int l1line_tune_set(l1line_ctx ctx, const int32_t *params);
 
+/* ------------------------------------------------------------------------
+ * Learned candidate ranker.  Exhaustive search solves every preserved
+ * coordinate j (Algorithm 1); the ranker scores the columns with a small MLP
+ * and solves only the K best exactly, falling back to the exhaustive search
+ * when the scores do not separate the candidates from the rest.
+ * ---------------------------------------------------------------------- */
+#define L1LINE_FEATURES 32        /* features per column                     */
+#define L1LINE_MLP_PARAMS 20865   /* FP32 parameters of the 32-128-128-1 MLP:
+                                     W1[32][128], b1[128], W2[128][128],
+                                     b2[128], W3[128], b3 (in this order)     */
+
+/* Per-column features F [m][32] (FP32, DEVICE).  Three exact "sketch" fits
+ * of Algorithm 1 on 64, 128 and 256 evenly spaced rows (penalty scaled by
+ * rows/n) give z~_j; with min / mean / std over j of each sketch:
+ *   f0-2   (z~ - min) / (mean - min)          f3-5  log1p(z~ / min - 1)
+ *   f6-8   (z~ - mean) / std                  f9    log(W_j / mean_j W_j)
+ *   f10    zero fraction of column j          f11   min(lambda / W_j, 10)
+ *   f12    log1p(lambda / W_j)                f13   mean of f0-2
+ *   f14    max - min of f0-2                  f15   1;  f16-31 = 0
+ * (W_j = column l1 mass). */
+int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n,
+                           int64_t m, int64_t ld, double lambda, float *F,
+                           void *stream);
+
+/* MLP forward: out[r] = MLP(F[r]) for N rows (all DEVICE).  Matrix products
+ * take BF16 operands (features, weights, hidden activations rounded to
+ * nearest-even BF16) on the MFMA units with FP32 accumulation:
+ *   H1 = bf16(relu(F W1 + b1)), H2 = bf16(relu(H1 W2 + b2)),
+ *   out = H2 . bf16(W3) + b3. */
+int l1line_mlp_forward(l1line_ctx ctx, const float *params, const float *F,
+                       int64_t N, float *out, void *stream);
+
+/* Gradient of the loss mean_r (out[r] - y[r])^2 with respect to the
+ * parameters (grad [L1LINE_MLP_PARAMS], loss [1], DEVICE).  Deterministic:
+ * per-tile partials are added in a fixed order. */
+int l1line_mlp_grad(l1line_ctx ctx, const float *params, const float *F,
+                    const float *y, int64_t N, float *grad, float *loss,
+                    void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * on the FP32 master parameters with moments m1, m2 (all DEVICE). */
+int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2,
+                    const float *grad, int64_t step, float lr, void *stream);
+
+/* Ranked fit: features, MLP scores (lower = better candidate), the K best
+ * columns solved exactly; if the score gap between the best column and the
+ * first one left out is below margin_threshold (or K = m) the exhaustive
+ * search runs instead (decided on the device, no host synchronisation).
+ *   v, j, obj, median_row, status  as l1line_fit (DEVICE)
+ *   used_fallback  [1] 1 when the exhaustive search ran (DEVICE, nullable)
+ *   scores         [m] the MLP scores (DEVICE, nullable)
+ * Host errors: as l1line_fit, and EINVAL for K outside [1, m] or a negative
+ * or non-finite threshold. */
+int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                      int64_t ld, double lambda, const float *params,
+                      int32_t K, float margin_threshold, double *v,
+                      int64_t *j, double *obj, int32_t *median_row,
+                      int32_t *used_fallback, float *scores, int32_t *status,
+                      void *stream);
+
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.
  * l1line_profile_read waits for the recorded events, returns the summed

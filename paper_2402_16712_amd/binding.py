@@ -20,8 +20,11 @@ MAX_LAMBDAS = 128
 
 EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_column_stats",
            "l1line_fit", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
-           "l1line_tune_set", "l1line_profile", "l1line_profile_read"]
+           "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
+           "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked"]
 BATCH_GRAPH = 1
+FEATURES = 32
+MLP_PARAMS = 20865
 
 
 class Problem(ctypes.Structure):
@@ -61,12 +64,19 @@ def lib() -> ctypes.CDLL:
         L.l1line_autotune.argtypes = [P, P, I64, P, P]
         L.l1line_tune_get.argtypes = [P, P]
         L.l1line_tune_set.argtypes = [P, P]
+        F32 = ctypes.c_float
+        L.l1line_ranker_features.argtypes = [P, P, I64, I64, I64, D, P, P]
+        L.l1line_mlp_forward.argtypes = [P, P, P, I64, P, P]
+        L.l1line_mlp_grad.argtypes = [P, P, P, P, I64, P, P, P]
+        L.l1line_mlp_adam.argtypes = [P, P, P, P, P, I64, F32, P]
+        L.l1line_fit_ranked.argtypes = [P, P, I64, I64, I64, D, P, I32, F32, P, P, P, P, P, P, P, P]
         L.l1line_profile.argtypes = [P, I32]
         L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),
                                           ctypes.POINTER(I64), I32]
         for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit",
                   "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
-                  "l1line_tune_set", "l1line_profile", "l1line_profile_read"):
+                  "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
+                  "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -251,3 +261,64 @@ class Context:
     def tune_set(self, params):
         arr = (ctypes.c_int32 * 3)(*[int(x) for x in params])
         _check(lib().l1line_tune_set(self._h, arr), "l1line_tune_set")
+
+    # -------------------------------------------------------------- ranker
+    def features(self, X, lam: float):
+        """[m, 32] FP32 per-column features (device)."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        F = self._empty((m, FEATURES), torch.float32)
+        _check(lib().l1line_ranker_features(self._h, _ptr(X), n, m, ld, float(lam), _ptr(F),
+                                            self._stream()), "l1line_ranker_features")
+        return F
+
+    @staticmethod
+    def _f32(t, shape=None):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or \
+                not t.is_contiguous():
+            raise TypeError("expected a contiguous float32 CUDA tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return t
+
+    def mlp_forward(self, params, F):
+        torch = _torch()
+        self._f32(params, (MLP_PARAMS,))
+        self._f32(F)
+        N = F.shape[0]
+        out = self._empty((N,), torch.float32)
+        _check(lib().l1line_mlp_forward(self._h, _ptr(params), _ptr(F), N, _ptr(out), self._stream()),
+               "l1line_mlp_forward")
+        return out
+
+    def mlp_grad(self, params, F, y):
+        torch = _torch()
+        self._f32(params, (MLP_PARAMS,))
+        self._f32(F)
+        self._f32(y, (F.shape[0],))
+        grad = self._empty((MLP_PARAMS,), torch.float32)
+        loss = self._empty((1,), torch.float32)
+        _check(lib().l1line_mlp_grad(self._h, _ptr(params), _ptr(F), _ptr(y), F.shape[0], _ptr(grad),
+                                     _ptr(loss), self._stream()), "l1line_mlp_grad")
+        return grad, loss
+
+    def mlp_adam(self, params, m1, m2, grad, step: int, lr: float):
+        for t in (params, m1, m2, grad):
+            self._f32(t, (MLP_PARAMS,))
+        _check(lib().l1line_mlp_adam(self._h, _ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), int(step),
+                                     float(lr), self._stream()), "l1line_mlp_adam")
+
+    def fit_ranked(self, X, lam: float, params, K: int = 32, margin: float = 0.05):
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        self._f32(params, (MLP_PARAMS,))
+        out = dict(v=self._empty((m,), torch.float64), j=self._empty((1,), torch.int64),
+                   obj=self._empty((1,), torch.float64), row=self._empty((m,), torch.int32),
+                   used_fallback=self._empty((1,), torch.int32),
+                   scores=self._empty((m,), torch.float32), status=self._empty((1,), torch.int32))
+        _check(lib().l1line_fit_ranked(self._h, _ptr(X), n, m, ld, float(lam), _ptr(params), int(K),
+                                       float(margin), _ptr(out["v"]), _ptr(out["j"]), _ptr(out["obj"]),
+                                       _ptr(out["row"]), _ptr(out["used_fallback"]), _ptr(out["scores"]),
+                                       _ptr(out["status"]), self._stream()), "l1line_fit_ranked")
+        return out

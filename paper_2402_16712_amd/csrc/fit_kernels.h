@@ -130,9 +130,10 @@ k_colprep(const double *__restrict__ X, int n, int m, long long ld, ColInfo *__r
 // every column of every problem: colstart[b] = first column of problem b
 __global__ void __launch_bounds__(256)
 k_colprep_batch(const ProbDesc *__restrict__ P, const int *__restrict__ colstart, int B, int total_cols,
-                ColInfo *__restrict__ ci, int *__restrict__ segflags) {
+                ColInfo *__restrict__ ci, int *__restrict__ segflags, const int *__restrict__ gate, int gate_on) {
   const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (g >= total_cols) return;
+  if (gate && *gate != gate_on) return;
   const int b = find_owner(colstart, B, g);
   const ProbDesc d = P[b];
   const int col = g - colstart[b];
@@ -796,12 +797,17 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 // counter until none is left (items are ordered by decreasing cost).  With
 // items == nullptr the items of problem 0 are implicit: item q covers
 // j = q / ksplit and the (q mod ksplit)-th of ksplit equal k ranges.
+// cand (optional): the preserved columns of the implicit items (item q has
+// j = cand[q / ksplit]); gate (optional): the kernel does nothing unless
+// *gate == gate_on.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int ksplit,
             int *__restrict__ counter, const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
-            double *__restrict__ V, double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags) {
+            double *__restrict__ V, double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
+            const int *__restrict__ cand, const int *__restrict__ gate, int gate_on) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_item;
+  if (gate && *gate != gate_on) return;
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
@@ -815,7 +821,7 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
       const int m0 = P[0].m;
       const int kchunk = (m0 + ksplit - 1) / ksplit;
       it.b = 0;
-      it.j = q / ksplit;
+      it.j = cand ? cand[q / ksplit] : q / ksplit;
       it.kbeg = (q % ksplit) * kchunk;
       it.kend = min(m0, it.kbeg + kchunk);
     }
@@ -832,13 +838,23 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
 __global__ void __launch_bounds__(64)
 k_reduce_batch(const ProbDesc *__restrict__ P, const int *__restrict__ zstart, int B,
                const double *__restrict__ lam_all, const double *__restrict__ V, const double *__restrict__ E,
-               double *__restrict__ Z, int *__restrict__ zflag) {
+               double *__restrict__ Z, int *__restrict__ zflag, const int *__restrict__ jmask,
+               const int *__restrict__ gate, int gate_on) {
+  if (gate && *gate != gate_on) return;
   const long long g = blockIdx.x;
   const int lane = threadIdx.x;
   const int b = find_owner(zstart, B, g);
   const ProbDesc d = P[b];
   const int local = (int)(g - zstart[b]);
   const int t = local / d.m, j = local % d.m;
+  if (jmask && !jmask[j]) {
+    // not a candidate (problem 0 only): never the argmin
+    if (lane == 0) {
+      Z[d.z_off + (long long)t * d.m + j] = __longlong_as_double(0x7ff0000000000000ll);
+      zflag[d.z_off + (long long)t * d.m + j] = 0;
+    }
+    return;
+  }
   const long long off = d.ws_off + ((long long)t * d.m + j) * d.m;
   double pe = 0.0, pv = 0.0;
   int bad = 0;
@@ -867,10 +883,12 @@ k_reduce_batch(const ProbDesc *__restrict__ P, const int *__restrict__ zstart, i
 __global__ void __launch_bounds__(256)
 k_argmin_batch(const ProbDesc *__restrict__ P, const int *__restrict__ ostart, int B,
                const double *__restrict__ V, const int *__restrict__ R, const double *__restrict__ Z,
-               const int *__restrict__ zflag, const ColInfo *__restrict__ ci, const int *__restrict__ segflags) {
+               const int *__restrict__ zflag, const ColInfo *__restrict__ ci, const int *__restrict__ segflags,
+               const int *__restrict__ jmask, const int *__restrict__ gate, int gate_on) {
   __shared__ double sz[256];
   __shared__ int sj[256];
   __shared__ int sflag[256];
+  if (gate && *gate != gate_on) return;
   const int g = blockIdx.x, tid = threadIdx.x;
   const int b = find_owner(ostart, B, g);
   const ProbDesc d = P[b];
@@ -917,7 +935,7 @@ k_argmin_batch(const ProbDesc *__restrict__ P, const int *__restrict__ ostart, i
       const int cf = ci[d.col_off + j].flags;
       if (cf & COL_NONFINITE) f |= 1;
       if (cf & COL_WIDE) f |= 2;
-      if (segflags[d.col_off + j]) f |= 4;
+      if (segflags[d.col_off + j] && (!jmask || jmask[j])) f |= 4;
     }
     for (long long q = tid; q < (long long)d.L * m; q += blockDim.x)
       if (zflag[d.z_off + q]) f |= 8;

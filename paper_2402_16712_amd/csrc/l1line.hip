@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "fit_kernels.h"
+#include "ranker_kernels.h"
 
 // ------------------------------------------------------------------- context
 struct ProfRec {
@@ -46,6 +47,8 @@ struct l1line_ctx_s {
   TuneParams tune;
   bool profiling;
   std::vector<ProfRec> prof;
+  void *rk;                 // ranker scratch (features, sketches, MLP buffers)
+  size_t rk_bytes;
 };
 
 #define HIP_TRY(expr)                                   \
@@ -102,6 +105,23 @@ static int ensure_ws(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
     return L1LINE_ENOMEM;
   }
   ctx->ws_bytes = want;
+  return L1LINE_OK;
+}
+
+static int ensure_rk(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
+  if (bytes <= ctx->rk_bytes) return L1LINE_OK;
+  if (ctx->rk) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipFree(ctx->rk));
+    ctx->rk = nullptr;
+    ctx->rk_bytes = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 8, 1 << 20);
+  if (hipMalloc(&ctx->rk, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return L1LINE_ENOMEM;
+  }
+  ctx->rk_bytes = want;
   return L1LINE_OK;
 }
 
@@ -196,10 +216,22 @@ static uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
 
 static bool lds_attr_set = false;
 
+// Optional restrictions of a one-problem run (device pointers): cand / ncand
+// restrict the preserved columns to a list, jmask marks them for the
+// reduction, gate / gate_on make every kernel a no-op unless *gate == gate_on.
+struct RunOpts {
+  const int *cand;
+  int ncand;
+  const int *jmask;
+  const int *gate;
+  int gate_on;
+};
+static const RunOpts kNoOpts = {nullptr, 0, nullptr, nullptr, 0};
+
 // Build the layout, stage the metadata, launch (or replay) the sequence.
 // `only_seg_ms` (autotuner): time the segment kernel alone.
 static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, hipStream_t s,
-                     const TuneParams &tp, float *only_seg_ms) {
+                     const TuneParams &tp, float *only_seg_ms, const RunOpts &ro = kNoOpts) {
   BatchLayout Ly;
   memset(&Ly, 0, sizeof Ly);
   Ly.B = (int)B;
@@ -230,7 +262,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     const int kmax = std::max(1, m / tp.kchunk_min);
     ksplit = std::max(1, std::min(ksplit, kmax));
     Ly.ksplit = ksplit;
-    Ly.nitems = m * ksplit;
+    Ly.nitems = (ro.cand ? ro.ncand : m) * ksplit;
   } else {
     for (int64_t b = 0; b < B; ++b) {
       const int m = (int)probs[b].m;
@@ -312,6 +344,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   uint64_t key = fnv1a(h, Ly.meta_bytes, 1469598103934665603ull);
   key = fnv1a(&tp, sizeof tp, key);
   key = fnv1a(&ctx->ws, sizeof ctx->ws, key);
+  key = fnv1a(&ro, sizeof ro, key);
   const bool use_graph = (flags & L1LINE_BATCH_GRAPH) && !ctx->profiling && !only_seg_ms;
   if (use_graph && ctx->graph && ctx->graph_key == key) {
     // the device metadata of this layout is still in place: replay
@@ -344,7 +377,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     ProfScope ps(ctx, ls, "colprep");
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 4ll, 0);
     hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
-                       (int)B, (int)Ly.total_cols, dci, dsegflags);
+                       (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
   }
   if (only_seg_ms) {
     HIP_TRY(hipEventCreate(&t0));
@@ -354,18 +387,19 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   {
     ProfScope ps(ctx, ls, "fit_seg");
     hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
-                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dV, dE, dR, dsegflags);
+                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dV, dE, dR, dsegflags, ro.cand, ro.gate,
+                       ro.gate_on);
   }
   if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
   {
     ProfScope ps(ctx, ls, "reduce");
     hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)Ly.total_z), dim3(64), 0, ls, dP, dz, (int)B, dlam, dV, dE,
-                       dZ, dzflag);
+                       dZ, dzflag, ro.jmask, ro.gate, ro.gate_on);
   }
   {
     ProfScope ps(ctx, ls, "argmin");
     hipLaunchKernelGGL(k_argmin_batch, dim3((unsigned)Ly.total_out), dim3(256), 0, ls, dP, dout, (int)B, dV, dR,
-                       dZ, dzflag, dci, dsegflags);
+                       dZ, dzflag, dci, dsegflags, ro.jmask, ro.gate, ro.gate_on);
   }
   const hipError_t le = hipGetLastError();
   if (use_graph) {
@@ -438,6 +472,8 @@ int l1line_create(l1line_ctx *ctx, int device) {
   c->graph_key = 0;
   c->tune = kDefaultTune;
   c->profiling = false;
+  c->rk = nullptr;
+  c->rk_bytes = 0;
   if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
@@ -463,6 +499,7 @@ int l1line_destroy(l1line_ctx ctx) {
   drop_graph(ctx);
   if (ctx->ws && hipFree(ctx->ws) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->stage && hipHostFree(ctx->stage) != hipSuccess) st = L1LINE_EHIP;
+  if (ctx->rk && hipFree(ctx->rk) != hipSuccess) st = L1LINE_EHIP;
   (void)hipEventDestroy(ctx->stage_done);
   (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
@@ -616,6 +653,187 @@ int l1line_tune_get(l1line_ctx ctx, int32_t *params) {
   params[0] = ctx->tune.blocks_per_cu;
   params[1] = ctx->tune.kchunk_min;
   params[2] = ctx->tune.items_per_cu;
+  return L1LINE_OK;
+}
+
+// ------------------------------------------------------------------ ranker
+static bool bwd_attr_set = false;
+
+static int mlp_forward(l1line_ctx ctx, const float *P, const float *F, int64_t N, float *out, float *H1, float *H2,
+                       hipStream_t s) {
+  ProfScope ps(ctx, s, "mlp_fwd");
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((N + FWD_ROWS - 1) / FWD_ROWS)), dim3(64), 0, s, P, F, (int)N, out,
+                     H1, H2);
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_mlp_forward(l1line_ctx ctx, const float *params, const float *F, int64_t N, float *out, void *stream) {
+  if (!ctx || !params || !F || !out || N < 1 || N > (1ll << 24)) return L1LINE_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  return mlp_forward(ctx, params, F, N, out, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int l1line_mlp_grad(l1line_ctx ctx, const float *params, const float *F, const float *y, int64_t N, float *grad,
+                    float *loss, void *stream) {
+  if (!ctx || !params || !F || !y || !grad || N < 1 || N > (1ll << 22)) return L1LINE_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int ntiles = (int)((N + BWD_ROWS - 1) / BWD_ROWS);
+  const size_t fb = sizeof(float);
+  const size_t o_out = 0, o_h1 = align_up(fb * N, 256), o_h2 = o_h1 + align_up(fb * N * MLP_H, 256),
+               o_g = o_h2 + align_up(fb * N * MLP_H, 256), o_l = o_g + align_up(fb * ntiles * MLP_NPARAM, 256),
+               total = o_l + align_up(fb * ntiles, 256);
+  int st = ensure_rk(ctx, total, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  float *out = (float *)(b + o_out), *H1 = (float *)(b + o_h1), *H2 = (float *)(b + o_h2);
+  float *gpart = (float *)(b + o_g), *lpart = (float *)(b + o_l);
+  st = mlp_forward(ctx, params, F, N, out, H1, H2, s);
+  if (st) return st;
+  if (!bwd_attr_set) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_mlp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BWD_LDS));
+    bwd_attr_set = true;
+  }
+  {
+    ProfScope ps(ctx, s, "mlp_bwd");
+    hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)ntiles), dim3(64), BWD_LDS, s, params, F, y, (int)N, out, H1, H2,
+                       gpart, lpart);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, gpart, lpart, ntiles, grad,
+                       loss);
+  }
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2, const float *grad, int64_t step, float lr,
+                    void *stream) {
+  if (!ctx || !params || !m1 || !m2 || !grad || step < 1 || !(lr > 0.0f)) return L1LINE_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, m1, m2,
+                     grad, (long long)step, lr, 0.9f, 0.999f, 1e-8f);
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+// ranker scratch layout for a matrix of n x m: sketch matrices, their
+// outputs, column info, statistics, scores, candidates, mask, flags
+struct RkLayout {
+  int nsk, s[3];
+  size_t o_xs[3], o_v[3], o_j, o_obj, o_z, o_ci, o_stats, o_F, o_score, o_cand, o_mask, o_flag, o_margin, bytes;
+};
+
+static RkLayout rk_layout(int64_t n, int64_t m) {
+  RkLayout R;
+  R.nsk = 3;
+  const int sizes[3] = {64, 128, 256};
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off = align_up(off + b, 256); return o; };
+  for (int q = 0; q < 3; ++q) {
+    R.s[q] = (int)std::min<int64_t>(n, sizes[q]);
+    R.o_xs[q] = take(sizeof(double) * R.s[q] * m);
+    R.o_v[q] = take(sizeof(double) * m);
+  }
+  R.o_j = take(sizeof(int64_t) * 3);
+  R.o_obj = take(sizeof(double) * 3);
+  R.o_z = take(sizeof(double) * 3 * m);
+  R.o_ci = take(sizeof(ColInfo) * m);
+  R.o_stats = take(sizeof(double) * 4 * 4);
+  R.o_F = take(sizeof(float) * MLP_IN * m);
+  R.o_score = take(sizeof(float) * m);
+  R.o_cand = take(sizeof(int) * m);
+  R.o_mask = take(sizeof(int) * m);
+  R.o_flag = take(sizeof(int) * 4);
+  R.o_margin = take(sizeof(float) * 4);
+  R.bytes = off;
+  return R;
+}
+
+static int ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                           float *F, hipStream_t s) {
+  const RkLayout R = rk_layout(n, m);
+  int st = ensure_rk(ctx, R.bytes, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  l1line_problem pr[3];
+  double lam_q[3];
+  for (int q = 0; q < 3; ++q) {
+    double *Xs = (double *)(b + R.o_xs[q]);
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((R.s[q] * m + 255) / 256)), dim3(256), 0, s, X, (int)n,
+                       (int)m, (long long)ld, R.s[q], Xs);
+    // the penalty scales with the number of rows, as the error term does
+    lam_q[q] = lambda * (double)R.s[q] / (double)n;
+    pr[q] = single(Xs, R.s[q], m, R.s[q], &lam_q[q], 1, (double *)(b + R.o_v[q]), (int64_t *)(b + R.o_j) + q,
+                   (double *)(b + R.o_obj) + q, nullptr, (double *)(b + R.o_z) + q * m, nullptr);
+  }
+  HIP_TRY(hipGetLastError());
+  st = run_batch(ctx, pr, 3, 0, s, ctx->tune, nullptr);
+  if (st) return st;
+  ColInfo *ci = (ColInfo *)(b + R.o_ci);
+  double *stats = (double *)(b + R.o_stats);
+  hipLaunchKernelGGL(k_colprep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld, ci);
+  hipLaunchKernelGGL(k_feature_stats, dim3(1), dim3(256), 0, s, (const double *)(b + R.o_z), 3, (int)m, ci, stats);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, (const double *)(b + R.o_z), 3,
+                     (int)m, (int)n, lambda, ci, stats, F);
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                           float *F, void *stream) {
+  if (!ctx || !F) return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  st = check_lambdas(&lambda, 1);
+  if (st) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  return ranker_features(ctx, X, n, m, ld, lambda, F, (hipStream_t)stream);
+}
+
+__global__ void k_copy_flag(const int *src, int *dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                      const float *params, int32_t K, float margin_threshold, double *v, int64_t *j, double *obj,
+                      int32_t *median_row, int32_t *used_fallback, float *scores, int32_t *status, void *stream) {
+  if (!ctx || !params || !v || !j || !obj) return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  st = check_lambdas(&lambda, 1);
+  if (st) return st;
+  if (K < 1 || K > m || !(margin_threshold >= 0.0f) || isinf(margin_threshold)) return L1LINE_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const RkLayout R = rk_layout(n, m);
+  st = ensure_rk(ctx, R.bytes, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  float *F = (float *)(b + R.o_F);
+  float *sc = scores ? scores : (float *)(b + R.o_score);
+  int *cand = (int *)(b + R.o_cand), *mask = (int *)(b + R.o_mask), *flag = (int *)(b + R.o_flag);
+  float *margin = (float *)(b + R.o_margin);
+  {
+    ProfScope ps(ctx, s, "features");
+    st = ranker_features(ctx, X, n, m, ld, lambda, F, s);
+    if (st) return st;
+  }
+  st = mlp_forward(ctx, params, F, m, sc, nullptr, nullptr, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, s, sc, (int)m, (int)K, margin_threshold, cand, mask, flag,
+                     margin);
+  HIP_TRY(hipGetLastError());
+  const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, nullptr, status);
+  // exact solve of the K candidates
+  const RunOpts rc{cand, (int)K, mask, nullptr, 0};
+  st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, rc);
+  if (st) return st;
+  // exhaustive solve, which does nothing unless the margin test failed
+  const RunOpts rf{nullptr, 0, nullptr, flag, 1};
+  st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, rf);
+  if (st) return st;
+  if (used_fallback) hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, s, flag, used_fallback);
+  HIP_TRY(hipGetLastError());
   return L1LINE_OK;
 }
 

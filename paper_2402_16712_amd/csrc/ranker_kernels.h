@@ -1,0 +1,396 @@
+// ranker_kernels.h -- learned candidate ranker for the exhaustive search over
+// the preserved coordinate j: per-column features, a 32 -> 128 -> 128 -> 1 MLP
+// (BF16 operands on the MFMA units, FP32 accumulation) with its backward pass
+// and Adam, and the top-K candidate selection.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <l1line.h>
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ parameters
+// Flat FP32 parameter vector (master weights):
+constexpr int MLP_IN = L1LINE_FEATURES, MLP_H = 128;
+constexpr int OFF_W1 = 0;                          // [MLP_IN][MLP_H]
+constexpr int OFF_B1 = OFF_W1 + MLP_IN * MLP_H;    // [MLP_H]
+constexpr int OFF_W2 = OFF_B1 + MLP_H;             // [MLP_H][MLP_H]
+constexpr int OFF_B2 = OFF_W2 + MLP_H * MLP_H;     // [MLP_H]
+constexpr int OFF_W3 = OFF_B2 + MLP_H;             // [MLP_H]
+constexpr int OFF_B3 = OFF_W3 + MLP_H;             // [1]
+constexpr int MLP_NPARAM = OFF_B3 + 1;
+static_assert(MLP_NPARAM == L1LINE_MLP_PARAMS, "parameter count");
+
+__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
+
+// MFMA 16x16x32 (BF16 in, FP32 accumulate).  Fragment layouts of one wave64:
+//   A (16 x 32): lane l holds A[l & 15][8 (l >> 4) + q], q = 0..7
+//   B (32 x 16): lane l holds B[8 (l >> 4) + q][l & 15]
+//   C (16 x 16): lane l holds C[4 (l >> 4) + q][l & 15], q = 0..3
+// A[r][k] = M[(r0 + r) * rs + (k0 + k) * cs]
+__device__ __forceinline__ bf16x8 frag_a(const float *M, int rs, int cs, int r0, int k0, int lane) {
+  bf16x8 a;
+  const int r = r0 + (lane & 15), kb = k0 + 8 * (lane >> 4);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = (__bf16)M[r * rs + (kb + q) * cs];
+  return a;
+}
+// B[k][c] = N[(k0 + k) * rs + (c0 + c) * cs]
+__device__ __forceinline__ bf16x8 frag_b(const float *N, int rs, int cs, int k0, int c0, int lane) {
+  bf16x8 b;
+  const int c = c0 + (lane & 15), kb = k0 + 8 * (lane >> 4);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b[q] = (__bf16)N[(kb + q) * rs + c * cs];
+  return b;
+}
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ forward
+// One wave per 16-row tile:
+//   H1 = bf16(relu(bf16(F) bf16(W1) + b1)),  H2 = bf16(relu(H1 bf16(W2) + b2)),
+//   out = sum_c H2[c] bf16(W3[c]) + b3  (four 32-column partials added in order)
+// H1, H2 (N x 128, the rounded values) are stored when the pointers are given.
+constexpr int FWD_ROWS = 16;
+
+__global__ void __launch_bounds__(64)
+k_mlp_fwd(const float *__restrict__ P, const float *__restrict__ F, int N, float *__restrict__ out,
+          float *__restrict__ H1g, float *__restrict__ H2g) {
+  __shared__ float sF[FWD_ROWS * MLP_IN];
+  __shared__ float sH1[FWD_ROWS * MLP_H];
+  __shared__ float sH2[FWD_ROWS * MLP_H];
+  const int lane = threadIdx.x;
+  const int row0 = blockIdx.x * FWD_ROWS;
+  for (int e = lane; e < FWD_ROWS * MLP_IN; e += 64) {
+    const int r = e / MLP_IN, k = e % MLP_IN;
+    sF[e] = (row0 + r < N) ? F[(long long)(row0 + r) * MLP_IN + k] : 0.0f;
+  }
+  __syncthreads();
+  const int col = lane & 15, rq = 4 * (lane >> 4);
+  for (int cb = 0; cb < MLP_H / 16; ++cb) {
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = mfma16(frag_a(sF, MLP_IN, 1, 0, 0, lane), frag_b(P + OFF_W1, MLP_H, 1, 0, 16 * cb, lane), c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float h = c[q] + P[OFF_B1 + 16 * cb + col];
+      sH1[(rq + q) * MLP_H + 16 * cb + col] = bf16_round(h > 0.f ? h : 0.f);
+    }
+  }
+  __syncthreads();
+  for (int cb = 0; cb < MLP_H / 16; ++cb) {
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < MLP_H / 32; ++kc)
+      c = mfma16(frag_a(sH1, MLP_H, 1, 0, 32 * kc, lane), frag_b(P + OFF_W2, MLP_H, 1, 32 * kc, 16 * cb, lane), c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float h = c[q] + P[OFF_B2 + 16 * cb + col];
+      sH2[(rq + q) * MLP_H + 16 * cb + col] = bf16_round(h > 0.f ? h : 0.f);
+    }
+  }
+  __syncthreads();
+  // output: lane (r = lane & 15, s = lane >> 4) sums columns [32 s, 32 s + 32)
+  const int r = lane & 15, sg = lane >> 4;
+  float p = 0.f;
+  for (int c2 = 32 * sg; c2 < 32 * sg + 32; ++c2) p += sH2[r * MLP_H + c2] * bf16_round(P[OFF_W3 + c2]);
+  const float p1 = __shfl(p, r + 16), p2 = __shfl(p, r + 32), p3 = __shfl(p, r + 48);
+  if (lane < 16 && row0 + r < N) out[row0 + r] = (((p + p1) + p2) + p3) + P[OFF_B3];
+  if (H1g || H2g) {
+    for (int e = lane; e < FWD_ROWS * MLP_H; e += 64) {
+      const int rr = e / MLP_H;
+      if (row0 + rr < N) {
+        if (H1g) H1g[(long long)row0 * MLP_H + e] = sH1[e];
+        if (H2g) H2g[(long long)row0 * MLP_H + e] = sH2[e];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- backward
+// Loss = mean over rows of (out - y)^2.  One wave per 32-row tile writes its
+// gradient partial (all parameters) and loss partial; a second kernel adds
+// the partials in tile order (deterministic).  Backward products use BF16
+// operands (the rounded activations and BF16(dH)) with FP32 accumulation.
+constexpr int BWD_ROWS = 32;
+
+__global__ void __launch_bounds__(64)
+k_mlp_bwd(const float *__restrict__ P, const float *__restrict__ F, const float *__restrict__ y, int N,
+          const float *__restrict__ out, const float *__restrict__ H1g, const float *__restrict__ H2g,
+          float *__restrict__ gpart, float *__restrict__ lpart) {
+  extern __shared__ __attribute__((aligned(16))) float smem_f[];
+  float *sF = smem_f;                         // 32 x 32
+  float *sH1 = sF + BWD_ROWS * MLP_IN;        // 32 x 128
+  float *sH2 = sH1 + BWD_ROWS * MLP_H;        // 32 x 128
+  float *sD2 = sH2 + BWD_ROWS * MLP_H;        // dH2, BF16-rounded, 32 x 128
+  float *sD1 = sD2 + BWD_ROWS * MLP_H;        // dH1, BF16-rounded, 32 x 128
+  float *sdo = sD1 + BWD_ROWS * MLP_H;        // dout, 32
+  const int lane = threadIdx.x;
+  const int tile = blockIdx.x, row0 = tile * BWD_ROWS;
+  float *g = gpart + (long long)tile * MLP_NPARAM;
+  for (int e = lane; e < BWD_ROWS * MLP_IN; e += 64) {
+    const int r = e / MLP_IN;
+    sF[e] = (row0 + r < N) ? F[(long long)row0 * MLP_IN + e] : 0.0f;
+  }
+  for (int e = lane; e < BWD_ROWS * MLP_H; e += 64) {
+    const int r = e / MLP_H;
+    const bool in = row0 + r < N;
+    sH1[e] = in ? H1g[(long long)row0 * MLP_H + e] : 0.0f;
+    sH2[e] = in ? H2g[(long long)row0 * MLP_H + e] : 0.0f;
+  }
+  if (lane < BWD_ROWS) {
+    const int r = row0 + lane;
+    const float d = r < N ? out[r] - y[r] : 0.0f;
+    sdo[lane] = 2.0f * d / (float)N;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    float l = 0.f;
+    for (int r = 0; r < BWD_ROWS; ++r) {
+      const int rr = row0 + r;
+      const float d = rr < N ? out[rr] - y[rr] : 0.0f;
+      l += d * d;
+    }
+    lpart[tile] = l / (float)N;
+    float db3 = 0.f;
+    for (int r = 0; r < BWD_ROWS; ++r) db3 += sdo[r];
+    g[OFF_B3] = db3;
+  }
+  // dW3, dH2
+  for (int c = lane; c < MLP_H; c += 64) {
+    float acc = 0.f;
+    const float w3 = bf16_round(P[OFF_W3 + c]);
+    for (int r = 0; r < BWD_ROWS; ++r) {
+      acc += sH2[r * MLP_H + c] * sdo[r];
+      sD2[r * MLP_H + c] = bf16_round(sH2[r * MLP_H + c] > 0.f ? sdo[r] * w3 : 0.f);
+    }
+    g[OFF_W3 + c] = acc;
+  }
+  __syncthreads();
+  const int col = lane & 15, rq = 4 * (lane >> 4);
+  // dW2[i][o] = sum_r H1[r][i] dH2[r][o]
+  for (int ib = 0; ib < MLP_H / 16; ++ib)
+    for (int ob = 0; ob < MLP_H / 16; ++ob) {
+      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      c = mfma16(frag_a(sH1, 1, MLP_H, 16 * ib, 0, lane), frag_b(sD2, MLP_H, 1, 0, 16 * ob, lane), c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[OFF_W2 + (16 * ib + rq + q) * MLP_H + 16 * ob + col] = c[q];
+    }
+  // db2
+  for (int o = lane; o < MLP_H; o += 64) {
+    float acc = 0.f;
+    for (int r = 0; r < BWD_ROWS; ++r) acc += sD2[r * MLP_H + o];
+    g[OFF_B2 + o] = acc;
+  }
+  // dH1[r][i] = relu'(H1) sum_o dH2[r][o] W2[i][o]
+  for (int rb = 0; rb < BWD_ROWS / 16; ++rb)
+    for (int ib = 0; ib < MLP_H / 16; ++ib) {
+      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      for (int kc = 0; kc < MLP_H / 32; ++kc)
+        c = mfma16(frag_a(sD2, MLP_H, 1, 16 * rb, 32 * kc, lane), frag_b(P + OFF_W2, 1, MLP_H, 32 * kc, 16 * ib, lane),
+                   c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * rb + rq + q, i = 16 * ib + col;
+        sD1[r * MLP_H + i] = bf16_round(sH1[r * MLP_H + i] > 0.f ? c[q] : 0.f);
+      }
+    }
+  __syncthreads();
+  // db1
+  for (int i = lane; i < MLP_H; i += 64) {
+    float acc = 0.f;
+    for (int r = 0; r < BWD_ROWS; ++r) acc += sD1[r * MLP_H + i];
+    g[OFF_B1 + i] = acc;
+  }
+  // dW1[k][i] = sum_r F[r][k] dH1[r][i]
+  for (int kb = 0; kb < MLP_IN / 16; ++kb)
+    for (int ib = 0; ib < MLP_H / 16; ++ib) {
+      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      c = mfma16(frag_a(sF, 1, MLP_IN, 16 * kb, 0, lane), frag_b(sD1, MLP_H, 1, 0, 16 * ib, lane), c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[OFF_W1 + (16 * kb + rq + q) * MLP_H + 16 * ib + col] = c[q];
+    }
+}
+
+constexpr size_t BWD_LDS = sizeof(float) * (BWD_ROWS * MLP_IN + 4 * BWD_ROWS * MLP_H + BWD_ROWS);
+
+// sum of the tile partials in tile order
+__global__ void k_mlp_reduce(const float *__restrict__ gpart, const float *__restrict__ lpart, int ntiles,
+                             float *__restrict__ grad, float *__restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < MLP_NPARAM) {
+    float acc = 0.f;
+    for (int t = 0; t < ntiles; ++t) acc += gpart[(long long)t * MLP_NPARAM + p];
+    grad[p] = acc;
+  }
+  if (p == 0 && loss) {
+    float l = 0.f;
+    for (int t = 0; t < ntiles; ++t) l += lpart[t];
+    *loss = l;
+  }
+}
+
+// Adam on the FP32 master weights (bias-corrected; step counts from 1)
+__global__ void k_mlp_adam(float *__restrict__ P, float *__restrict__ m1, float *__restrict__ m2,
+                           const float *__restrict__ grad, long long step, float lr, float beta1, float beta2,
+                           float eps) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= MLP_NPARAM) return;
+  const float gr = grad[p];
+  const float a = beta1 * m1[p] + (1.0f - beta1) * gr;
+  const float b = beta2 * m2[p] + (1.0f - beta2) * gr * gr;
+  m1[p] = a;
+  m2[p] = b;
+  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+  const float mh = a / c1, vh = b / c2;
+  P[p] = P[p] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// ----------------------------------------------------------------- features
+// Rows of the sketches: row q of a sketch of s rows is floor((q + 0.5) n / s).
+__global__ void k_gather_rows(const double *__restrict__ X, int n, int m, long long ld, int s,
+                              double *__restrict__ Xs) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)s * m) return;
+  const int k = (int)(e / s), q = (int)(e % s);
+  const int i = (int)(((2ll * q + 1) * n) / (2ll * s));
+  Xs[(long long)k * s + q] = X[(long long)k * ld + i];
+}
+
+// min / mean / std of each sketch's z over the columns (one workgroup)
+__global__ void k_feature_stats(const double *__restrict__ Zs, int nsk, int m, const ColInfo *__restrict__ ci,
+                                double *__restrict__ stats) {
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  for (int q = 0; q <= nsk; ++q) {
+    // q < nsk: sketch q's z; q == nsk: column masses
+    double mn = 1e300, sum = 0.0, sq = 0.0;
+    for (int j = tid; j < m; j += blockDim.x) {
+      const double v = q < nsk ? Zs[(long long)q * m + j] : ci[j].W;
+      mn = fmin(mn, v);
+      sum += v;
+      sq += v * v;
+    }
+    sh[tid] = mn;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+      if (tid < s) sh[tid] = fmin(sh[tid], sh[tid + s]);
+      __syncthreads();
+    }
+    const double gmin = sh[0];
+    __syncthreads();
+    sh[tid] = sum;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+      if (tid < s) sh[tid] += sh[tid + s];
+      __syncthreads();
+    }
+    const double gsum = sh[0];
+    __syncthreads();
+    sh[tid] = sq;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+      if (tid < s) sh[tid] += sh[tid + s];
+      __syncthreads();
+    }
+    const double gsq = sh[0];
+    __syncthreads();
+    if (tid == 0) {
+      const double mean = gsum / m;
+      const double var = fmax(gsq / m - mean * mean, 0.0);
+      stats[4 * q + 0] = gmin;
+      stats[4 * q + 1] = mean;
+      stats[4 * q + 2] = sqrt(var);
+    }
+  }
+}
+
+// the 32 features of column j (documented in the header)
+__global__ void k_features(const double *__restrict__ Zs, int nsk, int m, int n, double lambda,
+                           const ColInfo *__restrict__ ci, const double *__restrict__ stats, float *__restrict__ F) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  float f[MLP_IN];
+#pragma unroll
+  for (int q = 0; q < MLP_IN; ++q) f[q] = 0.f;
+  double gapsum = 0.0, gmin = 1e300, gmax = -1e300;
+  for (int q = 0; q < nsk && q < 3; ++q) {
+    const double z = Zs[(long long)q * m + j];
+    const double mn = stats[4 * q], mean = stats[4 * q + 1], sd = stats[4 * q + 2];
+    const double gap = (mean > mn) ? (z - mn) / (mean - mn) : 0.0;
+    f[q] = (float)gap;
+    f[3 + q] = (float)log1p(fmax(mn > 0.0 ? z / mn - 1.0 : 0.0, 0.0));
+    f[6 + q] = (float)(sd > 0.0 ? (z - mean) / sd : 0.0);
+    gapsum += gap;
+    gmin = fmin(gmin, gap);
+    gmax = fmax(gmax, gap);
+  }
+  const ColInfo c = ci[j];
+  const double meanW = stats[4 * nsk + 1];
+  f[9] = (float)(c.W > 0.0 && meanW > 0.0 ? log(c.W / meanW) : -30.0);
+  f[10] = (float)c.zeros / (float)n;
+  f[11] = (float)(c.W > 0.0 ? fmin(lambda / c.W, 10.0) : 10.0);
+  f[12] = (float)(c.W > 0.0 ? log1p(lambda / c.W) : 10.0);
+  f[13] = (float)(gapsum / 3.0);
+  f[14] = (float)(gmax - gmin);
+  f[15] = 1.0f;
+#pragma unroll
+  for (int q = 0; q < MLP_IN; ++q) F[(long long)j * MLP_IN + q] = f[q];
+}
+
+// ------------------------------------------------------------------- top-K
+// K smallest scores (lowest index on ties), their list in increasing score,
+// a candidate mask, and the margin between the first score left out and the
+// best; fallback = (margin < threshold) or K >= m.
+__global__ void k_topk(const float *__restrict__ score, int m, int K, float threshold, int *__restrict__ cand,
+                       int *__restrict__ mask, int *__restrict__ fallback, float *__restrict__ margin_out) {
+  __shared__ float sv[256];
+  __shared__ int si[256];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < m; j += blockDim.x) mask[j] = 0;
+  __syncthreads();
+  float best0 = 0.f, next = 0.f;
+  for (int r = 0; r <= K && r < m; ++r) {
+    float bv = 0.f;
+    int bi = -1;
+    for (int j = tid; j < m; j += blockDim.x) {
+      if (mask[j]) continue;
+      const float v = isnan(score[j]) ? INFINITY : score[j];
+      if (bi < 0 || v < bv) { bv = v; bi = j; }
+    }
+    sv[tid] = bv;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+      if (tid < s) {
+        const int oi = si[tid + s];
+        const float ov = sv[tid + s];
+        if (oi >= 0 && (si[tid] < 0 || ov < sv[tid] || (ov == sv[tid] && oi < si[tid]))) {
+          sv[tid] = ov;
+          si[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int pick = si[0];
+    const float pv = sv[0];
+    __syncthreads();
+    if (r == 0) best0 = pv;
+    if (r < K) {
+      if (tid == 0) {
+        cand[r] = pick;
+        mask[pick] = 1;
+      }
+    } else {
+      next = pv;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const float mg = (K < m) ? next - best0 : 0.f;
+    *margin_out = mg;
+    *fallback = (K >= m || mg < threshold) ? 1 : 0;
+  }
+}

@@ -1,0 +1,182 @@
+"""Training and evaluation of the learned candidate ranker.
+
+The labels are the exact per-column objectives z_j of Algorithm 1 computed by
+the library's exhaustive GPU fit; the target of column j is its normalized
+gap (z_j - min z) / (mean z - min z), so lower scores mean better
+candidates.  Forward, backward and Adam run in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as wl
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases; FP32 flat vector."""
+    rng = wl._rng(9, seed)
+    P = np.zeros(B.MLP_PARAMS, dtype=np.float64)
+    i = 0
+    for fan_in, fan_out in ((32, 128), (128, 128)):
+        P[i:i + fan_in * fan_out] = rng.standard_normal(fan_in * fan_out) * np.sqrt(2.0 / fan_in)
+        i += fan_in * fan_out + fan_out
+    P[i:i + 128] = rng.standard_normal(128) * np.sqrt(1.0 / 128)
+    return P.astype(np.float32)
+
+
+def targets(z):
+    """Normalized gap of the exact objectives (torch tensor in, float32 out)."""
+    import torch
+    z = z.to(torch.float64)
+    lo, mean = z.min(), z.mean()
+    span = (mean - lo) if float(mean - lo) > 0 else torch.tensor(1.0, dtype=torch.float64, device=z.device)
+    return ((z - lo) / span).to(torch.float32).contiguous()
+
+
+class Trainer:
+    def __init__(self, ctx: B.Context, seed: int = 0, lr: float = 1e-3):
+        import torch
+        self.ctx = ctx
+        dev = ctx._torch_device
+        self.params = torch.from_numpy(init_params(seed)).to(dev)
+        self.m1 = torch.zeros_like(self.params)
+        self.m2 = torch.zeros_like(self.params)
+        self.step = 0
+        self.cursor = 0
+        self.lr = lr
+
+    def example(self, index: int, **kw):
+        """(features, targets) of training matrix `index`."""
+        X, lam = wl.ranker_matrix_torch(index, device=self.ctx._torch_device, **kw)
+        out = self.ctx.fit(X, lam)
+        F = self.ctx.features(X, lam)
+        return F, targets(out["z_all"])
+
+    def train_step(self, F, y):
+        grad, loss = self.ctx.mlp_grad(self.params, F, y)
+        self.step += 1
+        self.ctx.mlp_adam(self.params, self.m1, self.m2, grad, self.step, self.lr)
+        return loss
+
+    def train(self, n_examples: int, log_every: int = 0, **kw):
+        losses = []
+        for _ in range(n_examples):
+            F, y = self.example(self.cursor, **kw)
+            losses.append(self.train_step(F, y))
+            self.cursor += 1
+            if log_every and self.cursor % log_every == 0:
+                print(f"ranker step {self.step} loss {float(losses[-1].item()):.4g}", flush=True)
+        return losses
+
+    def save(self, path: str):
+        np.savez(path, params=self.params.cpu().numpy(), m1=self.m1.cpu().numpy(),
+                 m2=self.m2.cpu().numpy(), step=np.int64(self.step), cursor=np.int64(self.cursor),
+                 lr=np.float64(self.lr))
+
+    def load(self, path: str):
+        import torch
+        with np.load(path, allow_pickle=False) as d:
+            dev = self.ctx._torch_device
+            self.params = torch.from_numpy(d["params"]).to(dev)
+            self.m1 = torch.from_numpy(d["m1"]).to(dev)
+            self.m2 = torch.from_numpy(d["m2"]).to(dev)
+            self.step = int(d["step"])
+            self.cursor = int(d["cursor"])
+            self.lr = float(d["lr"])
+
+
+def load_params(path: str, device="cuda:0"):
+    import torch
+    with np.load(path, allow_pickle=False) as d:
+        return torch.from_numpy(d["params"]).to(device)
+
+
+def evaluate(ctx: B.Context, params, indices, K: int = 32, margin: float = 0.05, rel_tol: float = 1e-9,
+             **kw):
+    """Ranked fit vs exhaustive fit on evaluation matrices: fraction within
+    rel_tol of the exhaustive objective, fallback rate, times."""
+    import torch
+    rows = []
+    for idx in indices:
+        X, lam = wl.ranker_matrix_torch(idx, device=ctx._torch_device, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ex = ctx.fit(X, lam, rows=False, z_all=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rk = ctx.fit_ranked(X, lam, params, K, margin)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ze, zr = float(ex["obj"].item()), float(rk["obj"].item())
+        rows.append(dict(index=idx, z_exhaustive=ze, z_ranked=zr, ok=abs(zr - ze) <= rel_tol * abs(ze),
+                         fallback=int(rk["used_fallback"].item()), t_exhaustive=t1 - t0, t_ranked=t2 - t1,
+                         status=(int(ex["status"].item()), int(rk["status"].item()))))
+    return rows
+
+
+TRAIN_BASE = 1000        # training matrices are indices 1000, 1001, ...
+EVAL_BASE = 90000        # evaluation matrices (10000 x 4000) are 90000, 90001, ...
+WEIGHTS = __file__.rsplit("/", 1)[0] + "/ranker_weights.npz"
+
+
+def _main(argv=None):
+    import argparse
+    import json
+
+    import torch
+    ap = argparse.ArgumentParser(description="train / evaluate the candidate ranker on the GPU")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--examples", type=int, default=20000)
+    t.add_argument("--ckpt", default="ranker_ckpt.npz", help="checkpoint (resumed if present)")
+    t.add_argument("--out", default=WEIGHTS, help="trained parameters")
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--save-every", type=int, default=1000)
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--count", type=int, default=300)
+    e.add_argument("--n", type=int, default=10000)
+    e.add_argument("--m", type=int, default=4000)
+    e.add_argument("--K", type=int, default=32)
+    e.add_argument("--margin", type=float, default=0.05)
+    a = ap.parse_args(argv)
+    ctx = B.Context(0)
+    if a.cmd == "train":
+        tr = Trainer(ctx, seed=a.seed, lr=a.lr)
+        tr.cursor = TRAIN_BASE
+        try:
+            tr.load(a.ckpt)
+            print(f"resumed at step {tr.step}", flush=True)
+        except OSError:
+            pass
+        t0 = time.perf_counter()
+        while tr.step < a.examples:
+            chunk = min(a.save_every, a.examples - tr.step)
+            losses = tr.train(chunk)
+            tr.save(a.ckpt)
+            mean = float(torch.stack(losses).mean().item())
+            print(json.dumps({"step": tr.step, "mean_loss": mean, "s": time.perf_counter() - t0}), flush=True)
+        np.savez(a.out, params=tr.params.cpu().numpy())
+    else:
+        params = load_params(a.weights)
+        rows = []
+        for q in range(a.count):
+            r = evaluate(ctx, params, [EVAL_BASE + q], a.K, a.margin, n=a.n, m=a.m)[0]
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+        ok = sum(r["ok"] for r in rows)
+        fb = sum(r["fallback"] for r in rows)
+        te = sum(r["t_exhaustive"] for r in rows)
+        tk = sum(r["t_ranked"] for r in rows)
+        print(json.dumps({"instances": len(rows), "within_1e-9": ok / len(rows), "fallback_rate": fb / len(rows),
+                          "exhaustive_fits_per_s": len(rows) / te, "ranked_fits_per_s": len(rows) / tk,
+                          "speedup": te / tk}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    _main()

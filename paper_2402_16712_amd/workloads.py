@@ -161,3 +161,50 @@ def random_small(seed: int, n: int, m: int, integer: bool = False,
     if nz:
         X.reshape(-1)[rng.choice(n * m, size=nz, replace=False)] = 0.0
     return np.asfortranarray(X)
+
+
+def rank_one_matrix_torch(n: int, m: int, s: int, n_outlier_rows: int, outlier_sigma: float,
+                          zero_frac: float, seed: int, device="cuda:0", laplace_b: float = LAPLACE_B):
+    """The same recipe as rank_one_matrix, drawn on the GPU with torch's
+    seeded Philox generator (for the large training and evaluation sets of
+    the candidate ranker).  Returns a column-major (n, m) FP64 device tensor
+    (strides (1, n))."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    f64 = torch.float64
+    u = torch.randn(n, generator=g, device=device, dtype=f64)
+    load = torch.zeros(m, device=device, dtype=f64)
+    s = int(min(max(s, 0), m))
+    if s:
+        pos = torch.randperm(m, generator=g, device=device)[:s]
+        load[pos] = torch.rand(s, generator=g, device=device, dtype=f64) * 2.0 - 1.0
+    # Laplace(0, b) by inversion of a uniform on (-1/2, 1/2)
+    U = torch.rand((m, n), generator=g, device=device, dtype=f64) - 0.5
+    noise = -laplace_b * torch.sign(U) * torch.log1p(-2.0 * U.abs())
+    XT = load[:, None] * u[None, :] + noise                       # (m, n): column k is row k
+    n_out = int(min(max(n_outlier_rows, 0), n))
+    if n_out:
+        rows = torch.randperm(n, generator=g, device=device)[:n_out]
+        XT[:, rows] = outlier_sigma * torch.randn((m, n_out), generator=g, device=device, dtype=f64)
+    nz = int(round(zero_frac * n * m))
+    if nz:
+        flat = torch.randperm(n * m, generator=g, device=device)[:nz]
+        XT.view(-1)[flat] = 0.0
+    return XT.t()
+
+
+def ranker_matrix_torch(index: int, n=None, m=None, n_range=(500, 4000), m_range=(50, 500),
+                        device="cuda:0"):
+    """Ranker training / evaluation matrix `index` on the GPU: sizes from the
+    ranges unless fixed, 10% of m nonzero loadings, 10% outlier rows replaced
+    by 20*N(0,1), 1% zeros, lambda = 0.05 * max column mass."""
+    import torch
+    rng = _rng(8, index)
+    if n is None:
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+    if m is None:
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+    X = rank_one_matrix_torch(n, m, max(1, m // 10), n // 10, 20.0, 0.01, 1_000_003 * index + 17, device)
+    lam = 0.05 * float(X.abs().sum(dim=0).max())
+    return X, lam

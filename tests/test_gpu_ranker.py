@@ -1,0 +1,227 @@
+"""GPU parity of the candidate ranker: MLP forward / gradient / Adam against
+the FP64 reference that mirrors the BF16 rounding points, features against
+oracle sketch fits, and the ranked fit against the exhaustive oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from oracle import oracle as O
+from paper_2402_16712_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_16712_amd import binding as B
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _params(seed):
+    from paper_2402_16712_amd import ranker
+    P = ranker.init_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    # nonzero biases so every term of the gradient is exercised
+    P[M.OFF_B1:M.OFF_W2] = rng.standard_normal(M.H) * 0.1
+    P[M.OFF_B2:M.OFF_W3] = rng.standard_normal(M.H) * 0.1
+    P[M.OFF_B3] = 0.3
+    return P.astype(np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+# FP32 accumulation against the exact FP64 sums: an FP32 sum of <= 128 BF16
+# products is within ~1e-6 relative of the exact one, which can flip the BF16
+# rounding of a hidden activation (one ulp = 2^-8 relative) in rare cases.
+# The bound below admits a few such flips, no structural error.
+def _close(got, want, rel, what):
+    got = np.asarray(got, dtype=np.float64)
+    err = np.linalg.norm(got - want)
+    scale = np.linalg.norm(want) + 1e-30
+    assert err <= rel * scale, (what, err / scale)
+
+
+@pytest.mark.parametrize("N", [1, 15, 16, 17, 333, 4096 + 5])
+def test_mlp_forward(ctx, N):
+    _say(f"mlp_forward N={N}")
+    P = _params(1)
+    F = np.random.default_rng(N).standard_normal((N, M.IN)).astype(np.float32)
+    out = ctx.mlp_forward(_dev(P), _dev(F)).cpu().numpy()
+    want, _ = M.forward(P, F, bf=True)
+    _close(out, want, 2e-3, "out")
+    # elementwise: most rows agree to FP32 accumulation accuracy
+    d = np.abs(out - want) / (np.abs(want) + 1e-3)
+    assert np.mean(d < 1e-4) > 0.95, np.mean(d < 1e-4)
+
+
+@pytest.mark.parametrize("N", [1, 31, 32, 33, 500, 2048 + 7])
+def test_mlp_grad(ctx, N):
+    _say(f"mlp_grad N={N}")
+    P = _params(2)
+    rng = np.random.default_rng(N + 7)
+    F = rng.standard_normal((N, M.IN)).astype(np.float32)
+    y = rng.standard_normal(N).astype(np.float32)
+    g, loss = ctx.mlp_grad(_dev(P), _dev(F), _dev(y))
+    g = g.cpu().numpy()
+    want_loss, want = M.loss_and_grad(P, F, y, bf=True)
+    assert abs(float(loss.item()) - want_loss) <= 1e-4 * abs(want_loss), (float(loss.item()), want_loss)
+    for name, lo, hi in (("W1", M.OFF_W1, M.OFF_B1), ("b1", M.OFF_B1, M.OFF_W2), ("W2", M.OFF_W2, M.OFF_B2),
+                         ("b2", M.OFF_B2, M.OFF_W3), ("W3", M.OFF_W3, M.OFF_B3), ("b3", M.OFF_B3, M.NPARAM)):
+        _close(g[lo:hi], want[lo:hi], 1e-2, name)
+
+
+def test_mlp_grad_deterministic(ctx):
+    P = _params(3)
+    rng = np.random.default_rng(5)
+    F = _dev(rng.standard_normal((1000, M.IN)))
+    y = _dev(rng.standard_normal(1000))
+    g1, l1 = ctx.mlp_grad(_dev(P), F, y)
+    g2, l2 = ctx.mlp_grad(_dev(P), F, y)
+    assert g1.cpu().numpy().tobytes() == g2.cpu().numpy().tobytes()
+    assert l1.cpu().numpy().tobytes() == l2.cpu().numpy().tobytes()
+
+
+def test_mlp_adam(ctx):
+    rng = np.random.default_rng(11)
+    P = rng.standard_normal(M.NPARAM).astype(np.float32)
+    m1 = (rng.standard_normal(M.NPARAM) * 0.01).astype(np.float32)
+    m2 = (rng.random(M.NPARAM) * 1e-4).astype(np.float32)
+    g = rng.standard_normal(M.NPARAM).astype(np.float32)
+    dP, dm1, dm2 = _dev(P), _dev(m1), _dev(m2)
+    ctx.mlp_adam(dP, dm1, dm2, _dev(g), 7, 1e-3)
+    wP, wm1, wm2 = M.adam(P.astype(np.float64), m1.astype(np.float64), m2.astype(np.float64),
+                          g.astype(np.float64), 7, 1e-3)
+    np.testing.assert_allclose(dm1.cpu().numpy(), wm1, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(dm2.cpu().numpy(), wm2, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(dP.cpu().numpy(), wP, rtol=1e-6, atol=1e-6)
+
+
+def _features_ref(X, lam):
+    """The 32 features from oracle fits of the three sketches (FP64)."""
+    n, m = X.shape
+    W, zeros = O.column_stats(X)
+    gaps, f = [], np.zeros((m, 32))
+    for q, size in enumerate((64, 128, 256)):
+        s = min(n, size)
+        rows = ((2 * np.arange(s) + 1) * n) // (2 * s)
+        Xs = np.asfortranarray(X[rows, :])
+        z = O.fit(Xs, lam * s / n)["z_all"]
+        mn, mean = z.min(), z.mean()
+        sd = np.sqrt(max(np.mean(z * z) - mean * mean, 0.0))
+        gap = (z - mn) / (mean - mn) if mean > mn else np.zeros(m)
+        f[:, q] = gap
+        f[:, 3 + q] = np.log1p(np.maximum(z / mn - 1.0, 0.0)) if mn > 0 else 0.0
+        f[:, 6 + q] = (z - mean) / sd if sd > 0 else 0.0
+        gaps.append(gap)
+    gaps = np.array(gaps)
+    meanW = W.mean()
+    with np.errstate(divide="ignore"):
+        f[:, 9] = np.where(W > 0, np.log(np.where(W > 0, W, 1.0) / meanW), -30.0)
+        f[:, 10] = zeros / n
+        f[:, 11] = np.where(W > 0, np.minimum(lam / np.where(W > 0, W, 1.0), 10.0), 10.0)
+        f[:, 12] = np.where(W > 0, np.log1p(lam / np.where(W > 0, W, 1.0)), 10.0)
+    f[:, 13] = gaps.sum(0) / 3.0
+    f[:, 14] = gaps.max(0) - gaps.min(0)
+    f[:, 15] = 1.0
+    return f
+
+
+@pytest.mark.parametrize("n,m,seed", [(300, 40, 0), (50, 25, 1), (1000, 60, 2), (64, 9, 3)])
+def test_features(ctx, n, m, seed):
+    from paper_2402_16712_amd import binding as B
+    _say(f"features {n}x{m} seed {seed}")
+    X = wl.rank_one_matrix(n, m, max(1, m // 10), n // 10, 20.0, 0.01, (20, seed))
+    lam = 0.05 * wl.max_column_mass(X)
+    F = ctx.features(B.device_matrix(X), lam).cpu().numpy()
+    want = _features_ref(X, lam)
+    # the sketch objectives are exact on both sides; the features are FP32
+    # roundings of FP64 arithmetic (statistics summed in different orders)
+    np.testing.assert_allclose(F, want, rtol=1e-5, atol=2e-6)
+
+
+def _topk_ref(scores, K):
+    s = np.where(np.isnan(scores), np.inf, scores.astype(np.float64))
+    order = np.lexsort((np.arange(len(s)), s))
+    return order[:K], (s[order[K]] - s[order[0]]) if K < len(s) else 0.0
+
+
+@pytest.mark.parametrize("n,m,K,seed", [(400, 50, 8, 0), (120, 17, 1, 1), (900, 64, 63, 2)])
+def test_fit_ranked_candidates(ctx, n, m, K, seed):
+    """Threshold 0: never falls back unless K = m; the answer is the exact
+    optimum over the K best-scored columns."""
+    from paper_2402_16712_amd import binding as B
+    _say(f"fit_ranked {n}x{m} K={K}")
+    X = wl.rank_one_matrix(n, m, max(1, m // 10), n // 10, 20.0, 0.01, (21, seed))
+    lam = 0.05 * wl.max_column_mass(X)
+    P = _dev(_params(seed))
+    r = ctx.fit_ranked(B.device_matrix(X), lam, P, K, 0.0)
+    assert int(r["status"].item()) == 0
+    assert int(r["used_fallback"].item()) == 0
+    scores = r["scores"].cpu().numpy()
+    cand, _ = _topk_ref(scores, K)
+    ref = O.fit(X, lam)
+    z = ref["z_all"][cand]
+    jbest = int(cand[np.lexsort((cand, z))[0]])
+    assert int(r["j"].item()) == jbest
+    assert np.float64(r["obj"].item()).tobytes() == np.float64(ref["z_all"][jbest]).tobytes()
+    one = O.fit_j(X, jbest, [lam])
+    assert r["v"].cpu().numpy().tobytes() == one["V"][0].tobytes()
+    assert np.array_equal(r["row"].cpu().numpy(), one["ROW"][0])
+
+
+@pytest.mark.parametrize("K", [5, 30])
+def test_fit_ranked_fallback(ctx, K):
+    """A threshold no margin reaches (or K = m) runs the exhaustive search:
+    the result is the oracle's, bit for bit."""
+    from paper_2402_16712_amd import binding as B
+    X = wl.rank_one_matrix(500, 30, 3, 50, 20.0, 0.01, (22, K))
+    lam = 0.05 * wl.max_column_mass(X)
+    r = ctx.fit_ranked(B.device_matrix(X), lam, _dev(_params(9)), K, 1e30)
+    ref = O.fit(X, lam)
+    assert int(r["status"].item()) == 0
+    assert int(r["used_fallback"].item()) == 1
+    assert int(r["j"].item()) == ref["j"]
+    assert np.float64(r["obj"].item()).tobytes() == np.float64(ref["obj"]).tobytes()
+    assert r["v"].cpu().numpy().tobytes() == ref["v"].tobytes()
+    assert np.array_equal(r["row"].cpu().numpy(), ref["row"])
+
+
+def test_fit_ranked_bad_args(ctx):
+    from paper_2402_16712_amd import binding as B
+    X = B.device_matrix(wl.random_small(1, 20, 5))
+    P = _dev(_params(0))
+    for K, thr in ((0, 0.1), (6, 0.1), (2, -1.0), (2, float("nan")), (2, float("inf"))):
+        with pytest.raises(B.L1LineError):
+            ctx.fit_ranked(X, 1.0, P, K, thr)
+
+
+def test_trainer_resume(ctx, tmp_path):
+    """A checkpointed trainer resumed in a fresh object continues bit for bit."""
+    from paper_2402_16712_amd import ranker
+    kw = dict(n_range=(100, 300), m_range=(20, 40))
+    a = ranker.Trainer(ctx, seed=4, lr=1e-3)
+    a.train(3, **kw)
+    path = str(tmp_path / "ck.npz")
+    a.save(path)
+    a.train(2, **kw)
+    b = ranker.Trainer(ctx, seed=99, lr=5.0)
+    b.load(path)
+    b.train(2, **kw)
+    assert a.step == b.step == 5 and a.cursor == b.cursor
+    assert a.params.cpu().numpy().tobytes() == b.params.cpu().numpy().tobytes()
+    assert a.m2.cpu().numpy().tobytes() == b.m2.cpu().numpy().tobytes()
