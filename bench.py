@@ -4,7 +4,10 @@ One step = one call of the whole hot path (column prep, every (j, k)
 weighted median with its residual, the per-j objectives, the argmin) on a
 2000 x 2000 FP64 matrix resident in HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs path,batch,ranked]
+
+Besides the main line it reports, as extra fields, the 64-penalty path on
+the same matrix, the 512-matrix uneven batch and the learned top-K fit.
 """
 from __future__ import annotations
 
@@ -40,6 +43,9 @@ def _args():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (scale for HBM byte counters)")
+    ap.add_argument("--legs", default="path,batch,ranked",
+                    help="extra workloads reported beside the main line (comma list; '' for none)")
+    ap.add_argument("--ranked-instances", type=int, default=3)
     return ap.parse_args()
 
 
@@ -111,6 +117,73 @@ def cpu_baseline(p, lam, z_gpu, columns):
                 z_mismatches=len(mism))
 
 
+def _timed(fn, steps, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1) / steps
+
+
+def leg_path(ctx, seed, steps, stream):
+    """Lambda path: 2000 x 2000, 64 penalties, one call."""
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import workloads as wl
+    p = wl.lambda_path(seed)
+    X = B.device_matrix(p.X)
+    ctx.fit_path(X, p.lambdas)
+    out, ms = _timed(lambda: ctx.fit_path(X, p.lambdas, rows=False, z_all=False), steps, stream)
+    st = int(out["status"].item())
+    n, m = p.X.shape
+    L = len(p.lambdas)
+    return {"workload": f"lambda path {n}x{m} FP64, {L} penalties log-spaced 1e-3..1 x max column mass",
+            "ms_per_call": ms, "fits_per_s": L * 1000.0 / ms, "medians_per_s": m * (m - 1) * L * 1000.0 / ms,
+            "status": st}
+
+
+def leg_batch(ctx, steps, stream):
+    """512 uneven problems (n 50..4000, m 10..500, 16 penalties each), one
+    batch call replayed from a captured graph."""
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import workloads as wl
+    probs = wl.uneven_batch()
+    dev = [(B.device_matrix(p.X), p.lambdas) for p in probs]
+    arr, outs, keep = ctx._batch_args(dev, False, False)
+    ctx.fit_batch_prepared(arr, len(dev), graph=True)       # capture
+    ctx.fit_batch_prepared(arr, len(dev), graph=True)       # replay
+    _, ms = _timed(lambda: ctx.fit_batch_prepared(arr, len(dev), graph=True), steps, stream)
+    bad = sum(int(o["status"].item()) != 0 for o in outs)
+    medians = sum(p.m * (p.m - 1) * len(p.lambdas) for p in probs)
+    del keep
+    return {"workload": "512 uneven matrices n~U{50..4000} m~U{10..500}, 16 penalties each, graph replay",
+            "ms_per_batch": ms, "problems_per_s": len(probs) * 1000.0 / ms,
+            "medians_per_s": medians * 1000.0 / ms, "nonzero_status": bad}
+
+
+def leg_ranked(ctx, count):
+    """Learned top-K (K = 32) vs exhaustive on 10000 x 4000 matrices."""
+    import os
+    from paper_2402_16712_amd import ranker
+    if not os.path.exists(ranker.WEIGHTS):
+        return {"skipped": "no trained ranker weights in the package"}
+    params = ranker.load_params(ranker.WEIGHTS)
+    # one warm-up instance outside the statistics (allocations, first launches)
+    ranker.evaluate(ctx, params, [ranker.EVAL_BASE + 10 ** 6], n=2000, m=500)
+    rows = ranker.evaluate(ctx, params, [ranker.EVAL_BASE + q for q in range(count)], n=10000, m=4000)
+    te = sum(r["t_exhaustive"] for r in rows)
+    tk = sum(r["t_ranked"] for r in rows)
+    return {"workload": f"ranked fit, {count} matrices 10000x4000 FP64, K=32, margin 0.05, lambda 0.05 x mass",
+            "exhaustive_fits_per_s": len(rows) / te, "ranked_fits_per_s": len(rows) / tk,
+            "speedup": te / tk, "within_1e-9": sum(r["ok"] for r in rows) / len(rows),
+            "fallback_rate": sum(r["fallback"] for r in rows) / len(rows),
+            "statuses_nonzero": sum(1 for r in rows if r["status"] != (0, 0))}
+
+
 def main():
     a = _args()
     if a.calibrate_copy:
@@ -151,7 +224,7 @@ def main():
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     kern = {}
-    for name in ("colprep", "fit_seg", "reduce", "argmin"):
+    for name in ("colprep", "signsum", "fit_seg", "reduce", "argmin"):
         ms, cnt = ctx.profile_read(name)
         kern[name] = ms / max(cnt, 1)
     ctx.profile_read(reset=True)
@@ -166,16 +239,18 @@ def main():
     z_gpu = out["z_all"].cpu().numpy()
     j_star = int(out["j"].item())
 
-    # roofline of the dominant kernel (one launch = one fit's m(m-1) segments)
+    # roofline of the dominant kernel, the segment kernel, together with its
+    # division-free first pass (the sign sums): one launch of each = one
+    # fit's m(m-1) segments
     nnz = np.count_nonzero(p.X, axis=0)
     elements = float(nnz.sum()) * (m - 1)          # ratio elements per launch
-    seg_s = kern["fit_seg"] / 1000.0
-    achieved = elements * OPS_PER_ELEMENT / seg_s
-    roof = {"bound": "alu", "kernel": "k_fit_seg", "achieved": achieved / 1e12,
+    seg_ms = kern["fit_seg"] + kern["signsum"]
+    achieved = elements * OPS_PER_ELEMENT / (seg_ms / 1000.0)
+    roof = {"bound": "alu", "kernel": "k_seg_batch + k_signsum_batch", "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
-            "frac": achieved / VALU_PEAK_OPS, "traffic": _traffic("fit_seg_2000x2000"),
+            "frac": achieved / VALU_PEAK_OPS, "traffic": _traffic("seg_2000x2000"),
             "ops_per_element": OPS_PER_ELEMENT, "elements_per_launch": elements,
-            "avg_launch_ms": kern["fit_seg"]}
+            "avg_launch_ms": seg_ms}
 
     line = {
         "metric": "fits/s & weighted-medians/s, 2000x2000 FP64; learned top-K vs exhaustive",
@@ -193,6 +268,13 @@ def main():
         "roofline": roof,
         "j_star": j_star,
     }
+    legs = [x for x in a.legs.split(",") if x]
+    if "path" in legs:
+        line["path"] = leg_path(ctx, a.seed, 3, stream)
+    if "batch" in legs:
+        line["batch"] = leg_batch(ctx, 3, stream)
+    if "ranked" in legs:
+        line["ranked"] = leg_ranked(ctx, a.ranked_instances)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, lam, z_gpu, a.cpu_columns)
     ctx.close()

@@ -229,7 +229,8 @@ int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
  * context launches is bracketed by HIP events on its stream.
  * l1line_profile_read waits for the recorded events, returns the summed
  * duration (ms) and launch count of the kernels whose name is `kernel`
- * ("colprep", "fit_seg", "reduce", "argmin"; NULL = all), and with reset != 0
+ * ("colprep", "signsum", "fit_seg", "reduce", "argmin", "features",
+ * "mlp_fwd", "mlp_bwd"; NULL = all), and with reset != 0
  * forgets every record.  Outputs are HOST pointers (nullable). */
 int l1line_profile(l1line_ctx ctx, int enable);
 int l1line_profile_read(l1line_ctx ctx, const char *kernel, double *total_ms,

@@ -37,6 +37,7 @@ struct ProbDesc {
   int out_off;          // first (problem, lambda) slot: sum of L over earlier problems
   long long ws_off;     // first element of this problem's L*m*m block in V / E / R
   long long z_off;      // first element of this problem's L*m block in Z / zflag
+  long long pair_off;   // first element of this problem's m*m block of sign sums
   double *Vout;         // L*m
   long long *Jout;      // L
   double *OBJout;       // L
@@ -497,24 +498,112 @@ __device__ __forceinline__ void wave_sort2(uint64_t &a, uint64_t &b, int lane) {
   }
 }
 
+// --------------------------------------------------------------- sign sums
+// For the pair (j, k) the ratio of row i, x_ik / x_ij, is positive, negative
+// or zero with the signs of x_ik and x_ij (barring underflow, checked per
+// segment).  Its weight is |x_ij|, so
+//   D_jk  = sum_i x_ij sgn(x_ik)        = (weight of positive ratios) - (negative)
+//   Zr_jk = sum_i |x_ij| [x_ik == 0]    = weight of the zero ratios
+// and 0 minimises g_jk exactly when |D_jk| <= lambda + Zr_jk (Lemma 1 at the
+// point 0).  Both are dense contractions over the rows: X^T sgn(X) and
+// |X|^T [X == 0], computed here for all pairs with FP64 MFMA (16x16x4).
+// Their rounding error (at most about n 2^-52 of the column mass) is far
+// below the decision margin the segment kernel applies.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int SS_TILE = 64;     // 64 (j) x 64 (k) outputs per workgroup, 4 waves of 16 x 64
+constexpr int SS_ROWS = 32;     // rows i per LDS stage
+constexpr int SS_LD = SS_TILE + 2;
+
+// Fragment layout of v_mfma_f64_16x16x4f64 (wave64, measured on gfx950):
+// lane l holds A[l & 15][l >> 4], B[l >> 4][l & 15] and D[(l >> 4) + 4 q][l & 15],
+// q = 0..3 (unlike the FP32-output forms, the row index steps by 4 per
+// register).
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// tstart[b] = first tile of problem b; problem b has ceil(mj / 64) x
+// ceil(m / 64) tiles with mj = ncand when cand is given (problem 0 only),
+// else m.  DZ[pair_off + j m + k] = (D_jk, Zr_jk).
+__global__ void __launch_bounds__(256)
+k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, int B,
+                const int *__restrict__ cand, int ncand, double2 *__restrict__ DZ,
+                const int *__restrict__ gate, int gate_on) {
+  __shared__ double sA[SS_ROWS * SS_LD];
+  __shared__ double sB[SS_ROWS * SS_LD];
+  __shared__ int sj[SS_TILE];
+  if (gate && *gate != gate_on) return;
+  const int g = blockIdx.x;
+  const int b = find_owner(tstart, B, g);
+  const ProbDesc d = P[b];
+  const int mj = cand ? ncand : d.m;
+  const int tk_count = (d.m + SS_TILE - 1) / SS_TILE;
+  const int tloc = g - tstart[b];
+  const int j0 = (tloc / tk_count) * SS_TILE, k0 = (tloc % tk_count) * SS_TILE;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid < SS_TILE) {
+    const int jj = j0 + tid;
+    sj[tid] = jj < mj ? (cand ? cand[jj] : jj) : -1;
+  }
+  __syncthreads();
+  f64x4 accD[4], accZ[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    accD[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    accZ[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  }
+  for (int i0 = 0; i0 < d.n; i0 += SS_ROWS) {
+    for (int e = tid; e < SS_ROWS * SS_TILE; e += 256) {
+      const int c = e / SS_ROWS, r = e % SS_ROWS, i = i0 + r;
+      const int jc = sj[c], kc = k0 + c;
+      sA[r * SS_LD + c] = (i < d.n && jc >= 0) ? d.X[(long long)jc * d.ld + i] : 0.0;
+      sB[r * SS_LD + c] = (i < d.n && kc < d.m) ? d.X[(long long)kc * d.ld + i] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < SS_ROWS / 4; ++kk) {
+      const int r = 4 * kk + (lane >> 4);
+      const double a = sA[r * SS_LD + 16 * wave + (lane & 15)];
+      const double aa = fabs(a);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double x = sB[r * SS_LD + 16 * t + (lane & 15)];
+        const double sg = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
+        const double zr = x == 0.0 ? 1.0 : 0.0;
+        accD[t] = mfma_f64(a, sg, accD[t]);
+        accZ[t] = mfma_f64(aa, zr, accZ[t]);
+      }
+    }
+    __syncthreads();
+  }
+  double2 *out = DZ + d.pair_off;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = k0 + 16 * t + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = sj[16 * wave + (lane >> 4) + 4 * q];
+      if (j >= 0 && k < d.m) out[(long long)j * d.m + k] = make_double2(accD[t][q], accZ[t][q]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- segments
 // Workgroup = (preserved column j, one part of the k range); its waves take
 // the next k from an LDS counter.  For every (j, k) and lambda_t it writes
 //   V[(t m + j) m + k] = v_k,  E[...] = e_jk,  R[...] = median row (-1 for 0).
 //
 // Per segment:
-//  1. a division-free pass sums the weights of the negative and of the
-//     non-positive ratios approximately.  Where those sums prove, with a
-//     rigorous error margin, that 0 minimises g_jk, v_k = 0 and e_jk is the
-//     R64 column mass of k (|x_ik - fl(0 x_ij)| = |x_ik|); where they prove
-//     the side of 0 the minimiser lies on, that side is taken.  Otherwise an
-//     exact pass (128-bit sums) decides.
+//  1. the sign sums D_jk, Zr_jk (k_signsum_batch) decide, with a rigorous
+//     error margin, whether 0 minimises g_jk -- then v_k = 0 and e_jk is the
+//     R64 column mass of k (|x_ik - fl(0 x_ij)| = |x_ik|) -- or on which side
+//     of 0 the minimiser lies.  Otherwise an exact pass (128-bit sums)
+//     decides.
 //  2. The ratios of 128 rows drawn once per j with probability proportional
 //     to |x_ij| estimate where the weighted median lies: a key window.
-//  3. One exact pass sums the weight below the window and builds an exact
-//     bucketed histogram of the window's weights in LDS, recording the rows
-//     that fall in the window; the bucket that reaches the target is
-//     finished by sorting its few elements.
+//  3. One exact pass sums the weight below the window and appends the
+//     window's elements (key, row) to an LDS list, which is sorted and
+//     scanned exactly.
 //  Whatever the window does not settle goes to the general rounds.
 constexpr int SEG_WAVES = 4;
 constexpr int SAMPLE_ROWS = 128;
@@ -561,7 +650,8 @@ __device__ __forceinline__ ExactSides exact_sides(const SegIO &s) {
 // R and segflags are this problem's slices.
 __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, int m, long long ld,
                                          const ColInfo *__restrict__ ci, const double *__restrict__ lam, int L,
-                                         int j, int kbeg, int kend, double *__restrict__ V,
+                                         const double2 *__restrict__ DZ, int j, int kbeg, int kend,
+                                         double *__restrict__ V,
                                          double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
                                          unsigned char *smem) {
   const int T = (n + 63) >> 6;
@@ -641,33 +731,12 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     const SegIO s{X + (long long)k * ld, sxj, n, T, Tp, cj.e0, lane};
     const double Wk = ck.W;
 
-    // 1. approximate weights of negative (A) and non-positive (B) ratios, no
-    // division: signs decide.  |x_ik / x_ij| can underflow to 0 only if the
-    // exponent fields differ by more than 1000; the column ranges rule that
-    // out for the whole segment in the usual case.
+    // 1. sign sums.  |x_ik / x_ij| can underflow to 0 only if the exponent
+    // fields differ by more than 1000: the column ranges rule that out for the
+    // whole segment in the usual case, else the exact pass decides.
     const bool maybe_tiny = ck.nnz > 0 && cj.nnz > 0 && ck.bemin - cj.bemax < -1000;
-    double accA = 0.0, accB = 0.0;
-    int unc = 0;
-#pragma unroll 8
-    for (int t = 0; t < T; ++t) {
-      const int i = lane + 64 * t;
-      const double a = sxj[i];
-      const double b = s.xk[i < n ? i : n - 1];
-      const double w = fabs(a);
-      const bool bz = b == 0.0;
-      const unsigned ha = (unsigned)(__double_as_longlong(a) >> 32), hb = (unsigned)(__double_as_longlong(b) >> 32);
-      const bool opp = ((ha ^ hb) >> 31) != 0;
-      if (maybe_tiny) {
-        const int gap = (int)((hb >> 20) & 0x7ff) - (int)((ha >> 20) & 0x7ff);
-        unc |= (a != 0.0 && !bz && gap < -1000) ? 1 : 0;
-      }
-      // rows i >= n have a == 0 in the padded LDS copy: weight 0
-      accA = accA + ((opp && !bz) ? w : 0.0);
-      accB = accB + ((opp || bz) ? w : 0.0);
-    }
-    accA = wave_sum_dbl(accA);
-    accB = wave_sum_dbl(accB);
-    if (maybe_tiny) unc = wave_max_int(unc);
+    const double2 dz = DZ[(long long)j * m + k];
+    const bool unc = maybe_tiny || !isfinite(dz.x) || !isfinite(dz.y);
 
     bool have_exact = false;
     ExactSides ex;
@@ -676,12 +745,13 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     for (int t = 0; t < L; ++t) {
       const double lamt = lam[t];
       // decision margin 2^-32 (W + lambda): far above the rounding error of
-      // the approximate sums (at most ~n 2^-53 of W)
+      // the sign sums (at most ~n 2^-52 of W, plus n 2^-1022 should the
+      // matrix unit flush subnormal terms: hence the floor on M)
       const double M = 0x1p-32 * (Wd + lamt);
-      const double d1 = Wd + lamt - 2.0 * accA;     // >= 0  <=>  2A <= W + lambda
-      const double d2 = 2.0 * accB + lamt - Wd;     // >= 0  <=>  W <= 2B + lambda
+      const double d1 = lamt + dz.y + dz.x;        // >= 0  <=>  2A <= W + lambda
+      const double d2 = lamt + dz.y - dz.x;        // >= 0  <=>  W <= 2B + lambda
       int side;                                    // 0: v = 0, 1: negative, 2: positive, 3: unknown
-      if (unc) side = 3;
+      if (unc || !(M >= 0x1p-1000)) side = 3;
       else if (d1 > M && d2 > M) side = 0;
       else if (d1 < -M) side = 1;
       else if (d2 < -M) side = 2;
@@ -803,8 +873,9 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int ksplit,
             int *__restrict__ counter, const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
-            double *__restrict__ V, double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
-            const int *__restrict__ cand, const int *__restrict__ gate, int gate_on) {
+            const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
+            int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand,
+            const int *__restrict__ gate, int gate_on) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_item;
   if (gate && *gate != gate_on) return;
@@ -826,7 +897,8 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
       it.kend = min(m0, it.kbeg + kchunk);
     }
     const ProbDesc d = P[it.b];
-    seg_item(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, it.j, it.kbeg, it.kend,
+    seg_item(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j, it.kbeg,
+             it.kend,
              V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, smem);
   }
 }

@@ -174,9 +174,9 @@ static int check_problem(const l1line_problem &p) {
 //   data: ColInfo, segflags, V, E, R, Z, zflag
 struct BatchLayout {
   int B, nitems, ksplit, nmax, Lmax;
-  long long total_cols, total_z, total_out, total_ws, total_lam;
-  size_t o_desc, o_colstart, o_zstart, o_ostart, o_lam, o_items, o_counter, meta_bytes;
-  size_t o_ci, o_segflags, o_V, o_E, o_R, o_Z, o_zflag, bytes;
+  long long total_cols, total_z, total_out, total_ws, total_lam, total_pairs, total_tiles;
+  size_t o_desc, o_colstart, o_zstart, o_ostart, o_tstart, o_lam, o_items, o_counter, meta_bytes;
+  size_t o_ci, o_segflags, o_DZ, o_V, o_E, o_R, o_Z, o_zflag, bytes;
 };
 
 static void layout_sizes(BatchLayout &Ly) {
@@ -186,12 +186,14 @@ static void layout_sizes(BatchLayout &Ly) {
   Ly.o_colstart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_zstart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_ostart = take(sizeof(int) * (Ly.B + 1));
+  Ly.o_tstart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_lam = take(sizeof(double) * Ly.total_lam);
   Ly.o_items = take(sizeof(WorkItem) * (Ly.ksplit ? 0 : Ly.nitems));
   Ly.o_counter = take(sizeof(int) * 4);
   Ly.meta_bytes = off;
   Ly.o_ci = take(sizeof(ColInfo) * Ly.total_cols);
   Ly.o_segflags = take(sizeof(int) * Ly.total_cols);
+  Ly.o_DZ = take(2 * sizeof(double) * Ly.total_pairs);
   Ly.o_V = take(sizeof(double) * Ly.total_ws);
   Ly.o_E = take(sizeof(double) * Ly.total_ws);
   Ly.o_R = take(sizeof(int) * Ly.total_ws);
@@ -245,11 +247,15 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     Ly.total_out += p.L;
     Ly.total_ws += p.L * p.m * p.m;
     Ly.total_lam += p.L;
+    Ly.total_pairs += p.m * p.m;
+    const int64_t mj = (ro.cand && B == 1) ? ro.ncand : p.m;
+    Ly.total_tiles += ((mj + SS_TILE - 1) / SS_TILE) * ((p.m + SS_TILE - 1) / SS_TILE);
     Ly.nmax = std::max<int>(Ly.nmax, (int)p.n);
     Ly.Lmax = std::max<int>(Ly.Lmax, (int)p.L);
     total_cost += (double)p.n * (double)p.m * (double)p.m;
   }
-  if (Ly.total_cols > (1ll << 30) || Ly.total_z > (1ll << 30) || Ly.total_out > (1ll << 30))
+  if (Ly.total_cols > (1ll << 30) || Ly.total_z > (1ll << 30) || Ly.total_out > (1ll << 30) ||
+      Ly.total_tiles > (1ll << 30))
     return L1LINE_EINVAL;
 
   // work items: split every problem's k range so the whole batch offers
@@ -294,8 +300,9 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   memset(h, 0, Ly.meta_bytes);
   ProbDesc *hd = (ProbDesc *)(h + Ly.o_desc);
   int *hcol = (int *)(h + Ly.o_colstart), *hz = (int *)(h + Ly.o_zstart), *ho = (int *)(h + Ly.o_ostart);
+  int *ht = (int *)(h + Ly.o_tstart);
   double *hlam = (double *)(h + Ly.o_lam);
-  long long col = 0, z = 0, out = 0, wsoff = 0, lamoff = 0;
+  long long col = 0, z = 0, out = 0, wsoff = 0, lamoff = 0, pairoff = 0, tiles = 0;
   for (int64_t b = 0; b < B; ++b) {
     const l1line_problem &p = probs[b];
     ProbDesc &q = hd[b];
@@ -309,6 +316,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     q.out_off = (int)out;
     q.ws_off = wsoff;
     q.z_off = z;
+    q.pair_off = pairoff;
     q.Vout = p.V;
     q.Jout = (long long *)p.J;
     q.OBJout = p.OBJ;
@@ -318,21 +326,26 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     hcol[b] = (int)col;
     hz[b] = (int)z;
     ho[b] = (int)out;
+    ht[b] = (int)tiles;
     for (int64_t t = 0; t < p.L; ++t) hlam[lamoff + t] = p.lambdas[t];
     col += p.m;
     z += p.L * p.m;
     out += p.L;
     wsoff += p.L * p.m * p.m;
     lamoff += p.L;
+    pairoff += p.m * p.m;
+    const int64_t mj = (ro.cand && B == 1) ? ro.ncand : p.m;
+    tiles += ((mj + SS_TILE - 1) / SS_TILE) * ((p.m + SS_TILE - 1) / SS_TILE);
   }
   hcol[B] = (int)col;
+  ht[B] = (int)tiles;
   hz[B] = (int)z;
   ho[B] = (int)out;
   if (!items.empty()) memcpy(h + Ly.o_items, items.data(), sizeof(WorkItem) * items.size());
 
   const ProbDesc *dP = (const ProbDesc *)(d + Ly.o_desc);
   const int *dcol = (const int *)(d + Ly.o_colstart), *dz = (const int *)(d + Ly.o_zstart),
-            *dout = (const int *)(d + Ly.o_ostart);
+            *dout = (const int *)(d + Ly.o_ostart), *dtile = (const int *)(d + Ly.o_tstart);
   const double *dlam = (const double *)(d + Ly.o_lam);
   const WorkItem *ditems = Ly.ksplit ? nullptr : (const WorkItem *)(d + Ly.o_items);
   int *dcounter = (int *)(d + Ly.o_counter);
@@ -340,6 +353,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   int *dsegflags = (int *)(d + Ly.o_segflags);
   double *dV = (double *)(d + Ly.o_V), *dE = (double *)(d + Ly.o_E), *dZ = (double *)(d + Ly.o_Z);
   int *dR = (int *)(d + Ly.o_R), *dzflag = (int *)(d + Ly.o_zflag);
+  double2 *dDZ = (double2 *)(d + Ly.o_DZ);
 
   uint64_t key = fnv1a(h, Ly.meta_bytes, 1469598103934665603ull);
   key = fnv1a(&tp, sizeof tp, key);
@@ -379,6 +393,11 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
                        (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
   }
+  {
+    ProfScope ps(ctx, ls, "signsum");
+    hipLaunchKernelGGL(k_signsum_batch, dim3((unsigned)Ly.total_tiles), dim3(256), 0, ls, dP, dtile, (int)B,
+                       (B == 1) ? ro.cand : nullptr, ro.ncand, dDZ, ro.gate, ro.gate_on);
+  }
   if (only_seg_ms) {
     HIP_TRY(hipEventCreate(&t0));
     HIP_TRY(hipEventCreate(&t1));
@@ -387,7 +406,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   {
     ProfScope ps(ctx, ls, "fit_seg");
     hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
-                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dV, dE, dR, dsegflags, ro.cand, ro.gate,
+                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand, ro.gate,
                        ro.gate_on);
   }
   if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));

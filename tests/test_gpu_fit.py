@@ -141,6 +141,21 @@ def test_extreme_magnitudes(ctx, scale_exp):
     assert_path_equal(gpu_path(ctx, X, lams), O.fit_path(X, lams), f"2^{scale_exp}")
 
 
+def test_underflowing_ratios(ctx):
+    # column 2 sits near the bottom of the subnormal range, column 5 just
+    # above it: many of x_i2 / x_ij underflow to 0 (they join the zero block),
+    # so the sign sums of those pairs must be overruled by the exact pass
+    X = wl.random_small(11, 300, 8)
+    X[:, 2] *= 2.0 ** -1072
+    X[:, 5] *= 2.0 ** -1000
+    X = np.asfortranarray(X)
+    mass = float(np.abs(X).sum(0).max())
+    # lambda > 0 keeps the tiny preserved columns at v = 0 (their ratios overflow)
+    lams = np.array([0.05 * mass, 0.4 * mass])
+    _say("case underflowing ratios")
+    assert_path_equal(gpu_path(ctx, X, lams), O.fit_path(X, lams), "underflow")
+
+
 def test_padded_leading_dimension(ctx):
     X = wl.random_small(9, 150, 11, zero_frac=0.05)
     lams = np.array([0.0, 2.0, 20.0])
