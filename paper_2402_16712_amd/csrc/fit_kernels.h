@@ -180,10 +180,12 @@ __device__ __forceinline__ void take_sample(bool c, int pri, uint64_t key, int t
 
 // Per-wave LDS area: the elements (key, row) that fall in the key window of
 // the exact pass, and a 64-entry compaction buffer.
+// Per-wave LDS: the <= 64 final candidates of the selection rounds, and the
+// window list (keys and rows, capacity chosen per launch: WIN_CAP for single
+// penalties, PATH_CAP for paths when the LDS allows).
 constexpr int WIN_CAP = 512;
+constexpr int PATH_CAP = 1024;
 struct WaveScratch {
-  uint64_t wkeys[WIN_CAP];
-  unsigned short wrows[WIN_CAP];
   uint64_t ckey[64];
   int crow[64];
 };
@@ -397,19 +399,15 @@ __device__ __forceinline__ void wave_select_rounds(const SegIO &s, const Src &sr
 }
 
 // --------------------------------------------------- sorting the window list
-// The window list (nlist <= WIN_CAP entries, row order) is padded to a power
-// of two N >= 64, sorted in place in LDS by (key, row) with a bitonic network
-// (each lane handles N/128 compare-exchanges per stage), then read E = N/64
-// consecutive elements per lane and its exact prefix weights scanned from
-// Slo: the first element whose prefix reaches tau is the answer.
-__device__ __forceinline__ void wave_sort_list(const SegIO &s, WaveScratch *ws, int nlist, u128 Slo, u128 tau,
-                                               uint64_t &okey, int &orow, int &err) {
-  const int lane = s.lane;
+// The window list (nlist entries, row order) is padded to a power of two
+// N >= 64 with KEY_NONE and sorted by (key, row) with a bitonic network in
+// LDS (each lane handles N/128 compare-exchanges per stage).  Returns N.
+__device__ __forceinline__ int wave_sort_lds(uint64_t *lk, unsigned short *lr, int nlist, int lane) {
   int N = 64;
   while (N < nlist) N <<= 1;
   for (int e = nlist + lane; e < N; e += 64) {
-    ws->wkeys[e] = KEY_NONE;
-    ws->wrows[e] = 0xFFFF;
+    lk[e] = KEY_NONE;
+    lr[e] = 0xFFFF;
   }
   wave_lds_sync();
   for (int size = 2; size <= N; size <<= 1) {
@@ -417,48 +415,73 @@ __device__ __forceinline__ void wave_sort_list(const SegIO &s, WaveScratch *ws, 
       for (int pidx = lane; pidx < (N >> 1); pidx += 64) {
         const int e = ((pidx & ~(stride - 1)) << 1) | (pidx & (stride - 1));
         const int f = e + stride;
-        const uint64_t ke = ws->wkeys[e], kf = ws->wkeys[f];
-        const unsigned re = ws->wrows[e], rf = ws->wrows[f];
+        const uint64_t ke = lk[e], kf = lk[f];
+        const unsigned re = lr[e], rf = lr[f];
         const bool up = (e & size) == 0;
         const bool gt = ke > kf || (ke == kf && re > rf);
         const bool lt = ke < kf || (ke == kf && re < rf);
         if (up ? gt : lt) {
-          ws->wkeys[e] = kf;
-          ws->wkeys[f] = ke;
-          ws->wrows[e] = (unsigned short)rf;
-          ws->wrows[f] = (unsigned short)re;
+          lk[e] = kf;
+          lk[f] = ke;
+          lr[e] = (unsigned short)rf;
+          lr[f] = (unsigned short)re;
         }
       }
       wave_lds_sync();
     }
   }
-  const int E = N >> 6;
-  u128 tot = 0;
+  return N;
+}
+
+// Exact weights of the sorted list: lane l owns the E = N/64 consecutive
+// entries [E l, E l + E); tot = their exact weight, incl = inclusive scan of
+// tot over the lanes.
+__device__ __forceinline__ void wave_list_sums(const SegIO &s, const uint64_t *lk, const unsigned short *lr, int E,
+                                               u128 &tot, u128 &incl) {
+  tot = 0;
   for (int q = 0; q < E; ++q) {
-    const int e = E * lane + q;
-    const bool valid = ws->wkeys[e] != KEY_NONE;
-    tot += seg_weight(s, valid ? (int)ws->wrows[e] : 0, valid);
+    const int e = E * s.lane + q;
+    const bool valid = lk[e] != KEY_NONE;
+    tot += seg_weight(s, valid ? (int)lr[e] : 0, valid);
   }
-  const u128 incl = wave_incl_scan_u128(tot, lane);
-  u128 run = Slo + incl - tot;
-  int ehit = -1;
-  for (int q = 0; q < E; ++q) {
-    const int e = E * lane + q;
-    const bool valid = ws->wkeys[e] != KEY_NONE;
-    run += seg_weight(s, valid ? (int)ws->wrows[e] : 0, valid);
-    if (ehit < 0 && valid && run >= tau) ehit = e;
+  incl = wave_incl_scan_u128(tot, s.lane);
+}
+
+// Lane-parallel resolution: every lane with a target (active) finds the first
+// list entry whose exact prefix weight, counted from Slo (the weight of every
+// element below the list), reaches its tau.  A binary search over the lanes'
+// inclusive sums finds the owning lane, a walk over its entries the element.
+// hit = false when tau lies outside (Slo, Slo + weight of the list].
+__device__ __forceinline__ void wave_resolve(const SegIO &s, const uint64_t *lk, const unsigned short *lr, int E,
+                                             u128 Slo, u128 tot, u128 incl, bool active, u128 tau,
+                                             uint64_t &okey, int &orow, bool &hit) {
+  const u128 wall = shfl_u128(incl, 63);
+  const bool inwin = active && tau > Slo && tau <= Slo + wall;
+  int lo = 0, hi = 63;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const u128 im = shfl_u128(incl, mid);
+    if (Slo + im >= tau) hi = mid;
+    else lo = mid + 1;
   }
-  const uint64_t hit = __ballot(ehit >= 0);
-  if (!hit) {
-    err |= SEG_INTERNAL;
-    okey = KEY_NONE;
-    orow = -1;
-    return;
+  const u128 totc = shfl_u128(tot, lo), inclc = shfl_u128(incl, lo);
+  hit = false;
+  if (inwin) {
+    u128 run = Slo + inclc - totc;
+    for (int q = 0; q < E; ++q) {
+      const int e = E * lo + q;
+      const uint64_t key = lk[e];
+      const bool valid = key != KEY_NONE;
+      run += seg_weight(s, valid ? (int)lr[e] : 0, valid);
+      if (valid && run >= tau) {
+        okey = key;
+        orow = (int)lr[e];
+        hit = true;
+        break;
+      }
+    }
   }
-  const int e = uni_int(__shfl(ehit, __builtin_ctzll(hit)));
-  okey = ws->wkeys[e];
-  orow = (int)ws->wrows[e];
-  wave_lds_sync();
 }
 
 // e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0)
@@ -611,8 +634,9 @@ constexpr int SAMPLE_ROWS = 128;
 __host__ __device__ constexpr size_t seg_sxj_bytes(int n) {
   return ((size_t)((n + 63) / 64) * 64 * 8 + 15) / 16 * 16;
 }
-__host__ __device__ constexpr size_t seg_lds_bytes(int n, int L) {
-  return seg_sxj_bytes(n) + SAMPLE_ROWS * 4 + (size_t)L * 16 + SEG_WAVES * sizeof(WaveScratch) + 16;
+__host__ __device__ constexpr size_t seg_lds_bytes(int n, int L, int lcap) {
+  return seg_sxj_bytes(n) + SAMPLE_ROWS * 4 + (size_t)L * 16 +
+         SEG_WAVES * (sizeof(WaveScratch) + (size_t)lcap * (sizeof(uint64_t) + sizeof(unsigned short))) + 16;
 }
 
 // exact A (negative ratios), B (non-positive), counts, one sample per side
@@ -653,13 +677,15 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
                                          const double2 *__restrict__ DZ, int j, int kbeg, int kend,
                                          double *__restrict__ V,
                                          double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
-                                         unsigned char *smem) {
+                                         int lcap, unsigned char *smem) {
   const int T = (n + 63) >> 6;
   double *sxj = (double *)smem;                     // T*64 entries, zero padded
   int *srow = (int *)(smem + seg_sxj_bytes(n));
   u128 *slam = (u128 *)(srow + SAMPLE_ROWS);
   WaveScratch *wsc = (WaveScratch *)(slam + L);
-  int *knext = (int *)(wsc + SEG_WAVES);
+  uint64_t *lkeys = (uint64_t *)(wsc + SEG_WAVES);
+  unsigned short *lrows = (unsigned short *)(lkeys + (size_t)SEG_WAVES * lcap);
+  int *knext = (int *)(lrows + (size_t)SEG_WAVES * lcap);
 
   const ColInfo cj = ci[j];
   const double *xjg = X + (long long)j * ld;
@@ -705,6 +731,8 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
   __syncthreads();
 
   WaveScratch *ws = wsc + wave;
+  uint64_t *lk = lkeys + (size_t)wave * lcap;
+  unsigned short *lr = lrows + (size_t)wave * lcap;
   const long long mm = (long long)m * m;
   const double Wd = cj.W;
   int Tp = 1;
@@ -740,8 +768,12 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 
     bool have_exact = false;
     ExactSides ex;
-    int prev_row = -2;
-    double prev_e = 0.0;
+    const u128 W = cj.wfix;
+    // (a) the side of every penalty: v_k = 0, or the minimiser is negative
+    // (1) or positive (2).  A <= B makes the nonzero side the same for every
+    // penalty of the segment.
+    uint64_t nz0 = 0, nz1 = 0;                     // bit t: v_k != 0 at penalty t
+    int sd = 0;
     for (int t = 0; t < L; ++t) {
       const double lamt = lam[t];
       // decision margin 2^-32 (W + lambda): far above the rounding error of
@@ -750,36 +782,75 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       const double M = 0x1p-32 * (Wd + lamt);
       const double d1 = lamt + dz.y + dz.x;        // >= 0  <=>  2A <= W + lambda
       const double d2 = lamt + dz.y - dz.x;        // >= 0  <=>  W <= 2B + lambda
-      int side;                                    // 0: v = 0, 1: negative, 2: positive, 3: unknown
+      int side;
       if (unc || !(M >= 0x1p-1000)) side = 3;
       else if (d1 > M && d2 > M) side = 0;
       else if (d1 < -M) side = 1;
       else if (d2 < -M) side = 2;
       else side = 3;
-      const u128 W = cj.wfix, lamf = slam[t];
-      const u128 WpL = W + lamf;
       if (side == 3) {
         if (!have_exact) {
           ex = exact_sides(s);
           have_exact = true;
         }
+        const u128 lamf = slam[t], WpL = W + lamf;
         side = ((ex.A << 1) <= WpL && W <= (ex.B << 1) + lamf) ? 0 : ((ex.A << 1) > WpL ? 1 : 2);
       }
+      if (side) {
+        sd = side;
+        if (t < 64) nz0 |= 1ull << t;
+        else nz1 |= 1ull << (t - 64);
+      }
+    }
+    if ((nz0 | nz1) == 0) {
+      // v_k = 0 at every penalty: e_jk = R64 sum of |x_ik|
+      for (int t = lane; t < L; t += 64) {
+        V[t * mm + base] = 0.0;
+        E[t * mm + base] = Wk;
+        R[t * mm + base] = -1;
+      }
+      continue;
+    }
+    const bool neg = sd == 1;
+    const uint64_t klo0 = neg ? 0ull : KEY_ZERO, khi0 = neg ? KEY_ZERO - 1 : KEY_NONE - 1;
+    uint64_t sa = seg_key(s, srow[lane]), sb = seg_key(s, srow[lane + 64]);
+    wave_sort2(sa, sb, lane);
+    int prev_row = -2;
+    double prev_e = 0.0;
+    // penalties in groups of 64, lane l holding the target of penalty 64 g + l
+    for (int g = 0; 64 * g < L; ++g) {
+      const uint64_t nzg = g ? nz1 : nz0;
+      const int tl = 64 * g + lane;
+      const bool act = ((nzg >> lane) & 1ull) != 0;
+      // negative side: first S_p > (W + lambda)/2; positive: first S_p >= (W - lambda)/2
+      double q = 2.0;
+      if (act) {
+        const double lamt = lam[tl];
+        q = (neg ? 0.5 * (Wd + lamt) : 0.5 * (Wd - lamt)) / Wd;
+      }
+      // window bounds on the targets' weight fractions (positive doubles
+      // order as their bit patterns)
+      const double qmin = __longlong_as_double((long long)wave_min_u64((uint64_t)__double_as_longlong(fmax(q, 0.0))));
+      const double qmax =
+          __longlong_as_double((long long)wave_max_u64((uint64_t)__double_as_longlong(act ? fmax(q, 0.0) : 0.0)));
       uint64_t okey = KEY_NONE;
       int orow = -1;
-      if (side != 0) {
-        const bool neg = side == 1;
-        // negative side: first S_p > (W + lambda)/2; positive: first S_p >= (W - lambda)/2
-        const u128 tau = neg ? (WpL >> 1) + 1 : (W - lamf + 1) >> 1;
-        const uint64_t klo0 = neg ? 0ull : KEY_ZERO, khi0 = neg ? KEY_ZERO - 1 : KEY_NONE - 1;
-
-        // 2. window from the weighted sample of rows
-        const double q = (neg ? 0.5 * (Wd + lamt) : 0.5 * (Wd - lamt)) / Wd;
-        uint64_t sa = seg_key(s, srow[lane]), sb = seg_key(s, srow[lane + 64]);
-        wave_sort2(sa, sb, lane);
+      bool hit = false;
+      // the ratios of the weighted row sample bracket the targets: a key
+      // window; one exact pass lists the window's elements, one sort serves
+      // every penalty.  A window too wide for the list is retried per penalty.
+      for (int pass = 0; nzg && pass <= 64; ++pass) {
+        double wlo = qmin, whi = qmax;
+        bool mine = act;
+        if (pass > 0) {
+          const int t = pass - 1;
+          if (!((nzg >> t) & 1ull) || __shfl((int)hit, t)) continue;
+          wlo = whi = __shfl(q, t);
+          mine = lane == t;
+        }
         constexpr double WDELTA = 0.12;
-        const int ilo = (int)floor((q - WDELTA) * SAMPLE_ROWS) - 1;
-        const int ihi = (int)ceil((q + WDELTA) * SAMPLE_ROWS);
+        const int ilo = (int)floor((wlo - WDELTA) * SAMPLE_ROWS) - 1;
+        const int ihi = (int)ceil((whi + WDELTA) * SAMPLE_ROWS);
         uint64_t plo = klo0, phi = khi0;
         if (ilo >= 0 && ilo < SAMPLE_ROWS) {
           const uint64_t v = uni_u64(shfl_u64((ilo & 1) ? sb : sa, ilo >> 1));
@@ -792,10 +863,10 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         if (plo > khi0) plo = khi0;
         if (phi < plo) phi = plo;
 
-        // 3. exact pass: weight and count at or below the window; the window's
-        // elements go to the LDS list (in row order)
+        // exact pass: weight at or below the window; the window's elements
+        // go to the LDS list (in row order)
         u128 slo128 = 0;
-        int nwin = 0, clo = 0;
+        int nwin = 0;
 #pragma unroll 2
         for (int tt = 0; tt < T; ++tt) {
           const int i = lane + 64 * tt;
@@ -804,58 +875,89 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           const bool le_lo = valid && key <= plo;
           const bool inwin = valid && key > plo && key <= phi;
           slo128 += le_lo ? seg_weight(s, i, true) : (u128)0;
-          clo += le_lo ? 1 : 0;
           const uint64_t wm = __ballot(inwin);
           const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
           nwin += __builtin_popcountll(wm);
-          if (inwin && pos < WIN_CAP) {
-            ws->wkeys[pos] = key;
-            ws->wrows[pos] = (unsigned short)i;
+          if (inwin && pos < lcap) {
+            lk[pos] = key;
+            lr[pos] = (unsigned short)i;
           }
         }
         const u128 Slw = wave_sum_u128(slo128);
-        const int Clw = wave_sum_int(clo);
         nwin = uni_int(nwin);
         wave_lds_sync();
-        bool settled = false;
-        if (nwin <= WIN_CAP && Slw < tau) {
-          const ListSrc ls{s, Slw, Clw, ws->wkeys, ws->wrows, nwin};
-          // exact weight of the window
-          u128 wwin = 0;
-          for (int e = lane; e < nwin; e += 64) wwin += seg_weight(s, (int)ws->wrows[e], true);
-          wwin = wave_sum_u128(wwin);
-          if (tau <= Slw + wwin) {
-            wave_sort_list(s, ws, nwin, Slw, tau, okey, orow, err);
-            (void)ls;
-            settled = true;
-          }
+        if (nwin > lcap) {
+          // the list cannot hold the window: after the shared window, retry
+          // each penalty with its own; a single penalty goes to the rounds
+          if (pass == 0 && __builtin_popcountll(nzg) == 1) break;
+          continue;
         }
-        if (!settled) {
-          // the window missed (or overflowed): rounds over the whole side
-          if (!have_exact) {
-            ex = exact_sides(s);
-            have_exact = true;
-          }
-          const ColSrc cs{s, (u128)0, 0};
-          wave_select_rounds(s, cs, klo0, khi0, neg ? (u128)0 : ex.B, neg ? ex.A : W, neg ? 0 : ex.N + ex.Z,
-                             neg ? ex.N : ex.NV, tau, ws, okey, orow, err);
+        const int N = wave_sort_lds(lk, lr, nwin, lane);
+        u128 tot, incl;
+        wave_list_sums(s, lk, lr, N >> 6, tot, incl);
+        const u128 lamf = act ? slam[tl] : (u128)0;
+        const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
+        uint64_t k2 = KEY_NONE;
+        int r2 = -1;
+        bool h2 = false;
+        wave_resolve(s, lk, lr, N >> 6, Slw, tot, incl, mine && !hit, tau, k2, r2, h2);
+        if (h2) {
+          okey = k2;
+          orow = r2;
+          hit = true;
+        }
+        wave_lds_sync();
+        // the shared window held: the targets it missed go to the rounds
+        if (pass == 0) break;
+      }
+
+      // targets the windows missed: rounds over the whole side
+      uint64_t left = __ballot(act && !hit);
+      while (left) {
+        const int t = __builtin_ctzll(left);
+        left &= left - 1;
+        if (!have_exact) {
+          ex = exact_sides(s);
+          have_exact = true;
+        }
+        const u128 lamf = slam[64 * g + t];
+        const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
+        uint64_t k2 = KEY_NONE;
+        int r2 = -1;
+        const ColSrc cs{s, (u128)0, 0};
+        wave_select_rounds(s, cs, klo0, khi0, neg ? (u128)0 : ex.B, neg ? ex.A : W, neg ? 0 : ex.N + ex.Z,
+                           neg ? ex.N : ex.NV, tau, ws, k2, r2, err);
+        if (lane == t) {
+          okey = k2;
+          orow = r2;
         }
       }
-      const double v = (orow >= 0) ? ratio_of_key(okey) : 0.0;
-      double e;
-      if (orow < 0) {
-        e = Wk;                                      // R64 sum of |x_ik|
-      } else if (orow == prev_row) {
-        e = prev_e;
-      } else {
-        e = __shfl(wave_residual(s, v), 0);
-      }
-      prev_row = orow;
-      prev_e = e;
-      if (lane == 0) {
-        V[t * mm + base] = v;
-        E[t * mm + base] = e;
-        R[t * mm + base] = orow;
+
+      // residuals, reused while the selected row repeats
+      const int tend = min(L, 64 * g + 64);
+      for (int t = 64 * g; t < tend; ++t) {
+        uint64_t ok = KEY_NONE;
+        int orw = -1;
+        if ((nzg >> (t & 63)) & 1ull) {
+          ok = uni_u64(shfl_u64(okey, t & 63));
+          orw = uni_int(__shfl(orow, t & 63));
+        }
+        const double v = (orw >= 0) ? ratio_of_key(ok) : 0.0;
+        double e;
+        if (orw < 0) {
+          e = Wk;                                    // R64 sum of |x_ik|
+        } else if (orw == prev_row) {
+          e = prev_e;
+        } else {
+          e = __shfl(wave_residual(s, v), 0);
+        }
+        prev_row = orw;
+        prev_e = e;
+        if (lane == 0) {
+          V[t * mm + base] = v;
+          E[t * mm + base] = e;
+          R[t * mm + base] = orw;
+        }
       }
     }
   }
@@ -870,12 +972,12 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 // cand (optional): the preserved columns of the implicit items (item q has
 // j = cand[q / ksplit]); gate (optional): the kernel does nothing unless
 // *gate == gate_on.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int ksplit,
             int *__restrict__ counter, const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
             const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
             int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand,
-            const int *__restrict__ gate, int gate_on) {
+            const int *__restrict__ gate, int gate_on, int lcap) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_item;
   if (gate && *gate != gate_on) return;
@@ -899,7 +1001,7 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
     const ProbDesc d = P[it.b];
     seg_item(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j, it.kbeg,
              it.kend,
-             V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, smem);
+             V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap, smem);
   }
 }
 

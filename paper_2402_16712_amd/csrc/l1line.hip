@@ -370,10 +370,13 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   HIP_TRY(hipEventRecord(ctx->stage_done, s));
   ctx->stage_pending = true;
 
-  const size_t lds = seg_lds_bytes(Ly.nmax, Ly.Lmax);
+  // window list capacity: the larger path list where the LDS allows it
+  const size_t lds_max = seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS, WIN_CAP);
+  const int lcap = (Ly.Lmax > 1 && seg_lds_bytes(Ly.nmax, Ly.Lmax, PATH_CAP) <= lds_max) ? PATH_CAP : WIN_CAP;
+  const size_t lds = seg_lds_bytes(Ly.nmax, Ly.Lmax, lcap);
   if (!lds_attr_set) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS)));
+                                (int)lds_max));
     lds_attr_set = true;
   }
   const int grid_seg = std::max(1, std::min(Ly.nitems, tp.blocks_per_cu * ctx->num_cu));
@@ -407,7 +410,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     ProfScope ps(ctx, ls, "fit_seg");
     hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
                        Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand, ro.gate,
-                       ro.gate_on);
+                       ro.gate_on, lcap);
   }
   if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
   {

@@ -191,6 +191,30 @@ def test_overflowing_ratio_reports_erange(ctx):
     assert g["status"] == -4
 
 
+def test_path_many_unsorted_penalties(ctx):
+    # 100 penalties (two groups of 64 targets) in random order, with repeats
+    X = wl.random_small(12, 700, 12, zero_frac=0.02)
+    mass = float(np.abs(X).sum(0).max())
+    rng = np.random.default_rng(5)
+    lams = np.concatenate([rng.uniform(0.0, 0.6 * mass, 90), [0.0, 0.0, mass, 0.3 * mass],
+                           np.full(6, 0.05 * mass)])
+    rng.shuffle(lams)
+    _say("case 100 unsorted penalties")
+    assert_path_equal(gpu_path(ctx, X, lams), O.fit_path(X, lams), "L100")
+
+
+@pytest.mark.parametrize("n", [1500, 3000, 6000])
+def test_path_wide_windows(ctx, n):
+    # strongly correlated columns spread the penalties' targets over much of
+    # a segment: the shared window overflows the list and the penalties are
+    # retried one by one (or go to the rounds when even that overflows)
+    X = wl.rank_one_matrix(n, 6, 6, 0, 20.0, 0.0, (30, n), laplace_b=0.02)
+    mass = float(np.abs(X).sum(0).max())
+    lams = wl.log_lambdas(mass, 16)
+    _say(f"case wide windows n={n}")
+    assert_path_equal(gpu_path(ctx, X, lams), O.fit_path(X, lams), f"wide{n}")
+
+
 def test_fit_matches_path_and_is_deterministic(ctx):
     p = wl.lambda_path(0, n=600, m=150, L=8)
     _say("case fit-vs-path 600x150")
