@@ -46,6 +46,9 @@ def _args():
     ap.add_argument("--legs", default="path,batch,ranked",
                     help="extra workloads reported beside the main line (comma list; '' for none)")
     ap.add_argument("--ranked-instances", type=int, default=3)
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE counter files (bench run and --calibrate-copy "
+                         "run) into profiles/traffic.json and exit")
     return ap.parse_args()
 
 
@@ -64,9 +67,11 @@ def calibrate_copy():
 
 
 def _source_hash():
+    """Hash of the sources that define the segment kernels (the counters in
+    profiles/traffic.json are only used while these are unchanged)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2402_16712_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in ("device_common.h", "fit_kernels.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -84,6 +89,44 @@ def _traffic(kernel_key):
     if not rec or rec.get("source_hash") != _source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def _pmc_per_dispatch(path, counter):
+    """Mean counter value (KiB) per dispatch of each kernel in a rocprofv3
+    counter_collection.csv."""
+    import csv
+    import collections
+    tot, disp = collections.defaultdict(float), collections.defaultdict(set)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            k = r["Kernel_Name"].split("(")[0]
+            tot[k] += float(r["Counter_Value"])
+            disp[k].add(r["Dispatch_Id"])
+    return {k: tot[k] / len(disp[k]) for k in tot}
+
+
+def pmc_summary(fetch_csv, write_csv, copyf_csv, copyw_csv):
+    """HBM bytes per launch of the segment kernels from the FETCH_SIZE and
+    WRITE_SIZE counters, each scaled by what the counter reads for a copy of
+    exactly 512 MiB (bench.py --calibrate-copy)."""
+    nbytes = 512 << 20
+    cf = _pmc_per_dispatch(copyf_csv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"] * 1024
+    cw = _pmc_per_dispatch(copyw_csv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"] * 1024
+    fs, ws = nbytes / cf, nbytes / cw
+    f = _pmc_per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = _pmc_per_dispatch(write_csv, "WRITE_SIZE")
+    kern = ("k_seg_batch", "k_signsum_batch")
+    fetch = sum(f[k] for k in kern) * 1024 * fs
+    write = sum(w[k] for k in kern) * 1024 * ws
+    rec = {"seg_2000x2000": {"kernels": list(kern), "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
+                             "write_bytes": write, "fetch_scale": fs, "write_scale": ws,
+                             "per_kernel_kib_raw": {k: {"FETCH_SIZE": f[k], "WRITE_SIZE": w[k]} for k in kern},
+                             "source_hash": _source_hash()}}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def cpu_baseline(p, lam, z_gpu, columns):
@@ -188,6 +231,9 @@ def main():
     a = _args()
     if a.calibrate_copy:
         calibrate_copy()
+        return
+    if a.pmc_summary:
+        pmc_summary(*a.pmc_summary)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",

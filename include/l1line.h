@@ -63,7 +63,7 @@ extern "C" {
 #define L1LINE_EWIDE (-6)      /* a column's nonzero magnitudes span too many binades
                                   for exact 128-bit weight sums: (highest bit - lowest
                                   bit + 1) + bitlength(#nonzeros) > 124 (device)     */
-#define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N (host check)                  */
+#define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N, or m above L1LINE_RANKER_MAX_M for the ranker (host check) */
 #define L1LINE_EINTERNAL (-8)  /* a selection exceeded its round bound (device)      */
 
 #define L1LINE_MAX_N 16384         /* rows per matrix (column j is held in LDS)   */
@@ -176,15 +176,22 @@ int l1line_tune_set(l1line_ctx ctx, const int32_t *params);
                                      W1[32][128], b1[128], W2[128][128],
                                      b2[128], W3[128], b3 (in this order)     */
 
-/* Per-column features F [m][32] (FP32, DEVICE).  Three exact "sketch" fits
- * of Algorithm 1 on 64, 128 and 256 evenly spaced rows (penalty scaled by
- * rows/n) give z~_j; with min / mean / std over j of each sketch:
- *   f0-2   (z~ - min) / (mean - min)          f3-5  log1p(z~ / min - 1)
- *   f6-8   (z~ - mean) / std                  f9    log(W_j / mean_j W_j)
- *   f10    zero fraction of column j          f11   min(lambda / W_j, 10)
- *   f12    log1p(lambda / W_j)                f13   mean of f0-2
- *   f14    max - min of f0-2                  f15   1;  f16-31 = 0
- * (W_j = column l1 mass). */
+/* Per-column features F [m][32] (FP32, DEVICE).  With D_jk = sum_i x_ij
+ * sgn(x_ik) and Zr_jk = sum_i |x_ij| [x_ik == 0] (the weight balance of the
+ * ratios x_ik / x_ij, FP64 over all rows), the segment (j, k) has v_k != 0
+ * exactly when its initial slope s_jk = |D_jk| - Zr_jk - lambda is > 0, and
+ * z_j = sum_k W_k - W_j + lambda - sum_k Delta_jk with Delta_jk >= 0 the
+ * segment's improvement over v_k = 0.  Per column j (W = column l1 mass):
+ *   A1 = sum_k s_jk, A2 = sum_k s_jk^2 / W_k, A3 = sum_k s_jk / W_k,
+ *   A4 = #{k != j : s_jk > 0}, over the k with s_jk > 0; then
+ *   f0 (W - mean W) / sd W        f1 (W - max W) / sd W     f2 log(W / mean W)
+ *   f3 zero fraction of column j  f4 min(lambda / W, 10)     f5 A4 / (m - 1)
+ *   f6, f8, f10, f12  (A_q - mean A_q) / sd A_q     (q = 1..4)
+ *   f7, f9, f11, f13  (A_q - max A_q) / sd A_q
+ *   f14 log1p(A1 / W)             f15 1;  f16-31 = 0
+ * (mean, sd, max over the m columns; 0 where sd = 0; f2 = -30, f4 = 10 and
+ * f14 = 0 for W = 0).  m <= L1LINE_RANKER_MAX_M, else ESIZE. */
+#define L1LINE_RANKER_MAX_M 65536
 int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n,
                            int64_t m, int64_t ld, double lambda, float *F,
                            void *stream);
@@ -216,8 +223,8 @@ int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2,
  *   v, j, obj, median_row, status  as l1line_fit (DEVICE)
  *   used_fallback  [1] 1 when the exhaustive search ran (DEVICE, nullable)
  *   scores         [m] the MLP scores (DEVICE, nullable)
- * Host errors: as l1line_fit, and EINVAL for K outside [1, m] or a negative
- * or non-finite threshold. */
+ * Host errors: as l1line_fit, EINVAL for K outside [1, m] or a negative or
+ * non-finite threshold, ESIZE for m > L1LINE_RANKER_MAX_M. */
 int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                       int64_t ld, double lambda, const float *params,
                       int32_t K, float margin_threshold, double *v,

@@ -545,24 +545,15 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// tstart[b] = first tile of problem b; problem b has ceil(mj / 64) x
-// ceil(m / 64) tiles with mj = ncand when cand is given (problem 0 only),
-// else m.  DZ[pair_off + j m + k] = (D_jk, Zr_jk).
-__global__ void __launch_bounds__(256)
-k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, int B,
-                const int *__restrict__ cand, int ncand, double2 *__restrict__ DZ,
-                const int *__restrict__ gate, int gate_on) {
+// One 64 x 64 output tile of the sign sums of a column-major matrix; rows j of
+// the tile are j0.. j0 + 63 of the candidate list (cand) or of 0..m-1.
+// out[j m + k] = (D_jk, Zr_jk).  Every thread of the 256-wide block calls it.
+__device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n, int m, long long ld,
+                                             const int *__restrict__ cand, int mj, int j0, int k0,
+                                             double2 *__restrict__ out) {
   __shared__ double sA[SS_ROWS * SS_LD];
   __shared__ double sB[SS_ROWS * SS_LD];
   __shared__ int sj[SS_TILE];
-  if (gate && *gate != gate_on) return;
-  const int g = blockIdx.x;
-  const int b = find_owner(tstart, B, g);
-  const ProbDesc d = P[b];
-  const int mj = cand ? ncand : d.m;
-  const int tk_count = (d.m + SS_TILE - 1) / SS_TILE;
-  const int tloc = g - tstart[b];
-  const int j0 = (tloc / tk_count) * SS_TILE, k0 = (tloc % tk_count) * SS_TILE;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (tid < SS_TILE) {
     const int jj = j0 + tid;
@@ -575,12 +566,12 @@ k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, 
     accD[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     accZ[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
   }
-  for (int i0 = 0; i0 < d.n; i0 += SS_ROWS) {
+  for (int i0 = 0; i0 < n; i0 += SS_ROWS) {
     for (int e = tid; e < SS_ROWS * SS_TILE; e += 256) {
       const int c = e / SS_ROWS, r = e % SS_ROWS, i = i0 + r;
       const int jc = sj[c], kc = k0 + c;
-      sA[r * SS_LD + c] = (i < d.n && jc >= 0) ? d.X[(long long)jc * d.ld + i] : 0.0;
-      sB[r * SS_LD + c] = (i < d.n && kc < d.m) ? d.X[(long long)kc * d.ld + i] : 0.0;
+      sA[r * SS_LD + c] = (i < n && jc >= 0) ? X[(long long)jc * ld + i] : 0.0;
+      sB[r * SS_LD + c] = (i < n && kc < m) ? X[(long long)kc * ld + i] : 0.0;
     }
     __syncthreads();
 #pragma unroll 2
@@ -599,16 +590,40 @@ k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, 
     }
     __syncthreads();
   }
-  double2 *out = DZ + d.pair_off;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int k = k0 + 16 * t + (lane & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = sj[16 * wave + (lane >> 4) + 4 * q];
-      if (j >= 0 && k < d.m) out[(long long)j * d.m + k] = make_double2(accD[t][q], accZ[t][q]);
+      if (j >= 0 && k < m) out[(long long)j * m + k] = make_double2(accD[t][q], accZ[t][q]);
     }
   }
+}
+
+// tstart[b] = first tile of problem b; problem b has ceil(mj / 64) x
+// ceil(m / 64) tiles with mj = ncand when cand is given (problem 0 only),
+// else m.  DZ[pair_off + j m + k] = (D_jk, Zr_jk).
+__global__ void __launch_bounds__(256)
+k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, int B,
+                const int *__restrict__ cand, int ncand, double2 *__restrict__ DZ,
+                const int *__restrict__ gate, int gate_on) {
+  if (gate && *gate != gate_on) return;
+  const int g = blockIdx.x;
+  const int b = find_owner(tstart, B, g);
+  const ProbDesc d = P[b];
+  const int mj = cand ? ncand : d.m;
+  const int tk_count = (d.m + SS_TILE - 1) / SS_TILE;
+  const int tloc = g - tstart[b];
+  signsum_tile(d.X, d.n, d.m, d.ld, cand, mj, (tloc / tk_count) * SS_TILE, (tloc % tk_count) * SS_TILE,
+               DZ + d.pair_off);
+}
+
+// The sign sums of one matrix, all pairs (grid: ceil(m/64)^2 tiles).
+__global__ void __launch_bounds__(256)
+k_signsum_one(const double *__restrict__ X, int n, int m, long long ld, double2 *__restrict__ DZ) {
+  const int tk_count = (m + SS_TILE - 1) / SS_TILE;
+  signsum_tile(X, n, m, ld, nullptr, m, (blockIdx.x / tk_count) * SS_TILE, (blockIdx.x % tk_count) * SS_TILE, DZ);
 }
 
 // ---------------------------------------------------------------- segments
@@ -966,42 +981,71 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 }
 
 // Persistent segment kernel: every workgroup pulls work items from a global
-// counter until none is left (items are ordered by decreasing cost).  With
-// items == nullptr the items of problem 0 are implicit: item q covers
-// j = q / ksplit and the (q mod ksplit)-th of ksplit equal k ranges.
-// cand (optional): the preserved columns of the implicit items (item q has
-// j = cand[q / ksplit]); gate (optional): the kernel does nothing unless
-// *gate == gate_on.
+// counter until none is left.  Explicit items (a batch) are ordered by
+// decreasing cost.  With items == nullptr the items of problem 0 are
+// implicit and routed by XCD: its k range is cut into SEG_XCDS * chunks
+// equal parts, XCD x owns parts [x chunks, (x + 1) chunks) and enumerates
+// them part by part, every preserved column j (or cand[jj]) within a part, so
+// the columns k that the workgroups of one XCD stream stay in its L2.
+// Workgroups are dispatched to the XCDs round-robin (blockIdx mod 8); one
+// whose XCD has no item left takes items of the next XCDs (the routing only
+// affects where data is cached, never the results).  nitems = items per XCD
+// (implicit) or in total (explicit).  gate (optional): the kernel does
+// nothing unless *gate == gate_on.
+constexpr int SEG_XCDS = 8;
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int ksplit,
+k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int chunks,
             int *__restrict__ counter, const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
             const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
-            int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand,
+            int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand, int ncand,
             const int *__restrict__ gate, int gate_on, int lcap) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int s_item;
+  __shared__ int s_item, s_tried;                  // s_tried: XCD partitions found empty
   if (gate && *gate != gate_on) return;
+  if (threadIdx.x == 0) s_tried = 0;
   while (true) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) {
+      int q = -1;
+      if (items) {
+        const int c = atomicAdd(counter, 1);
+        q = c < nitems ? c : -1;
+      } else {
+        const int home = blockIdx.x % SEG_XCDS;
+        for (int tried = s_tried; tried < SEG_XCDS; ++tried) {
+          const int x = (home + tried) % SEG_XCDS;
+          const int c = atomicAdd(counter + x, 1);
+          if (c < nitems) {
+            q = x * nitems + c;
+            break;
+          }
+          s_tried = tried + 1;
+        }
+      }
+      s_item = q;
+    }
     __syncthreads();
     const int q = s_item;
     __syncthreads();
-    if (q >= nitems) break;
+    if (q < 0) break;
     WorkItem it;
     if (items) {
       it = items[q];
     } else {
       const int m0 = P[0].m;
-      const int kchunk = (m0 + ksplit - 1) / ksplit;
+      const int mj = cand ? ncand : m0;
+      const int x = q / nitems, c = q % nitems;
+      const int part = x * chunks + c / mj, jj = c % mj;
+      const int kchunk = (m0 + SEG_XCDS * chunks - 1) / (SEG_XCDS * chunks);
       it.b = 0;
-      it.j = cand ? cand[q / ksplit] : q / ksplit;
-      it.kbeg = (q % ksplit) * kchunk;
+      it.j = cand ? cand[jj] : jj;
+      it.kbeg = min(m0, part * kchunk);
       it.kend = min(m0, it.kbeg + kchunk);
+      if (it.kbeg >= it.kend) continue;            // an empty part of a narrow matrix
     }
     const ProbDesc d = P[it.b];
     seg_item(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j, it.kbeg,
-             it.kend,
-             V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap, smem);
+             it.kend, V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap, smem);
   }
 }
 

@@ -189,7 +189,7 @@ static void layout_sizes(BatchLayout &Ly) {
   Ly.o_tstart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_lam = take(sizeof(double) * Ly.total_lam);
   Ly.o_items = take(sizeof(WorkItem) * (Ly.ksplit ? 0 : Ly.nitems));
-  Ly.o_counter = take(sizeof(int) * 4);
+  Ly.o_counter = take(sizeof(int) * 16);
   Ly.meta_bytes = off;
   Ly.o_ci = take(sizeof(ColInfo) * Ly.total_cols);
   Ly.o_segflags = take(sizeof(int) * Ly.total_cols);
@@ -264,11 +264,19 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   const double target = (double)tp.items_per_cu * ctx->num_cu;
   if (B == 1) {
     const int m = (int)probs[0].m;
-    int ksplit = (int)ceil(target / m);
-    const int kmax = std::max(1, m / tp.kchunk_min);
-    ksplit = std::max(1, std::min(ksplit, kmax));
-    Ly.ksplit = ksplit;
-    Ly.nitems = (ro.cand ? ro.ncand : m) * ksplit;
+    // implicit items routed by XCD: each XCD's part of the k range is cut
+    // into chunks of at most ~2 MB of columns k (half an XCD's L2), but an
+    // item keeps at least kImplicitKmin columns k: short items cost a column
+    // j load, a row sample and a workgroup barrier each, which at large n
+    // (one workgroup per CU) outweighs the L2 reuse
+    constexpr int kImplicitKmin = 256;
+    const double part_bytes = 8.0 * (double)probs[0].n * (double)m / SEG_XCDS;
+    int chunks = (int)ceil(part_bytes / (2.0 * 1024 * 1024));
+    const int kmin = std::max(kImplicitKmin, tp.kchunk_min);
+    chunks = std::max(1, std::min(chunks, std::max(1, m / (SEG_XCDS * kmin))));
+    Ly.ksplit = chunks;
+    Ly.nitems = (ro.cand ? ro.ncand : m) * chunks;     // per XCD
+    (void)target;
   } else {
     for (int64_t b = 0; b < B; ++b) {
       const int m = (int)probs[b].m;
@@ -379,7 +387,8 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
                                 (int)lds_max));
     lds_attr_set = true;
   }
-  const int grid_seg = std::max(1, std::min(Ly.nitems, tp.blocks_per_cu * ctx->num_cu));
+  const long long all_items = Ly.ksplit ? (long long)Ly.nitems * SEG_XCDS : (long long)Ly.nitems;
+  const int grid_seg = (int)std::max(1ll, std::min(all_items, (long long)tp.blocks_per_cu * ctx->num_cu));
 
   hipStream_t ls = s;
   if (use_graph) {
@@ -392,7 +401,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   hipEvent_t t0 = nullptr, t1 = nullptr;
   {
     ProfScope ps(ctx, ls, "colprep");
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 4ll, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 16ll, 0);
     hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
                        (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
   }
@@ -409,8 +418,8 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   {
     ProfScope ps(ctx, ls, "fit_seg");
     hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
-                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand, ro.gate,
-                       ro.gate_on, lcap);
+                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand, ro.ncand,
+                       ro.gate, ro.gate_on, lcap);
   }
   if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
   {
@@ -561,7 +570,7 @@ const char *l1line_strerror(int code) {
     case L1LINE_ERANGE: return "a selected ratio overflowed";
     case L1LINE_ENOMEM: return "workspace allocation failed";
     case L1LINE_EWIDE: return "column magnitudes too spread for exact 128-bit weight sums";
-    case L1LINE_ESIZE: return "n exceeds L1LINE_MAX_N";
+    case L1LINE_ESIZE: return "a size exceeds the library limit (L1LINE_MAX_N rows, L1LINE_RANKER_MAX_M ranked columns)";
     case L1LINE_EINTERNAL: return "selection round bound exceeded";
     default: return "unknown status";
   }
@@ -738,29 +747,21 @@ int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2, const f
   return L1LINE_OK;
 }
 
-// ranker scratch layout for a matrix of n x m: sketch matrices, their
-// outputs, column info, statistics, scores, candidates, mask, flags
+// ranker scratch layout for a matrix of n x m: sign sums, slope aggregates,
+// column info, statistics, features, scores, candidates, mask, flags
 struct RkLayout {
-  int nsk, s[3];
-  size_t o_xs[3], o_v[3], o_j, o_obj, o_z, o_ci, o_stats, o_F, o_score, o_cand, o_mask, o_flag, o_margin, bytes;
+  size_t o_DZ, o_agg, o_ci, o_stats, o_F, o_score, o_cand, o_mask, o_flag, o_margin, bytes;
 };
 
 static RkLayout rk_layout(int64_t n, int64_t m) {
+  (void)n;
   RkLayout R;
-  R.nsk = 3;
-  const int sizes[3] = {64, 128, 256};
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b, 256); return o; };
-  for (int q = 0; q < 3; ++q) {
-    R.s[q] = (int)std::min<int64_t>(n, sizes[q]);
-    R.o_xs[q] = take(sizeof(double) * R.s[q] * m);
-    R.o_v[q] = take(sizeof(double) * m);
-  }
-  R.o_j = take(sizeof(int64_t) * 3);
-  R.o_obj = take(sizeof(double) * 3);
-  R.o_z = take(sizeof(double) * 3 * m);
+  R.o_DZ = take(2 * sizeof(double) * m * m);
+  R.o_agg = take(sizeof(double) * 4 * m);
   R.o_ci = take(sizeof(ColInfo) * m);
-  R.o_stats = take(sizeof(double) * 4 * 4);
+  R.o_stats = take(sizeof(double) * 3 * FEAT_Q);
   R.o_F = take(sizeof(float) * MLP_IN * m);
   R.o_score = take(sizeof(float) * m);
   R.o_cand = take(sizeof(int) * m);
@@ -777,26 +778,17 @@ static int ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   int st = ensure_rk(ctx, R.bytes, s);
   if (st) return st;
   char *b = (char *)ctx->rk;
-  l1line_problem pr[3];
-  double lam_q[3];
-  for (int q = 0; q < 3; ++q) {
-    double *Xs = (double *)(b + R.o_xs[q]);
-    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((R.s[q] * m + 255) / 256)), dim3(256), 0, s, X, (int)n,
-                       (int)m, (long long)ld, R.s[q], Xs);
-    // the penalty scales with the number of rows, as the error term does
-    lam_q[q] = lambda * (double)R.s[q] / (double)n;
-    pr[q] = single(Xs, R.s[q], m, R.s[q], &lam_q[q], 1, (double *)(b + R.o_v[q]), (int64_t *)(b + R.o_j) + q,
-                   (double *)(b + R.o_obj) + q, nullptr, (double *)(b + R.o_z) + q * m, nullptr);
-  }
-  HIP_TRY(hipGetLastError());
-  st = run_batch(ctx, pr, 3, 0, s, ctx->tune, nullptr);
-  if (st) return st;
   ColInfo *ci = (ColInfo *)(b + R.o_ci);
-  double *stats = (double *)(b + R.o_stats);
+  double2 *DZ = (double2 *)(b + R.o_DZ);
+  double *agg = (double *)(b + R.o_agg), *stats = (double *)(b + R.o_stats);
+  const int tk = (int)((m + SS_TILE - 1) / SS_TILE);
   hipLaunchKernelGGL(k_colprep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld, ci);
-  hipLaunchKernelGGL(k_feature_stats, dim3(1), dim3(256), 0, s, (const double *)(b + R.o_z), 3, (int)m, ci, stats);
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, (const double *)(b + R.o_z), 3,
-                     (int)m, (int)n, lambda, ci, stats, F);
+  hipLaunchKernelGGL(k_signsum_one, dim3((unsigned)(tk * tk)), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld, DZ);
+  hipLaunchKernelGGL(k_slope_aggr, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, (const double2 *)DZ, ci, (int)m,
+                     lambda, agg);
+  hipLaunchKernelGGL(k_feature_stats, dim3(1), dim3(256), 0, s, (const double *)agg, (int)m, ci, stats);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, (const double *)agg, (int)m,
+                     (int)n, lambda, ci, stats, F);
   HIP_TRY(hipGetLastError());
   return L1LINE_OK;
 }
@@ -806,6 +798,7 @@ int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   if (!ctx || !F) return L1LINE_EINVAL;
   int st = check_matrix(X, n, m, ld);
   if (st) return st;
+  if (m > L1LINE_RANKER_MAX_M) return L1LINE_ESIZE;
   st = check_lambdas(&lambda, 1);
   if (st) return st;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -825,6 +818,7 @@ int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int
   st = check_lambdas(&lambda, 1);
   if (st) return st;
   if (K < 1 || K > m || !(margin_threshold >= 0.0f) || isinf(margin_threshold)) return L1LINE_EINVAL;
+  if (m > L1LINE_RANKER_MAX_M) return L1LINE_ESIZE;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const RkLayout R = rk_layout(n, m);

@@ -249,92 +249,109 @@ __global__ void k_mlp_adam(float *__restrict__ P, float *__restrict__ m1, float 
 }
 
 // ----------------------------------------------------------------- features
-// Rows of the sketches: row q of a sketch of s rows is floor((q + 0.5) n / s).
-__global__ void k_gather_rows(const double *__restrict__ X, int n, int m, long long ld, int s,
-                              double *__restrict__ Xs) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)s * m) return;
-  const int k = (int)(e / s), q = (int)(e % s);
-  const int i = (int)(((2ll * q + 1) * n) / (2ll * s));
-  Xs[(long long)k * s + q] = X[(long long)k * ld + i];
+// Per column j, aggregates of the initial slopes s_jk = |D_jk| - Zr_jk - lambda
+// of the segments (j, k != j) where 0 is not the minimiser (s_jk > 0): the
+// objective is z_j = sum_k W_k - W_j + lambda - sum_k Delta_jk with
+// Delta_jk = g_jk(0) - g_jk(v_k) >= 0, zero exactly when s_jk <= 0, and
+// growing with s_jk.  agg[j] = (sum s, sum s^2 / W_k, sum s / W_k, count).
+// One wave per column.
+__global__ void k_slope_aggr(const double2 *__restrict__ DZ, const ColInfo *__restrict__ ci, int m, double lambda,
+                             double *__restrict__ agg) {
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= m) return;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0, c = 0.0;
+  for (int k = lane; k < m; k += 64) {
+    if (k == j) continue;
+    const double2 dz = DZ[(long long)j * m + k];
+    const double sl = fabs(dz.x) - dz.y - lambda;
+    if (sl > 0.0) {
+      const double Wk = ci[k].W;
+      s1 += sl;
+      c += 1.0;
+      if (Wk > 0.0) {
+        s2 += sl * sl / Wk;
+        s3 += sl / Wk;
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    s1 += __shfl_xor(s1, d);
+    s2 += __shfl_xor(s2, d);
+    s3 += __shfl_xor(s3, d);
+    c += __shfl_xor(c, d);
+  }
+  if (lane == 0) {
+    agg[4 * j + 0] = s1;
+    agg[4 * j + 1] = s2;
+    agg[4 * j + 2] = s3;
+    agg[4 * j + 3] = c;
+  }
 }
 
-// min / mean / std of each sketch's z over the columns (one workgroup)
-__global__ void k_feature_stats(const double *__restrict__ Zs, int nsk, int m, const ColInfo *__restrict__ ci,
+constexpr int FEAT_Q = 5;   // quantities with statistics: W, and the four slope aggregates
+
+// mean / standard deviation / max over the columns of W_j and of each
+// aggregate: stats[3 q + (0, 1, 2)] (one workgroup of 256)
+__global__ void k_feature_stats(const double *__restrict__ agg, int m, const ColInfo *__restrict__ ci,
                                 double *__restrict__ stats) {
-  __shared__ double sh[256];
+  __shared__ double sh[3][256];
   const int tid = threadIdx.x;
-  for (int q = 0; q <= nsk; ++q) {
-    // q < nsk: sketch q's z; q == nsk: column masses
-    double mn = 1e300, sum = 0.0, sq = 0.0;
+  for (int q = 0; q < FEAT_Q; ++q) {
+    double mx = -1e300, sum = 0.0, sq = 0.0;
     for (int j = tid; j < m; j += blockDim.x) {
-      const double v = q < nsk ? Zs[(long long)q * m + j] : ci[j].W;
-      mn = fmin(mn, v);
+      const double v = q == 0 ? ci[j].W : agg[4 * j + q - 1];
+      mx = fmax(mx, v);
       sum += v;
       sq += v * v;
     }
-    sh[tid] = mn;
+    sh[0][tid] = mx;
+    sh[1][tid] = sum;
+    sh[2][tid] = sq;
     __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-      if (tid < s) sh[tid] = fmin(sh[tid], sh[tid + s]);
+    for (int st = blockDim.x >> 1; st > 0; st >>= 1) {
+      if (tid < st) {
+        sh[0][tid] = fmax(sh[0][tid], sh[0][tid + st]);
+        sh[1][tid] += sh[1][tid + st];
+        sh[2][tid] += sh[2][tid + st];
+      }
       __syncthreads();
     }
-    const double gmin = sh[0];
-    __syncthreads();
-    sh[tid] = sum;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-      if (tid < s) sh[tid] += sh[tid + s];
-      __syncthreads();
-    }
-    const double gsum = sh[0];
-    __syncthreads();
-    sh[tid] = sq;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-      if (tid < s) sh[tid] += sh[tid + s];
-      __syncthreads();
-    }
-    const double gsq = sh[0];
-    __syncthreads();
     if (tid == 0) {
-      const double mean = gsum / m;
-      const double var = fmax(gsq / m - mean * mean, 0.0);
-      stats[4 * q + 0] = gmin;
-      stats[4 * q + 1] = mean;
-      stats[4 * q + 2] = sqrt(var);
+      const double mean = sh[1][0] / m;
+      const double var = fmax(sh[2][0] / m - mean * mean, 0.0);
+      stats[3 * q + 0] = mean;
+      stats[3 * q + 1] = sqrt(var);
+      stats[3 * q + 2] = sh[0][0];
     }
+    __syncthreads();
   }
 }
 
 // the 32 features of column j (documented in the header)
-__global__ void k_features(const double *__restrict__ Zs, int nsk, int m, int n, double lambda,
+__global__ void k_features(const double *__restrict__ agg, int m, int n, double lambda,
                            const ColInfo *__restrict__ ci, const double *__restrict__ stats, float *__restrict__ F) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   float f[MLP_IN];
 #pragma unroll
   for (int q = 0; q < MLP_IN; ++q) f[q] = 0.f;
-  double gapsum = 0.0, gmin = 1e300, gmax = -1e300;
-  for (int q = 0; q < nsk && q < 3; ++q) {
-    const double z = Zs[(long long)q * m + j];
-    const double mn = stats[4 * q], mean = stats[4 * q + 1], sd = stats[4 * q + 2];
-    const double gap = (mean > mn) ? (z - mn) / (mean - mn) : 0.0;
-    f[q] = (float)gap;
-    f[3 + q] = (float)log1p(fmax(mn > 0.0 ? z / mn - 1.0 : 0.0, 0.0));
-    f[6 + q] = (float)(sd > 0.0 ? (z - mean) / sd : 0.0);
-    gapsum += gap;
-    gmin = fmin(gmin, gap);
-    gmax = fmax(gmax, gap);
-  }
   const ColInfo c = ci[j];
-  const double meanW = stats[4 * nsk + 1];
-  f[9] = (float)(c.W > 0.0 && meanW > 0.0 ? log(c.W / meanW) : -30.0);
-  f[10] = (float)c.zeros / (float)n;
-  f[11] = (float)(c.W > 0.0 ? fmin(lambda / c.W, 10.0) : 10.0);
-  f[12] = (float)(c.W > 0.0 ? log1p(lambda / c.W) : 10.0);
-  f[13] = (float)(gapsum / 3.0);
-  f[14] = (float)(gmax - gmin);
+  const double W = c.W, meanW = stats[0], sdW = stats[1], maxW = stats[2];
+  f[0] = (float)(sdW > 0.0 ? (W - meanW) / sdW : 0.0);
+  f[1] = (float)(sdW > 0.0 ? (W - maxW) / sdW : 0.0);
+  f[2] = (float)(W > 0.0 && meanW > 0.0 ? log(W / meanW) : -30.0);
+  f[3] = (float)c.zeros / (float)n;
+  f[4] = (float)(W > 0.0 ? fmin(lambda / W, 10.0) : 10.0);
+  f[5] = (float)(agg[4 * j + 3] / (double)(m > 1 ? m - 1 : 1));
+#pragma unroll
+  for (int q = 1; q < FEAT_Q; ++q) {
+    const double v = agg[4 * j + q - 1], mean = stats[3 * q], sd = stats[3 * q + 1], mx = stats[3 * q + 2];
+    f[4 + 2 * q] = (float)(sd > 0.0 ? (v - mean) / sd : 0.0);
+    f[5 + 2 * q] = (float)(sd > 0.0 ? (v - mx) / sd : 0.0);
+  }
+  f[14] = (float)(W > 0.0 ? log1p(agg[4 * j] / W) : 0.0);
   f[15] = 1.0f;
 #pragma unroll
   for (int q = 0; q < MLP_IN; ++q) F[(long long)j * MLP_IN + q] = f[q];

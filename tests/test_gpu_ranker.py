@@ -1,6 +1,6 @@
 """GPU parity of the candidate ranker: MLP forward / gradient / Adam against
 the FP64 reference that mirrors the BF16 rounding points, features against
-oracle sketch fits, and the ranked fit against the exhaustive oracle."""
+their FP64 definition, and the ranked fit against the exhaustive oracle."""
 import sys
 
 import numpy as np
@@ -120,31 +120,36 @@ def test_mlp_adam(ctx):
 
 
 def _features_ref(X, lam):
-    """The 32 features from oracle fits of the three sketches (FP64)."""
+    """The 32 features in FP64 from their definition: sign sums by numpy
+    matrix products, column masses from the oracle."""
     n, m = X.shape
     W, zeros = O.column_stats(X)
-    gaps, f = [], np.zeros((m, 32))
-    for q, size in enumerate((64, 128, 256)):
-        s = min(n, size)
-        rows = ((2 * np.arange(s) + 1) * n) // (2 * s)
-        Xs = np.asfortranarray(X[rows, :])
-        z = O.fit(Xs, lam * s / n)["z_all"]
-        mn, mean = z.min(), z.mean()
-        sd = np.sqrt(max(np.mean(z * z) - mean * mean, 0.0))
-        gap = (z - mn) / (mean - mn) if mean > mn else np.zeros(m)
-        f[:, q] = gap
-        f[:, 3 + q] = np.log1p(np.maximum(z / mn - 1.0, 0.0)) if mn > 0 else 0.0
-        f[:, 6 + q] = (z - mean) / sd if sd > 0 else 0.0
-        gaps.append(gap)
-    gaps = np.array(gaps)
-    meanW = W.mean()
-    with np.errstate(divide="ignore"):
-        f[:, 9] = np.where(W > 0, np.log(np.where(W > 0, W, 1.0) / meanW), -30.0)
-        f[:, 10] = zeros / n
-        f[:, 11] = np.where(W > 0, np.minimum(lam / np.where(W > 0, W, 1.0), 10.0), 10.0)
-        f[:, 12] = np.where(W > 0, np.log1p(lam / np.where(W > 0, W, 1.0)), 10.0)
-    f[:, 13] = gaps.sum(0) / 3.0
-    f[:, 14] = gaps.max(0) - gaps.min(0)
+    D = X.T @ np.sign(X)                      # D[j, k] = sum_i x_ij sgn(x_ik)
+    Zr = np.abs(X).T @ (X == 0).astype(np.float64)
+    S = np.abs(D) - Zr - lam
+    np.fill_diagonal(S, -1.0)
+    pos = S > 0
+    Wk = W[None, :]
+    okw = pos & (Wk > 0)
+    Wsafe = np.where(Wk > 0, Wk, 1.0)
+    A = np.stack([np.where(pos, S, 0.0).sum(1), np.where(okw, S * S / Wsafe, 0.0).sum(1),
+                  np.where(okw, S / Wsafe, 0.0).sum(1), pos.sum(1).astype(np.float64)], axis=1)
+    f = np.zeros((m, 32))
+
+    def stand(v):
+        mean, mx = v.mean(), v.max()
+        sd = np.sqrt(max(np.mean(v * v) - mean * mean, 0.0))
+        return ((v - mean) / sd, (v - mx) / sd) if sd > 0 else (np.zeros(m), np.zeros(m))
+
+    f[:, 0], f[:, 1] = stand(W)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f[:, 2] = np.where(W > 0, np.log(np.where(W > 0, W, 1.0) / W.mean()), -30.0)
+        f[:, 3] = zeros / n
+        f[:, 4] = np.where(W > 0, np.minimum(lam / np.where(W > 0, W, 1.0), 10.0), 10.0)
+        f[:, 5] = A[:, 3] / max(m - 1, 1)
+        for q in range(4):
+            f[:, 6 + 2 * q], f[:, 7 + 2 * q] = stand(A[:, q])
+        f[:, 14] = np.where(W > 0, np.log1p(A[:, 0] / np.where(W > 0, W, 1.0)), 0.0)
     f[:, 15] = 1.0
     return f
 
@@ -157,8 +162,8 @@ def test_features(ctx, n, m, seed):
     lam = 0.05 * wl.max_column_mass(X)
     F = ctx.features(B.device_matrix(X), lam).cpu().numpy()
     want = _features_ref(X, lam)
-    # the sketch objectives are exact on both sides; the features are FP32
-    # roundings of FP64 arithmetic (statistics summed in different orders)
+    # the features are FP32 roundings of FP64 arithmetic (sign sums and
+    # statistics summed in different orders)
     np.testing.assert_allclose(F, want, rtol=1e-5, atol=2e-6)
 
 
