@@ -980,9 +980,10 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
   __syncthreads();   // the LDS is reused by the next item
 }
 
-// Persistent segment kernel: every workgroup pulls work items from a global
-// counter until none is left.  Explicit items (a batch) are ordered by
-// decreasing cost.  With items == nullptr the items of problem 0 are
+// Persistent segment kernel: every workgroup pulls work items from the
+// counter of its XCD until none is left.  Explicit items (a batch) come in
+// one list per XCD, [xstart[x], xstart[x + 1]).  With items == nullptr the
+// items of problem 0 are
 // implicit and routed by XCD: its k range is cut into SEG_XCDS * chunks
 // equal parts, XCD x owns parts [x chunks, (x + 1) chunks) and enumerates
 // them part by part, every preserved column j (or cand[jj]) within a part, so
@@ -996,7 +997,8 @@ constexpr int SEG_XCDS = 8;
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int chunks,
-            int *__restrict__ counter, const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
+            int *__restrict__ counter, const int *__restrict__ xstart, const double *__restrict__ lam_all,
+            const ColInfo *__restrict__ ci,
             const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
             int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand, int ncand,
             const int *__restrict__ gate, int gate_on, int lcap) {
@@ -1007,25 +1009,21 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
   while (true) {
     if (threadIdx.x == 0) {
       int q = -1;
-      if (items) {
-        const int c = atomicAdd(counter, 1);
-        q = c < nitems ? c : -1;
-      } else {
-        const int home = blockIdx.x % SEG_XCDS;
-        for (int tried = s_tried; tried < SEG_XCDS; ++tried) {
-          const int x = (home + tried) % SEG_XCDS;
-          const int c = atomicAdd(counter + x, 1);
-          if (c < nitems) {
-            q = x * nitems + c;
-            break;
-          }
-          s_tried = tried + 1;
+      const int home = blockIdx.x % SEG_XCDS;
+      for (int tried = s_tried; tried < SEG_XCDS; ++tried) {
+        const int x = (home + tried) % SEG_XCDS;
+        const int c = atomicAdd(counter + x, 1);
+        const int have = items ? xstart[x + 1] - xstart[x] : nitems;
+        if (c < have) {
+          q = items ? xstart[x] + c : x * nitems + c;
+          break;
         }
+        s_tried = tried + 1;
       }
       s_item = q;
     }
     __syncthreads();
-    const int q = s_item;
+    const int q = uni_int(s_item);
     __syncthreads();
     if (q < 0) break;
     WorkItem it;

@@ -174,8 +174,9 @@ static int check_problem(const l1line_problem &p) {
 //   data: ColInfo, segflags, V, E, R, Z, zflag
 struct BatchLayout {
   int B, nitems, ksplit, nmax, Lmax;
+  int xstart[SEG_XCDS + 1];   // explicit items: XCD x owns [xstart[x], xstart[x + 1])
   long long total_cols, total_z, total_out, total_ws, total_lam, total_pairs, total_tiles;
-  size_t o_desc, o_colstart, o_zstart, o_ostart, o_tstart, o_lam, o_items, o_counter, meta_bytes;
+  size_t o_desc, o_colstart, o_zstart, o_ostart, o_tstart, o_lam, o_items, o_counter, o_xstart, meta_bytes;
   size_t o_ci, o_segflags, o_DZ, o_V, o_E, o_R, o_Z, o_zflag, bytes;
 };
 
@@ -190,6 +191,7 @@ static void layout_sizes(BatchLayout &Ly) {
   Ly.o_lam = take(sizeof(double) * Ly.total_lam);
   Ly.o_items = take(sizeof(WorkItem) * (Ly.ksplit ? 0 : Ly.nitems));
   Ly.o_counter = take(sizeof(int) * 16);
+  Ly.o_xstart = take(sizeof(int) * (SEG_XCDS + 1));
   Ly.meta_bytes = off;
   Ly.o_ci = take(sizeof(ColInfo) * Ly.total_cols);
   Ly.o_segflags = take(sizeof(int) * Ly.total_cols);
@@ -278,21 +280,37 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     Ly.nitems = (ro.cand ? ro.ncand : m) * chunks;     // per XCD
     (void)target;
   } else {
-    for (int64_t b = 0; b < B; ++b) {
-      const int m = (int)probs[b].m;
-      const double share = target * ((double)probs[b].n * m * m) / total_cost;
-      int ksplit = (int)ceil(share / m);
-      const int kmax = std::max(1, m / tp.kchunk_min);
-      ksplit = std::max(1, std::min(ksplit, kmax));
-      const int kchunk = (m + ksplit - 1) / ksplit;
-      for (int j = 0; j < m; ++j)
-        for (int k0 = 0; k0 < m; k0 += kchunk) items.push_back(WorkItem{(int)b, j, k0, std::min(m, k0 + kchunk)});
+    // problems to XCDs, largest first onto the least loaded one; an XCD
+    // works through its problems largest first, so its workgroups share one
+    // matrix at a time in their L2 (stealing from the next XCDs evens out
+    // the end)
+    std::vector<int> order((size_t)B);
+    for (int64_t b = 0; b < B; ++b) order[(size_t)b] = (int)b;
+    auto cost = [&](int b) { return (double)probs[b].n * (double)probs[b].m * (double)probs[b].m; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    double load[SEG_XCDS] = {0};
+    std::vector<int> owned[SEG_XCDS];
+    for (int b : order) {
+      int x = 0;
+      for (int y = 1; y < SEG_XCDS; ++y)
+        if (load[y] < load[x]) x = y;
+      load[x] += cost(b);
+      owned[x].push_back(b);
     }
-    // longest first: dynamic pulling then approximates LPT scheduling
-    std::stable_sort(items.begin(), items.end(), [&](const WorkItem &x, const WorkItem &y) {
-      const double cx = (double)probs[x.b].n * (x.kend - x.kbeg), cy = (double)probs[y.b].n * (y.kend - y.kbeg);
-      return cx > cy;
-    });
+    for (int x = 0; x < SEG_XCDS; ++x) {
+      Ly.xstart[x] = (int)items.size();
+      for (int b : owned[x]) {
+        const int m = (int)probs[b].m;
+        const double share = target * cost(b) / total_cost;
+        int ksplit = (int)ceil(share / m);
+        const int kmax = std::max(1, m / tp.kchunk_min);
+        ksplit = std::max(1, std::min(ksplit, kmax));
+        const int kchunk = (m + ksplit - 1) / ksplit;
+        for (int j = 0; j < m; ++j)
+          for (int k0 = 0; k0 < m; k0 += kchunk) items.push_back(WorkItem{b, j, k0, std::min(m, k0 + kchunk)});
+      }
+    }
+    Ly.xstart[SEG_XCDS] = (int)items.size();
     Ly.ksplit = 0;
     Ly.nitems = (int)items.size();
   }
@@ -350,6 +368,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   hz[B] = (int)z;
   ho[B] = (int)out;
   if (!items.empty()) memcpy(h + Ly.o_items, items.data(), sizeof(WorkItem) * items.size());
+  memcpy(h + Ly.o_xstart, Ly.xstart, sizeof Ly.xstart);
 
   const ProbDesc *dP = (const ProbDesc *)(d + Ly.o_desc);
   const int *dcol = (const int *)(d + Ly.o_colstart), *dz = (const int *)(d + Ly.o_zstart),
@@ -357,6 +376,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   const double *dlam = (const double *)(d + Ly.o_lam);
   const WorkItem *ditems = Ly.ksplit ? nullptr : (const WorkItem *)(d + Ly.o_items);
   int *dcounter = (int *)(d + Ly.o_counter);
+  const int *dxstart = (const int *)(d + Ly.o_xstart);
   ColInfo *dci = (ColInfo *)(d + Ly.o_ci);
   int *dsegflags = (int *)(d + Ly.o_segflags);
   double *dV = (double *)(d + Ly.o_V), *dE = (double *)(d + Ly.o_E), *dZ = (double *)(d + Ly.o_Z);
@@ -418,7 +438,8 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   {
     ProfScope ps(ctx, ls, "fit_seg");
     hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
-                       Ly.nitems, Ly.ksplit, dcounter, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand, ro.ncand,
+                       Ly.nitems, Ly.ksplit, dcounter, dxstart, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand,
+                       ro.ncand,
                        ro.gate, ro.gate_on, lcap);
   }
   if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
