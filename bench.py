@@ -214,10 +214,10 @@ def leg_ranked(ctx, count):
     from paper_2402_16712_amd import ranker
     if not os.path.exists(ranker.WEIGHTS):
         return {"skipped": "no trained ranker weights in the package"}
-    params = ranker.load_params(ranker.WEIGHTS)
+    ctx.ranker_load(ranker.WEIGHTS)
     # one warm-up instance outside the statistics (allocations, first launches)
-    ranker.evaluate(ctx, params, [ranker.EVAL_BASE + 10 ** 6], n=2000, m=500)
-    rows = ranker.evaluate(ctx, params, [ranker.EVAL_BASE + q for q in range(count)], n=10000, m=4000)
+    ranker.evaluate(ctx, [ranker.EVAL_BASE + 10 ** 6], n=2000, m=500)
+    rows = ranker.evaluate(ctx, [ranker.EVAL_BASE + q for q in range(count)], n=10000, m=4000)
     te = sum(r["t_exhaustive"] for r in rows)
     tk = sum(r["t_ranked"] for r in rows)
     return {"workload": f"ranked fit, {count} matrices 10000x4000 FP64, K=32, margin 0.05, lambda 0.05 x mass",

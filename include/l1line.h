@@ -43,7 +43,9 @@
  *   Data-dependent conditions are found on the device and written to the
  *   optional `status` output (one int32, device memory): 0, or the first
  *   that applies of ENONFINITE, EWIDE, EINTERNAL, ERANGE.  With a nonzero
- *   status the other outputs are unspecified.
+ *   status the other outputs are unspecified.  The context also keeps a
+ *   sticky error: the first nonzero code an entry point returned, else the
+ *   first data-dependent status any call produced (l1line_last_error).
  */
 #ifndef L1LINE_H
 #define L1LINE_H
@@ -65,6 +67,8 @@ extern "C" {
                                   bit + 1) + bitlength(#nonzeros) > 124 (device)     */
 #define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N, or m above L1LINE_RANKER_MAX_M for the ranker (host check) */
 #define L1LINE_EINTERNAL (-8)  /* a selection exceeded its round bound (device)      */
+#define L1LINE_EIO (-9)        /* a file could not be read or written, or is malformed */
+#define L1LINE_ENOMODEL (-10)  /* the context holds no ranker weights                */
 
 #define L1LINE_MAX_N 16384         /* rows per matrix (column j is held in LDS)   */
 #define L1LINE_MAX_LAMBDAS 128     /* penalties per call (passed by value)        */
@@ -72,12 +76,21 @@ extern "C" {
 typedef struct l1line_ctx_s *l1line_ctx;
 
 /* Create a context on HIP device `device` (its workspace starts empty and
- * grows on demand).  *ctx receives the handle.  Returns EINVAL for a bad
- * device or null ctx, EHIP if the device cannot be selected. */
-int l1line_create(l1line_ctx *ctx, int device);
+ * grows on demand; it owns the launch parameters and the ranker weights).
+ * *ctx receives the handle.  tune_cache_path (HOST string, nullable): a
+ * file holding launch parameters, read here when it exists and written by
+ * l1line_autotune.  Returns EINVAL for a bad device or null ctx, EHIP if the
+ * device cannot be selected. */
+int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path);
 
 /* Free the context's workspace (synchronises its device first). */
 int l1line_destroy(l1line_ctx ctx);
+
+/* The context's sticky error, then cleared: the first nonzero code an entry
+ * point returned on it since the last call, else the first data-dependent
+ * status (ENONFINITE, EWIDE, EINTERNAL, ERANGE) of any call, else 0.  Reads a
+ * device word synchronously: call it after the work's stream has finished. */
+int l1line_last_error(l1line_ctx ctx);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *l1line_strerror(int code);
@@ -216,21 +229,55 @@ int l1line_mlp_grad(l1line_ctx ctx, const float *params, const float *F,
 int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2,
                     const float *grad, int64_t step, float lr, void *stream);
 
-/* Ranked fit: features, MLP scores (lower = better candidate), the K best
- * columns solved exactly; if the score gap between the best column and the
+/* Ranked fit with the context's ranker weights: features, MLP scores (lower
+ * = better candidate), the K best columns solved exactly by Algorithm 1
+ * restricted to them; if the score gap between the best column and the
  * first one left out is below margin_threshold (or K = m) the exhaustive
  * search runs instead (decided on the device, no host synchronisation).
  *   v, j, obj, median_row, status  as l1line_fit (DEVICE)
  *   used_fallback  [1] 1 when the exhaustive search ran (DEVICE, nullable)
  *   scores         [m] the MLP scores (DEVICE, nullable)
  * Host errors: as l1line_fit, EINVAL for K outside [1, m] or a negative or
- * non-finite threshold, ESIZE for m > L1LINE_RANKER_MAX_M. */
+ * non-finite threshold, ESIZE for m > L1LINE_RANKER_MAX_M, ENOMODEL when no
+ * weights were loaded, set or trained. */
 int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
-                      int64_t ld, double lambda, const float *params,
-                      int32_t K, float margin_threshold, double *v,
-                      int64_t *j, double *obj, int32_t *median_row,
+                      int64_t ld, double lambda, int32_t K,
+                      float margin_threshold, double *v, int64_t *j,
+                      double *obj, int32_t *median_row,
                       int32_t *used_fallback, float *scores, int32_t *status,
                       void *stream);
+
+/* Ranker weights owned by the context.
+ * File format (little endian): "L1RK", u32 version 1, u32 parameter count
+ * (L1LINE_MLP_PARAMS), u32 flags (bit 0: Adam state follows), i64 steps
+ * taken, u64 training seed, u64 next training example; FP32 weights; with
+ * bit 0 the FP32 Adam moments m1 and m2.
+ * l1line_ranker_load: weights (and state) from `path` (HOST string); EIO for
+ *   a missing, short or malformed file or non-finite weights.
+ * l1line_ranker_save: writes the weights (and the state after training) to
+ *   `path` atomically (a temporary file renamed); ENOMODEL without weights.
+ * l1line_ranker_set_params / get_params: copy L1LINE_MLP_PARAMS FP32 weights
+ *   from / to DEVICE memory on `stream` (set clears the Adam state). */
+int l1line_ranker_load(l1line_ctx ctx, const char *path);
+int l1line_ranker_save(l1line_ctx ctx, const char *path);
+int l1line_ranker_set_params(l1line_ctx ctx, const float *params, void *stream);
+int l1line_ranker_get_params(l1line_ctx ctx, float *params, void *stream);
+
+/* Train the context's ranker until `steps` Adam steps have been taken in
+ * total, one step per generated matrix: n ~ U{500..4000}, m ~ U{50..500}
+ * (sizes from splitmix64 of (seed, example)), entries from Philox-4x32-10
+ * keyed by (seed, example): x_ik = u_i l_k + Laplace(0, 0.1) noise, l_k ~
+ * U[-1, 1] on 10% of the columns, 10% of the rows replaced by 20 N(0, 1),
+ * 1% zeros; lambda = 0.05 x max column mass.  Labels: the exact z_j of the
+ * exhaustive fit, as y_j = (z_j - min z) / (mean z - min z); loss: mean
+ * squared error of the MLP; Adam (lr 1e-3).  ckpt_path (HOST string,
+ * nullable): resumed from when it exists (the seed is then the file's),
+ * rewritten every 1000 steps and at the end; the run is deterministic, so a
+ * resumed run ends with the same weights as an uninterrupted one.
+ * Synchronous (uses the default stream).  EIO for an unreadable checkpoint
+ * or one without Adam state. */
+int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps,
+                        uint64_t seed);
 
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.

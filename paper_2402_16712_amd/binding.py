@@ -14,14 +14,16 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_build", "libl1line.so")
 
-OK, EINVAL, EHIP, ENONFINITE, ERANGE, ENOMEM, EWIDE, ESIZE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, EHIP, ENONFINITE, ERANGE, ENOMEM, EWIDE, ESIZE, EINTERNAL, EIO, ENOMODEL = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
 MAX_N = 16384
 MAX_LAMBDAS = 128
 
-EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_column_stats",
+EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_error", "l1line_column_stats",
            "l1line_fit", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
-           "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked"]
+           "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
+           "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train"]
 BATCH_GRAPH = 1
 FEATURES = 32
 MLP_PARAMS = 20865
@@ -53,7 +55,13 @@ def lib() -> ctypes.CDLL:
                                "(run __graft_entry__.build() or python -m paper_2402_16712_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
-        L.l1line_create.argtypes = [ctypes.POINTER(P), I32]
+        L.l1line_create.argtypes = [ctypes.POINTER(P), I32, ctypes.c_char_p]
+        L.l1line_last_error.argtypes = [P]
+        L.l1line_ranker_load.argtypes = [P, ctypes.c_char_p]
+        L.l1line_ranker_save.argtypes = [P, ctypes.c_char_p]
+        L.l1line_ranker_set_params.argtypes = [P, P, P]
+        L.l1line_ranker_get_params.argtypes = [P, P, P]
+        L.l1line_ranker_train.argtypes = [P, ctypes.c_char_p, I64, ctypes.c_uint64]
         L.l1line_destroy.argtypes = [P]
         L.l1line_strerror.argtypes = [I32]
         L.l1line_strerror.restype = ctypes.c_char_p
@@ -69,14 +77,16 @@ def lib() -> ctypes.CDLL:
         L.l1line_mlp_forward.argtypes = [P, P, P, I64, P, P]
         L.l1line_mlp_grad.argtypes = [P, P, P, P, I64, P, P, P]
         L.l1line_mlp_adam.argtypes = [P, P, P, P, P, I64, F32, P]
-        L.l1line_fit_ranked.argtypes = [P, P, I64, I64, I64, D, P, I32, F32, P, P, P, P, P, P, P, P]
+        L.l1line_fit_ranked.argtypes = [P, P, I64, I64, I64, D, I32, F32, P, P, P, P, P, P, P, P]
         L.l1line_profile.argtypes = [P, I32]
         L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),
                                           ctypes.POINTER(I64), I32]
         for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit",
                   "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
                   "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
-                  "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked"):
+                  "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked",
+                  "l1line_last_error", "l1line_ranker_load", "l1line_ranker_save", "l1line_ranker_set_params",
+                  "l1line_ranker_get_params", "l1line_ranker_train"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -128,13 +138,18 @@ def _check_matrix(X):
 class Context:
     """One library context (workspace) on one device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache_path=None):
         torch = _torch()
         self.device = int(device)
         self._torch_device = torch.device("cuda", self.device)
         h = ctypes.c_void_p()
-        _check(lib().l1line_create(ctypes.byref(h), self.device), "l1line_create")
+        path = None if tune_cache_path is None else os.fsencode(tune_cache_path)
+        _check(lib().l1line_create(ctypes.byref(h), self.device, path), "l1line_create")
         self._h = h
+
+    def last_error(self) -> int:
+        """The context's sticky error (then cleared); call after synchronising."""
+        return int(lib().l1line_last_error(self._h))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -309,16 +324,71 @@ class Context:
         _check(lib().l1line_mlp_adam(self._h, _ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), int(step),
                                      float(lr), self._stream()), "l1line_mlp_adam")
 
-    def fit_ranked(self, X, lam: float, params, K: int = 32, margin: float = 0.05):
+    def fit_ranked(self, X, lam: float, K: int = 32, margin: float = 0.05):
+        """Ranked fit with the context's ranker weights."""
         torch = _torch()
         n, m, ld = _check_matrix(X)
-        self._f32(params, (MLP_PARAMS,))
         out = dict(v=self._empty((m,), torch.float64), j=self._empty((1,), torch.int64),
                    obj=self._empty((1,), torch.float64), row=self._empty((m,), torch.int32),
                    used_fallback=self._empty((1,), torch.int32),
                    scores=self._empty((m,), torch.float32), status=self._empty((1,), torch.int32))
-        _check(lib().l1line_fit_ranked(self._h, _ptr(X), n, m, ld, float(lam), _ptr(params), int(K),
-                                       float(margin), _ptr(out["v"]), _ptr(out["j"]), _ptr(out["obj"]),
-                                       _ptr(out["row"]), _ptr(out["used_fallback"]), _ptr(out["scores"]),
-                                       _ptr(out["status"]), self._stream()), "l1line_fit_ranked")
+        _check(lib().l1line_fit_ranked(self._h, _ptr(X), n, m, ld, float(lam), int(K), float(margin),
+                                       _ptr(out["v"]), _ptr(out["j"]), _ptr(out["obj"]), _ptr(out["row"]),
+                                       _ptr(out["used_fallback"]), _ptr(out["scores"]), _ptr(out["status"]),
+                                       self._stream()), "l1line_fit_ranked")
         return out
+
+    def ranker_load(self, path):
+        _check(lib().l1line_ranker_load(self._h, os.fsencode(path)), "l1line_ranker_load")
+
+    def ranker_save(self, path):
+        _check(lib().l1line_ranker_save(self._h, os.fsencode(path)), "l1line_ranker_save")
+
+    def ranker_set_params(self, params):
+        self._f32(params, (MLP_PARAMS,))
+        _check(lib().l1line_ranker_set_params(self._h, _ptr(params), self._stream()), "l1line_ranker_set_params")
+
+    def ranker_get_params(self):
+        torch = _torch()
+        out = self._empty((MLP_PARAMS,), torch.float32)
+        _check(lib().l1line_ranker_get_params(self._h, _ptr(out), self._stream()), "l1line_ranker_get_params")
+        return out
+
+    def ranker_train(self, steps: int, seed: int = 0, ckpt_path=None):
+        """Native training loop (synchronous, default stream)."""
+        _torch().cuda.synchronize(self._torch_device)
+        path = None if ckpt_path is None else os.fsencode(ckpt_path)
+        _check(lib().l1line_ranker_train(self._h, path, int(steps), int(seed) & 0xFFFFFFFFFFFFFFFF),
+               "l1line_ranker_train")
+
+
+def write_ranker_file(path, params):
+    """Write FP32 weights (numpy, L1LINE_MLP_PARAMS) in the library's ranker
+    file format (no optimizer state): "L1RK", version 1, count, flags 0,
+    step 0, seed 0, next example 0, then the weights."""
+    import struct
+    w = np.ascontiguousarray(np.asarray(params, dtype="<f4"))
+    if w.shape != (MLP_PARAMS,):
+        raise ValueError("expected %d weights" % MLP_PARAMS)
+    with open(path, "wb") as f:
+        f.write(b"L1RK" + struct.pack("<IIIqQQ", 1, MLP_PARAMS, 0, 0, 0, 0))
+        f.write(w.tobytes())
+
+
+def read_ranker_file(path):
+    """(weights, state or None, header dict) of a ranker file, numpy only."""
+    import struct
+    with open(path, "rb") as f:
+        head = f.read(40)
+        if len(head) != 40 or head[:4] != b"L1RK":
+            raise ValueError("not a ranker file")
+        ver, cnt, flags, step, seed, cursor = struct.unpack("<IIIqQQ", head[4:])
+        if ver != 1 or cnt != MLP_PARAMS or flags & ~1:
+            raise ValueError("unsupported ranker file")
+        data = np.frombuffer(f.read(), dtype="<f4")
+    k = 3 if flags & 1 else 1
+    if data.size != k * MLP_PARAMS:
+        raise ValueError("truncated ranker file")
+    w = data[:MLP_PARAMS].copy()
+    state = (data[MLP_PARAMS:2 * MLP_PARAMS].copy(), data[2 * MLP_PARAMS:].copy()) if k == 3 else None
+    return w, state, dict(step=step, seed=seed, cursor=cursor)

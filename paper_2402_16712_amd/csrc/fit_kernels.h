@@ -1100,7 +1100,7 @@ __global__ void __launch_bounds__(256)
 k_argmin_batch(const ProbDesc *__restrict__ P, const int *__restrict__ ostart, int B,
                const double *__restrict__ V, const int *__restrict__ R, const double *__restrict__ Z,
                const int *__restrict__ zflag, const ColInfo *__restrict__ ci, const int *__restrict__ segflags,
-               const int *__restrict__ jmask, const int *__restrict__ gate, int gate_on) {
+               const int *__restrict__ jmask, const int *__restrict__ gate, int gate_on, int *__restrict__ sticky) {
   __shared__ double sz[256];
   __shared__ int sj[256];
   __shared__ int sflag[256];
@@ -1143,7 +1143,7 @@ k_argmin_batch(const ProbDesc *__restrict__ P, const int *__restrict__ ostart, i
     d.Jout[t] = js;
     d.OBJout[t] = z[js];
   }
-  if (t == 0 && d.status) {
+  if (t == 0 && (d.status || sticky)) {
     // condition bits; the status is the first that applies of: non-finite
     // input, too-wide column, selection bound, overflowed ratio
     int f = 0;
@@ -1163,8 +1163,11 @@ k_argmin_batch(const ProbDesc *__restrict__ P, const int *__restrict__ ostart, i
     }
     if (tid == 0) {
       const int bb = sflag[0];
-      *d.status = (bb & 1) ? L1LINE_ENONFINITE : (bb & 2) ? L1LINE_EWIDE : (bb & 4) ? L1LINE_EINTERNAL
-                : (bb & 8) ? L1LINE_ERANGE : L1LINE_OK;
+      const int st = (bb & 1) ? L1LINE_ENONFINITE : (bb & 2) ? L1LINE_EWIDE : (bb & 4) ? L1LINE_EINTERNAL
+                   : (bb & 8) ? L1LINE_ERANGE : L1LINE_OK;
+      if (d.status) *d.status = st;
+      // the context's sticky error keeps the first data-dependent error
+      if (sticky && st != L1LINE_OK) atomicCAS(sticky, 0, st);
     }
   }
 }

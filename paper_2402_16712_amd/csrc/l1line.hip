@@ -47,8 +47,15 @@ struct l1line_ctx_s {
   TuneParams tune;
   bool profiling;
   std::vector<ProfRec> prof;
-  void *rk;                 // ranker scratch (features, sketches, MLP buffers)
+  void *rk;                 // ranker scratch (features, sign sums, MLP buffers)
   size_t rk_bytes;
+  int *sticky;              // device: first data-dependent error of any call on the context
+  int host_err;             // first argument / runtime error an entry point returned
+  std::string tune_path;    // launch-parameter cache file ("" = none)
+  float *rk_w;              // ranker: FP32 weights, Adam moments m1, m2 (device, 3 x L1LINE_MLP_PARAMS)
+  bool rk_have_w, rk_have_state;
+  int64_t rk_step;          // Adam steps taken (checkpoint state)
+  uint64_t rk_seed, rk_cursor;  // training-set seed and next example (checkpoint state)
 };
 
 #define HIP_TRY(expr)                                   \
@@ -451,7 +458,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   {
     ProfScope ps(ctx, ls, "argmin");
     hipLaunchKernelGGL(k_argmin_batch, dim3((unsigned)Ly.total_out), dim3(256), 0, ls, dP, dout, (int)B, dV, dR,
-                       dZ, dzflag, dci, dsegflags, ro.jmask, ro.gate, ro.gate_on);
+                       dZ, dzflag, dci, dsegflags, ro.jmask, ro.gate, ro.gate_on, ctx->sticky);
   }
   const hipError_t le = hipGetLastError();
   if (use_graph) {
@@ -502,7 +509,29 @@ static const TuneParams kDefaultTune = {3, 8, 24};
 
 extern "C" {
 
-int l1line_create(l1line_ctx *ctx, int device) {
+// Launch-parameter cache: one text line "l1line-tune <workgroups per CU>
+// <fewest k per item> <items per CU>"; a missing or malformed file is ignored.
+static void tune_load(l1line_ctx c) {
+  if (c->tune_path.empty()) return;
+  FILE *f = fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  int a = 0, k = 0, i = 0;
+  if (fscanf(f, "l1line-tune %d %d %d", &a, &k, &i) == 3 && a >= 1 && a <= 16 && k >= 1 && k <= (1 << 20) &&
+      i >= 1 && i <= 4096)
+    c->tune = TuneParams{a, k, i};
+  fclose(f);
+}
+
+static int tune_save(l1line_ctx c) {
+  if (c->tune_path.empty()) return L1LINE_OK;
+  FILE *f = fopen(c->tune_path.c_str(), "w");
+  if (!f) return L1LINE_EIO;
+  const int ok = fprintf(f, "l1line-tune %d %d %d\n", c->tune.blocks_per_cu, c->tune.kchunk_min,
+                         c->tune.items_per_cu) > 0;
+  return (fclose(f) == 0 && ok) ? L1LINE_OK : L1LINE_EIO;
+}
+
+int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path) {
   if (!ctx) return L1LINE_EINVAL;
   *ctx = nullptr;
   int count = 0;
@@ -526,13 +555,40 @@ int l1line_create(l1line_ctx *ctx, int device) {
   c->profiling = false;
   c->rk = nullptr;
   c->rk_bytes = 0;
+  c->sticky = nullptr;
+  c->host_err = L1LINE_OK;
+  c->rk_w = nullptr;
+  c->rk_have_w = c->rk_have_state = false;
+  c->rk_step = 0;
+  c->rk_seed = c->rk_cursor = 0;
+  if (tune_cache_path) c->tune_path = tune_cache_path;
+  tune_load(c);
   if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc((void **)&c->sticky, sizeof(int)) != hipSuccess || hipMemset(c->sticky, 0, sizeof(int)) != hipSuccess) {
+    if (c->sticky) (void)hipFree(c->sticky);
     delete c;
     return L1LINE_EHIP;
   }
   *ctx = c;
   return L1LINE_OK;
+}
+
+// Records the first nonzero status an entry point returns on the context.
+static int note(l1line_ctx ctx, int st) {
+  if (ctx && st != L1LINE_OK && ctx->host_err == L1LINE_OK) ctx->host_err = st;
+  return st;
+}
+
+int l1line_last_error(l1line_ctx ctx) {
+  if (!ctx) return L1LINE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return L1LINE_EHIP;
+  int dev = 0;
+  if (hipMemcpy(&dev, ctx->sticky, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return L1LINE_EHIP;
+  const int st = ctx->host_err != L1LINE_OK ? ctx->host_err : dev;
+  ctx->host_err = L1LINE_OK;
+  if (dev != 0 && hipMemset(ctx->sticky, 0, sizeof(int)) != hipSuccess) return L1LINE_EHIP;
+  return st;
 }
 
 static void prof_clear(l1line_ctx ctx) {
@@ -552,6 +608,8 @@ int l1line_destroy(l1line_ctx ctx) {
   if (ctx->ws && hipFree(ctx->ws) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->stage && hipHostFree(ctx->stage) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->rk && hipFree(ctx->rk) != hipSuccess) st = L1LINE_EHIP;
+  if (ctx->sticky && hipFree(ctx->sticky) != hipSuccess) st = L1LINE_EHIP;
+  if (ctx->rk_w && hipFree(ctx->rk_w) != hipSuccess) st = L1LINE_EHIP;
   (void)hipEventDestroy(ctx->stage_done);
   (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
@@ -593,11 +651,13 @@ const char *l1line_strerror(int code) {
     case L1LINE_EWIDE: return "column magnitudes too spread for exact 128-bit weight sums";
     case L1LINE_ESIZE: return "a size exceeds the library limit (L1LINE_MAX_N rows, L1LINE_RANKER_MAX_M ranked columns)";
     case L1LINE_EINTERNAL: return "selection round bound exceeded";
+    case L1LINE_EIO: return "file missing, unreadable or malformed";
+    case L1LINE_ENOMODEL: return "the context holds no ranker weights";
     default: return "unknown status";
   }
 }
 
-int l1line_column_stats(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double *W,
+static int column_stats_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double *W,
                         int32_t *zeros, int32_t *status, void *stream) {
   if (!ctx) return L1LINE_EINVAL;
   if (!X || n < 1 || m < 1 || ld < n || m > (1ll << 24) || n > (1ll << 30)) return L1LINE_EINVAL;
@@ -613,7 +673,12 @@ int l1line_column_stats(l1line_ctx ctx, const double *X, int64_t n, int64_t m, i
   return L1LINE_OK;
 }
 
-int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, double *v,
+int l1line_column_stats(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double *W,
+                        int32_t *zeros, int32_t *status, void *stream) {
+  return note(ctx, column_stats_impl(ctx, X, n, m, ld, W, zeros, status, stream));
+}
+
+static int fit_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, double *v,
                int64_t *j, double *obj, int32_t *median_row, double *z_all, int32_t *status, void *stream) {
   if (!ctx || !v || !j || !obj) return L1LINE_EINVAL;
   int st = check_matrix(X, n, m, ld);
@@ -625,7 +690,12 @@ int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld
   return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, ctx->tune, nullptr);
 }
 
-int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas,
+int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, double *v,
+               int64_t *j, double *obj, int32_t *median_row, double *z_all, int32_t *status, void *stream) {
+  return note(ctx, fit_impl(ctx, X, n, m, ld, lambda, v, j, obj, median_row, z_all, status, stream));
+}
+
+static int fit_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas,
                     int64_t L, double *V, int64_t *J, double *OBJ, int32_t *ROW, double *ZALL, int32_t *status,
                     void *stream) {
   if (!ctx || !V || !J || !OBJ) return L1LINE_EINVAL;
@@ -638,7 +708,13 @@ int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64
   return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, ctx->tune, nullptr);
 }
 
-int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, void *stream) {
+int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas,
+                    int64_t L, double *V, int64_t *J, double *OBJ, int32_t *ROW, double *ZALL, int32_t *status,
+                    void *stream) {
+  return note(ctx, fit_path_impl(ctx, X, n, m, ld, lambdas, L, V, J, OBJ, ROW, ZALL, status, stream));
+}
+
+static int fit_batch_impl(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, void *stream) {
   if (!ctx || !probs || B < 1 || B > (1 << 20)) return L1LINE_EINVAL;
   if (flags & ~L1LINE_BATCH_GRAPH) return L1LINE_EINVAL;
   for (int64_t b = 0; b < B; ++b) {
@@ -649,7 +725,11 @@ int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   return run_batch(ctx, probs, B, flags, (hipStream_t)stream, ctx->tune, nullptr);
 }
 
-int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B, void *stream, int32_t *params_out) {
+int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, void *stream) {
+  return note(ctx, fit_batch_impl(ctx, probs, B, flags, stream));
+}
+
+static int autotune_impl(l1line_ctx ctx, const l1line_problem *probs, int64_t B, void *stream, int32_t *params_out) {
   if (!ctx || !probs || B < 1 || B > (1 << 20)) return L1LINE_EINVAL;
   for (int64_t b = 0; b < B; ++b) {
     const int st = check_problem(probs[b]);
@@ -687,7 +767,11 @@ int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B, void
     params_out[1] = best.kchunk_min;
     params_out[2] = best.items_per_cu;
   }
-  return L1LINE_OK;
+  return tune_save(ctx);
+}
+
+int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B, void *stream, int32_t *params_out) {
+  return note(ctx, autotune_impl(ctx, probs, B, stream, params_out));
 }
 
 int l1line_tune_set(l1line_ctx ctx, const int32_t *params) {
@@ -720,13 +804,17 @@ static int mlp_forward(l1line_ctx ctx, const float *P, const float *F, int64_t N
   return L1LINE_OK;
 }
 
-int l1line_mlp_forward(l1line_ctx ctx, const float *params, const float *F, int64_t N, float *out, void *stream) {
+static int mlp_forward_impl(l1line_ctx ctx, const float *params, const float *F, int64_t N, float *out, void *stream) {
   if (!ctx || !params || !F || !out || N < 1 || N > (1ll << 24)) return L1LINE_EINVAL;
   HIP_TRY(hipSetDevice(ctx->device));
   return mlp_forward(ctx, params, F, N, out, nullptr, nullptr, (hipStream_t)stream);
 }
 
-int l1line_mlp_grad(l1line_ctx ctx, const float *params, const float *F, const float *y, int64_t N, float *grad,
+int l1line_mlp_forward(l1line_ctx ctx, const float *params, const float *F, int64_t N, float *out, void *stream) {
+  return note(ctx, mlp_forward_impl(ctx, params, F, N, out, stream));
+}
+
+static int mlp_grad_impl(l1line_ctx ctx, const float *params, const float *F, const float *y, int64_t N, float *grad,
                     float *loss, void *stream) {
   if (!ctx || !params || !F || !y || !grad || N < 1 || N > (1ll << 22)) return L1LINE_EINVAL;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -758,7 +846,12 @@ int l1line_mlp_grad(l1line_ctx ctx, const float *params, const float *F, const f
   return L1LINE_OK;
 }
 
-int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2, const float *grad, int64_t step, float lr,
+int l1line_mlp_grad(l1line_ctx ctx, const float *params, const float *F, const float *y, int64_t N, float *grad,
+                    float *loss, void *stream) {
+  return note(ctx, mlp_grad_impl(ctx, params, F, y, N, grad, loss, stream));
+}
+
+static int mlp_adam_impl(l1line_ctx ctx, float *params, float *m1, float *m2, const float *grad, int64_t step, float lr,
                     void *stream) {
   if (!ctx || !params || !m1 || !m2 || !grad || step < 1 || !(lr > 0.0f)) return L1LINE_EINVAL;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -766,6 +859,11 @@ int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2, const f
                      grad, (long long)step, lr, 0.9f, 0.999f, 1e-8f);
   HIP_TRY(hipGetLastError());
   return L1LINE_OK;
+}
+
+int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2, const float *grad, int64_t step, float lr,
+                    void *stream) {
+  return note(ctx, mlp_adam_impl(ctx, params, m1, m2, grad, step, lr, stream));
 }
 
 // ranker scratch layout for a matrix of n x m: sign sums, slope aggregates,
@@ -814,7 +912,7 @@ static int ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   return L1LINE_OK;
 }
 
-int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+static int ranker_features_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
                            float *F, void *stream) {
   if (!ctx || !F) return L1LINE_EINVAL;
   int st = check_matrix(X, n, m, ld);
@@ -826,20 +924,27 @@ int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   return ranker_features(ctx, X, n, m, ld, lambda, F, (hipStream_t)stream);
 }
 
+int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                           float *F, void *stream) {
+  return note(ctx, ranker_features_impl(ctx, X, n, m, ld, lambda, F, stream));
+}
+
 __global__ void k_copy_flag(const int *src, int *dst) {
   if (threadIdx.x == 0) *dst = *src;
 }
 
-int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
-                      const float *params, int32_t K, float margin_threshold, double *v, int64_t *j, double *obj,
-                      int32_t *median_row, int32_t *used_fallback, float *scores, int32_t *status, void *stream) {
-  if (!ctx || !params || !v || !j || !obj) return L1LINE_EINVAL;
+static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                           int32_t K, float margin_threshold, double *v, int64_t *j, double *obj,
+                           int32_t *median_row, int32_t *used_fallback, float *scores, int32_t *status,
+                           void *stream) {
+  if (!ctx || !v || !j || !obj) return L1LINE_EINVAL;
   int st = check_matrix(X, n, m, ld);
   if (st) return st;
   st = check_lambdas(&lambda, 1);
   if (st) return st;
   if (K < 1 || K > m || !(margin_threshold >= 0.0f) || isinf(margin_threshold)) return L1LINE_EINVAL;
   if (m > L1LINE_RANKER_MAX_M) return L1LINE_ESIZE;
+  if (!ctx->rk_have_w) return L1LINE_ENOMODEL;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const RkLayout R = rk_layout(n, m);
@@ -855,7 +960,7 @@ int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int
     st = ranker_features(ctx, X, n, m, ld, lambda, F, s);
     if (st) return st;
   }
-  st = mlp_forward(ctx, params, F, m, sc, nullptr, nullptr, s);
+  st = mlp_forward(ctx, ctx->rk_w, F, m, sc, nullptr, nullptr, s);
   if (st) return st;
   hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, s, sc, (int)m, (int)K, margin_threshold, cand, mask, flag,
                      margin);
@@ -872,6 +977,227 @@ int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int
   if (used_fallback) hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, s, flag, used_fallback);
   HIP_TRY(hipGetLastError());
   return L1LINE_OK;
+}
+
+int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, int32_t K,
+                      float margin_threshold, double *v, int64_t *j, double *obj, int32_t *median_row,
+                      int32_t *used_fallback, float *scores, int32_t *status, void *stream) {
+  return note(ctx, fit_ranked_impl(ctx, X, n, m, ld, lambda, K, margin_threshold, v, j, obj, median_row,
+                                   used_fallback, scores, status, stream));
+}
+
+// ------------------------------------------------------- ranker weights
+static int ensure_rk_w(l1line_ctx ctx) {
+  if (ctx->rk_w) return L1LINE_OK;
+  if (hipMalloc((void **)&ctx->rk_w, 3 * sizeof(float) * MLP_NPARAM) != hipSuccess) {
+    ctx->rk_w = nullptr;
+    return L1LINE_ENOMEM;
+  }
+  HIP_TRY(hipMemset(ctx->rk_w, 0, 3 * sizeof(float) * MLP_NPARAM));
+  return L1LINE_OK;
+}
+
+// Weight file (little endian): "L1RK", u32 version 1, u32 parameter count,
+// u32 flags (bit 0: Adam state follows), i64 step, u64 seed, u64 next
+// example; f32 weights[count]; with bit 0, f32 m1[count], f32 m2[count].
+struct RkHeader {
+  char magic[4];
+  uint32_t version, nparam, flags;
+  int64_t step;
+  uint64_t seed, cursor;
+};
+
+static int rk_write(l1line_ctx ctx, const char *path, bool with_state) {
+  std::vector<float> h((with_state ? 3 : 1) * (size_t)MLP_NPARAM);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(h.data(), ctx->rk_w, sizeof(float) * h.size(), hipMemcpyDeviceToHost));
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "wb");
+  if (!f) return L1LINE_EIO;
+  RkHeader hd;
+  memcpy(hd.magic, "L1RK", 4);
+  hd.version = 1;
+  hd.nparam = MLP_NPARAM;
+  hd.flags = with_state ? 1u : 0u;
+  hd.step = ctx->rk_step;
+  hd.seed = ctx->rk_seed;
+  hd.cursor = ctx->rk_cursor;
+  bool ok = fwrite(&hd, sizeof hd, 1, f) == 1 && fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || rename(tmp.c_str(), path) != 0) {
+    remove(tmp.c_str());
+    return L1LINE_EIO;
+  }
+  return L1LINE_OK;
+}
+
+static int rk_read(l1line_ctx ctx, const char *path) {
+  FILE *f = fopen(path, "rb");
+  if (!f) return L1LINE_EIO;
+  RkHeader hd;
+  std::vector<float> h;
+  bool ok = fread(&hd, sizeof hd, 1, f) == 1 && memcmp(hd.magic, "L1RK", 4) == 0 && hd.version == 1 &&
+            hd.nparam == (uint32_t)MLP_NPARAM && (hd.flags & ~1u) == 0;
+  if (ok) {
+    h.resize(((hd.flags & 1u) ? 3 : 1) * (size_t)MLP_NPARAM);
+    ok = fread(h.data(), sizeof(float), h.size(), f) == h.size();
+  }
+  fclose(f);
+  if (!ok) return L1LINE_EIO;
+  for (float x : h)
+    if (!std::isfinite(x)) return L1LINE_EIO;
+  int st = ensure_rk_w(ctx);
+  if (st) return st;
+  HIP_TRY(hipMemcpy(ctx->rk_w, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+  if (!(hd.flags & 1u)) HIP_TRY(hipMemset(ctx->rk_w + MLP_NPARAM, 0, 2 * sizeof(float) * MLP_NPARAM));
+  ctx->rk_have_w = true;
+  ctx->rk_have_state = (hd.flags & 1u) != 0;
+  ctx->rk_step = hd.step;
+  ctx->rk_seed = hd.seed;
+  ctx->rk_cursor = hd.cursor;
+  return L1LINE_OK;
+}
+
+int l1line_ranker_load(l1line_ctx ctx, const char *path) {
+  if (!ctx || !path) return L1LINE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return note(ctx, L1LINE_EHIP);
+  return note(ctx, rk_read(ctx, path));
+}
+
+int l1line_ranker_save(l1line_ctx ctx, const char *path) {
+  if (!ctx || !path) return L1LINE_EINVAL;
+  if (!ctx->rk_have_w) return note(ctx, L1LINE_ENOMODEL);
+  if (hipSetDevice(ctx->device) != hipSuccess) return note(ctx, L1LINE_EHIP);
+  return note(ctx, rk_write(ctx, path, ctx->rk_have_state));
+}
+
+int l1line_ranker_set_params(l1line_ctx ctx, const float *params, void *stream) {
+  if (!ctx || !params) return L1LINE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return note(ctx, L1LINE_EHIP);
+  int st = ensure_rk_w(ctx);
+  if (st) return note(ctx, st);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ctx->rk_w, params, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemsetAsync(ctx->rk_w + MLP_NPARAM, 0, 2 * sizeof(float) * MLP_NPARAM, s) != hipSuccess)
+    return note(ctx, L1LINE_EHIP);
+  ctx->rk_have_w = true;
+  ctx->rk_have_state = false;
+  ctx->rk_step = 0;
+  return L1LINE_OK;
+}
+
+int l1line_ranker_get_params(l1line_ctx ctx, float *params, void *stream) {
+  if (!ctx || !params) return L1LINE_EINVAL;
+  if (!ctx->rk_have_w) return note(ctx, L1LINE_ENOMODEL);
+  if (hipSetDevice(ctx->device) != hipSuccess) return note(ctx, L1LINE_EHIP);
+  if (hipMemcpyAsync(params, ctx->rk_w, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToDevice,
+                     (hipStream_t)stream) != hipSuccess)
+    return note(ctx, L1LINE_EHIP);
+  return L1LINE_OK;
+}
+
+// splitmix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the host-side stream for the initial weights and
+// the sizes of the training matrices
+static uint64_t splitmix64(uint64_t &x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// He-normal weights (variance 2 / fan-in; 1 / fan-in for the output layer),
+// zero biases, from the seed
+static void rk_init_host(uint64_t seed, std::vector<float> &w) {
+  w.assign(MLP_NPARAM, 0.f);
+  uint64_t x = seed ^ 0x5EEDC0DE12345678ull;
+  auto normal = [&]() {
+    const double u1 = ((double)(splitmix64(x) >> 11) + 0.5) * 0x1p-53, u2 = (double)(splitmix64(x) >> 11) * 0x1p-53;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  };
+  for (int q = 0; q < MLP_IN * MLP_H; ++q) w[OFF_W1 + q] = (float)(normal() * sqrt(2.0 / MLP_IN));
+  for (int q = 0; q < MLP_H * MLP_H; ++q) w[OFF_W2 + q] = (float)(normal() * sqrt(2.0 / MLP_H));
+  for (int q = 0; q < MLP_H; ++q) w[OFF_W3 + q] = (float)(normal() * sqrt(1.0 / MLP_H));
+}
+
+int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps, uint64_t seed) {
+  if (!ctx || steps < 0) return L1LINE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return note(ctx, L1LINE_EHIP);
+  int st = ensure_rk_w(ctx);
+  if (st) return note(ctx, st);
+  // resume from the checkpoint when there is one, else start from the seed
+  FILE *probe = ckpt_path ? fopen(ckpt_path, "rb") : nullptr;
+  if (probe) {
+    fclose(probe);
+    st = rk_read(ctx, ckpt_path);
+    if (st) return note(ctx, st);
+    if (!ctx->rk_have_state) return note(ctx, L1LINE_EIO);
+  } else {
+    std::vector<float> w;
+    rk_init_host(seed, w);
+    if (hipMemcpy(ctx->rk_w, w.data(), sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(ctx->rk_w + MLP_NPARAM, 0, 2 * sizeof(float) * MLP_NPARAM) != hipSuccess)
+      return note(ctx, L1LINE_EHIP);
+    ctx->rk_step = 0;
+    ctx->rk_seed = seed;
+    ctx->rk_cursor = 0;
+  }
+  ctx->rk_have_w = ctx->rk_have_state = true;
+  constexpr int kNmax = 4000, kMmax = 500, kSaveEvery = 1000;
+  constexpr float kLr = 1e-3f;
+  // training buffers: matrix, column info, fit outputs, features, targets, gradient
+  const size_t fb = sizeof(float), db = sizeof(double);
+  const size_t o_X = 0, o_ci = align_up(db * kNmax * kMmax, 256), o_v = o_ci + align_up(sizeof(ColInfo) * kMmax, 256),
+               o_j = o_v + align_up(db * kMmax, 256), o_obj = o_j + 256, o_z = o_obj + 256,
+               o_mass = o_z + align_up(db * kMmax, 256), o_F = o_mass + 256,
+               o_y = o_F + align_up(fb * MLP_IN * kMmax, 256), o_g = o_y + align_up(fb * kMmax, 256),
+               o_loss = o_g + align_up(fb * MLP_NPARAM, 256), total = o_loss + 256;
+  char *buf = nullptr;
+  if (hipMalloc((void **)&buf, total) != hipSuccess) return note(ctx, L1LINE_ENOMEM);
+  double *X = (double *)(buf + o_X), *V = (double *)(buf + o_v), *OBJ = (double *)(buf + o_obj);
+  double *Z = (double *)(buf + o_z), *mass = (double *)(buf + o_mass);
+  int64_t *J = (int64_t *)(buf + o_j);
+  ColInfo *ci = (ColInfo *)(buf + o_ci);
+  float *F = (float *)(buf + o_F), *y = (float *)(buf + o_y), *g = (float *)(buf + o_g), *loss = (float *)(buf + o_loss);
+  hipStream_t s = nullptr;
+  while (st == L1LINE_OK && ctx->rk_step < steps) {
+    // example `cursor` of the seed: its sizes, then its entries on the device
+    uint64_t hx = ctx->rk_seed * 0x9E3779B97F4A7C15ull + ctx->rk_cursor;
+    const uint64_t h = splitmix64(hx);
+    const int n = 500 + (int)(h % 3501), m = 50 + (int)((h >> 32) % 451);
+    const PhiloxKey key{(uint32_t)(h ^ (h >> 32)), (uint32_t)(ctx->rk_seed ^ (ctx->rk_cursor << 20))};
+    hipLaunchKernelGGL(k_gen_training, dim3((unsigned)(((long long)n * m + 255) / 256)), dim3(256), 0, s, X, n, m, key);
+    hipLaunchKernelGGL(k_colprep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, X, n, m, (long long)n, ci);
+    hipLaunchKernelGGL(k_max_mass, dim3(1), dim3(256), 0, s, (const ColInfo *)ci, m, mass);
+    double big = 0.0;
+    if (hipGetLastError() != hipSuccess || hipMemcpy(&big, mass, db, hipMemcpyDeviceToHost) != hipSuccess) {
+      st = L1LINE_EHIP;
+      break;
+    }
+    const double lam = 0.05 * big;
+    // labels: the exact z_j of every column
+    const l1line_problem p = single(X, n, m, n, &lam, 1, V, J, OBJ, nullptr, Z, nullptr);
+    st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr);
+    if (st) break;
+    st = ranker_features(ctx, X, n, m, n, lam, F, s);
+    if (st) break;
+    hipLaunchKernelGGL(k_targets, dim3(1), dim3(256), 0, s, (const double *)Z, m, y);
+    st = mlp_grad_impl(ctx, ctx->rk_w, F, y, m, g, loss, s);
+    if (st) break;
+    ++ctx->rk_step;
+    hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, ctx->rk_w,
+                       ctx->rk_w + MLP_NPARAM, ctx->rk_w + 2 * MLP_NPARAM, (const float *)g,
+                       (long long)ctx->rk_step, kLr, 0.9f, 0.999f, 1e-8f);
+    if (hipGetLastError() != hipSuccess) {
+      st = L1LINE_EHIP;
+      break;
+    }
+    ++ctx->rk_cursor;
+    if (ckpt_path && (ctx->rk_step % kSaveEvery == 0 || ctx->rk_step == steps)) st = rk_write(ctx, ckpt_path, true);
+  }
+  if (hipDeviceSynchronize() != hipSuccess && st == L1LINE_OK) st = L1LINE_EHIP;
+  (void)hipFree(buf);
+  return note(ctx, st);
 }
 
 }  // extern "C"

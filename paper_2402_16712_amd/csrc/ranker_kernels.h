@@ -411,3 +411,94 @@ __global__ void k_topk(const float *__restrict__ score, int m, int K, float thre
     *fallback = (K >= m || mg < threshold) ? 1 : 0;
   }
 }
+
+// ------------------------------------------------------- training matrices
+// Counter-based generator: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC 2011), written from its
+// published definition: ten rounds of two 32x32->64 multiplications with
+// the round keys bumped by the Weyl constants.
+struct PhiloxKey {
+  uint32_t k0, k1;
+};
+__device__ __forceinline__ uint4 philox4x32(uint4 c, PhiloxKey k) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.k0, lo1, hi0 ^ c.w ^ k.k1, lo0);
+    k.k0 += W0;
+    k.k1 += W1;
+  }
+  return c;
+}
+// uniform in (0, 1) from 32 random bits; standard normal by Box-Muller
+__device__ __forceinline__ double unit_open(uint32_t u) { return ((double)u + 0.5) * 0x1p-32; }
+__device__ __forceinline__ double normal_of(uint32_t a, uint32_t b) {
+  return sqrt(-2.0 * log(unit_open(a))) * cos(6.283185307179586 * unit_open(b));
+}
+
+// One training matrix n x m (column-major, ld = n) of the rank-one recipe:
+// x_ik = u_i l_k + e_ik with u_i ~ N(0,1), l_k ~ U[-1,1] on a random 10% of
+// the columns (0 elsewhere), e_ik ~ Laplace(0, 0.1) by inversion; a random
+// 10% of the rows replaced by 20 N(0,1); 1% of the entries set to +0.0.
+// Every random choice is an independent Bernoulli draw keyed by (seed,
+// example, row, column), so no permutation is needed.
+__global__ void k_gen_training(double *__restrict__ X, int n, int m, PhiloxKey key) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * m) return;
+  const int k = (int)(e / n), i = (int)(e % n);
+  const uint4 rr = philox4x32(make_uint4((uint32_t)i, 0xFFFFFFFFu, 1u, 0u), key);   // row draws
+  const uint4 rc = philox4x32(make_uint4(0xFFFFFFFFu, (uint32_t)k, 2u, 0u), key);   // column draws
+  const uint4 re = philox4x32(make_uint4((uint32_t)i, (uint32_t)k, 3u, 0u), key);   // entry draws
+  const double u = normal_of(rr.x, rr.y);
+  const bool outlier_row = unit_open(rr.z) < 0.1;
+  const double l = unit_open(rc.x) < 0.1 ? 2.0 * unit_open(rc.y) - 1.0 : 0.0;
+  double x;
+  if (outlier_row) {
+    x = 20.0 * normal_of(re.x, re.y);
+  } else {
+    const double h = unit_open(re.x) - 0.5;
+    const double lap = -0.1 * (h < 0.0 ? -1.0 : 1.0) * log1p(-2.0 * fabs(h));
+    x = u * l + lap;
+  }
+  if (unit_open(re.z) < 0.01) x = 0.0;
+  X[(long long)k * n + i] = x;
+}
+
+// max over the columns of the column mass (one workgroup of 256)
+__global__ void k_max_mass(const ColInfo *__restrict__ ci, int m, double *__restrict__ out) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) mx = fmax(mx, ci[j].W);
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = blockDim.x >> 1; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// training targets y_j = (z_j - min z) / (mean z - min z) (0 when the
+// objectives are all equal); one workgroup of 256
+__global__ void k_targets(const double *__restrict__ z, int m, float *__restrict__ y) {
+  __shared__ double smin[256], ssum[256];
+  double mn = 1e308, sum = 0.0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    mn = fmin(mn, z[j]);
+    sum += z[j];
+  }
+  smin[threadIdx.x] = mn;
+  ssum[threadIdx.x] = sum;
+  __syncthreads();
+  for (int st = blockDim.x >> 1; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + st]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  const double lo = smin[0], span = ssum[0] / m - lo;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = (float)(span > 0.0 ? (z[j] - lo) / span : 0.0);
+}

@@ -4,9 +4,15 @@ The labels are the exact per-column objectives z_j of Algorithm 1 computed by
 the library's exhaustive GPU fit; the target of column j is its normalized
 gap (z_j - min z) / (mean z - min z), so lower scores mean better
 candidates.  Forward, backward and Adam run in the library's HIP kernels.
+
+Two trainers: the library's own loop (l1line_ranker_train, the `train`
+command below: matrices generated on the device, checkpoints in the
+library's ranker file format) and `Trainer`, the same steps driven from
+Python through the C ABI on matrices from workloads.ranker_matrix_torch.
 """
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -89,15 +95,15 @@ class Trainer:
 
 
 def load_params(path: str, device="cuda:0"):
+    """Weights of a ranker file as a device tensor."""
     import torch
-    with np.load(path, allow_pickle=False) as d:
-        return torch.from_numpy(d["params"]).to(device)
+    w, _, _ = B.read_ranker_file(path)
+    return torch.from_numpy(w).to(device)
 
 
-def evaluate(ctx: B.Context, params, indices, K: int = 32, margin: float = 0.05, rel_tol: float = 1e-9,
-             **kw):
-    """Ranked fit vs exhaustive fit on evaluation matrices: fraction within
-    rel_tol of the exhaustive objective, fallback rate, times."""
+def evaluate(ctx: B.Context, indices, K: int = 32, margin: float = 0.05, rel_tol: float = 1e-9, **kw):
+    """Ranked fit (the context's weights) vs exhaustive fit on evaluation
+    matrices: within rel_tol of the exhaustive objective, fallback, times."""
     import torch
     rows = []
     for idx in indices:
@@ -107,7 +113,7 @@ def evaluate(ctx: B.Context, params, indices, K: int = 32, margin: float = 0.05,
         ex = ctx.fit(X, lam, rows=False, z_all=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rk = ctx.fit_ranked(X, lam, params, K, margin)
+        rk = ctx.fit_ranked(X, lam, K, margin)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         ze, zr = float(ex["obj"].item()), float(rk["obj"].item())
@@ -117,25 +123,22 @@ def evaluate(ctx: B.Context, params, indices, K: int = 32, margin: float = 0.05,
     return rows
 
 
-TRAIN_BASE = 1000        # training matrices are indices 1000, 1001, ...
 EVAL_BASE = 90000        # evaluation matrices (10000 x 4000) are 90000, 90001, ...
-WEIGHTS = __file__.rsplit("/", 1)[0] + "/ranker_weights.npz"
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "ranker_weights.l1rk")
 
 
 def _main(argv=None):
     import argparse
     import json
 
-    import torch
     ap = argparse.ArgumentParser(description="train / evaluate the candidate ranker on the GPU")
     sub = ap.add_subparsers(dest="cmd", required=True)
-    t = sub.add_parser("train")
-    t.add_argument("--examples", type=int, default=20000)
-    t.add_argument("--ckpt", default="ranker_ckpt.npz", help="checkpoint (resumed if present)")
-    t.add_argument("--out", default=WEIGHTS, help="trained parameters")
-    t.add_argument("--lr", type=float, default=1e-3)
-    t.add_argument("--seed", type=int, default=0)
-    t.add_argument("--save-every", type=int, default=1000)
+    t = sub.add_parser("train", help="native training loop (l1line_ranker_train)")
+    t.add_argument("--steps", type=int, default=20000)
+    t.add_argument("--seed", type=int, default=1)
+    t.add_argument("--ckpt", default="ranker_ckpt.l1rk", help="checkpoint (resumed if present)")
+    t.add_argument("--out", default=WEIGHTS, help="trained weights")
+    t.add_argument("--chunk", type=int, default=2000, help="steps between progress lines")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--count", type=int, default=300)
@@ -146,26 +149,19 @@ def _main(argv=None):
     a = ap.parse_args(argv)
     ctx = B.Context(0)
     if a.cmd == "train":
-        tr = Trainer(ctx, seed=a.seed, lr=a.lr)
-        tr.cursor = TRAIN_BASE
-        try:
-            tr.load(a.ckpt)
-            print(f"resumed at step {tr.step}", flush=True)
-        except OSError:
-            pass
         t0 = time.perf_counter()
-        while tr.step < a.examples:
-            chunk = min(a.save_every, a.examples - tr.step)
-            losses = tr.train(chunk)
-            tr.save(a.ckpt)
-            mean = float(torch.stack(losses).mean().item())
-            print(json.dumps({"step": tr.step, "mean_loss": mean, "s": time.perf_counter() - t0}), flush=True)
-        np.savez(a.out, params=tr.params.cpu().numpy())
+        done = 0
+        while done < a.steps:
+            done = min(a.steps, done + a.chunk)
+            ctx.ranker_train(done, a.seed, a.ckpt)
+            print(json.dumps({"steps": done, "s": round(time.perf_counter() - t0, 2)}), flush=True)
+        w, _, _ = B.read_ranker_file(a.ckpt)
+        B.write_ranker_file(a.out, w)
     else:
-        params = load_params(a.weights)
+        ctx.ranker_load(a.weights)
         rows = []
         for q in range(a.count):
-            r = evaluate(ctx, params, [EVAL_BASE + q], a.K, a.margin, n=a.n, m=a.m)[0]
+            r = evaluate(ctx, [EVAL_BASE + q], a.K, a.margin, n=a.n, m=a.m)[0]
             rows.append(r)
             print(json.dumps(r), flush=True)
         ok = sum(r["ok"] for r in rows)

@@ -32,7 +32,7 @@ def test_library_loads_and_exports_header_symbols():
 
 
 def test_strerror_names_every_code():
-    for c in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+    for c in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10):
         assert B.strerror(c) != "unknown status"
     assert B.strerror(-99) == "unknown status"
 
@@ -49,7 +49,9 @@ class _Fake:
     """A non-null context pointer: argument checks run before it is used."""
 
     def __init__(self):
-        self.buf = ctypes.create_string_buffer(64)
+        # zeroed and larger than the context structure: a rejected call
+        # records its code in the context's sticky error field
+        self.buf = ctypes.create_string_buffer(4096)
         self.h = ctypes.cast(self.buf, ctypes.c_void_p)
 
 
@@ -96,8 +98,9 @@ def test_stats_and_create_checks():
     assert lib.l1line_column_stats(None, P(1), 5, 5, 5, None, None, None, None) == B.EINVAL
     f = _Fake()
     assert lib.l1line_column_stats(f.h, P(1), 5, 5, 4, None, None, None, None) == B.EINVAL
-    assert lib.l1line_create(None, 0) == B.EINVAL
+    assert lib.l1line_create(None, 0, None) == B.EINVAL
     assert lib.l1line_destroy(None) == B.EINVAL
+    assert lib.l1line_last_error(None) == B.EINVAL
 
 
 def test_binding_refuses_without_library(monkeypatch, tmp_path):
@@ -129,3 +132,45 @@ def test_batch_host_argument_checks():
     assert lib.l1line_autotune(f.h, cast, 0, None, None) == B.EINVAL
     assert lib.l1line_tune_get(None, None) == B.EINVAL
     assert lib.l1line_tune_set(None, None) == B.EINVAL
+
+
+def test_ranker_host_checks():
+    lib = B.lib()
+    f = _Fake()
+    P = ctypes.c_void_p
+    assert lib.l1line_ranker_load(None, b"x") == B.EINVAL
+    assert lib.l1line_ranker_load(f.h, None) == B.EINVAL
+    assert lib.l1line_ranker_save(f.h, None) == B.EINVAL
+    assert lib.l1line_ranker_save(f.h, b"/nonexistent/x") == B.ENOMODEL      # no weights yet
+    assert lib.l1line_ranker_get_params(f.h, P(1), None) == B.ENOMODEL
+    assert lib.l1line_ranker_set_params(f.h, None, None) == B.EINVAL
+    assert lib.l1line_ranker_train(None, None, 10, 0) == B.EINVAL
+    assert lib.l1line_ranker_train(f.h, None, -1, 0) == B.EINVAL
+    out = [P(1)] * 3
+    # K outside [1, m], a bad threshold, then no weights
+    assert lib.l1line_fit_ranked(f.h, P(1), 10, 4, 10, 0.5, 0, 0.1, *out, None, None, None, None, None) == B.EINVAL
+    assert lib.l1line_fit_ranked(f.h, P(1), 10, 4, 10, 0.5, 5, 0.1, *out, None, None, None, None, None) == B.EINVAL
+    assert lib.l1line_fit_ranked(f.h, P(1), 10, 4, 10, 0.5, 2, -1.0, *out, None, None, None, None, None) == B.EINVAL
+    assert lib.l1line_fit_ranked(f.h, P(1), 10, 70000, 10, 0.5, 2, 0.1, *out, None, None, None, None,
+                                 None) == B.ESIZE
+    assert lib.l1line_fit_ranked(f.h, P(1), 10, 4, 10, 0.5, 2, 0.1, *out, None, None, None, None,
+                                 None) == B.ENOMODEL
+
+
+def test_ranker_file_roundtrip(tmp_path):
+    w = np.random.default_rng(0).standard_normal(B.MLP_PARAMS).astype(np.float32)
+    path = tmp_path / "w.l1rk"
+    B.write_ranker_file(path, w)
+    assert path.stat().st_size == 40 + 4 * B.MLP_PARAMS
+    r, state, head = B.read_ranker_file(path)
+    assert r.tobytes() == w.tobytes() and state is None and head == dict(step=0, seed=0, cursor=0)
+    bad = tmp_path / "bad.l1rk"
+    bad.write_bytes(path.read_bytes()[:100])
+    with pytest.raises(ValueError):
+        B.read_ranker_file(bad)
+
+
+def test_shipped_ranker_weights_readable():
+    from paper_2402_16712_amd import ranker
+    w, _, _ = B.read_ranker_file(ranker.WEIGHTS)
+    assert w.shape == (B.MLP_PARAMS,) and np.all(np.isfinite(w))

@@ -258,3 +258,27 @@ def test_large_fit_full_size_sampled(ctx):
         if j == js:
             assert r["V"][0].tobytes() == g["v"].tobytes()
             assert np.array_equal(r["ROW"][0], g["row"])
+
+
+def test_sticky_error_and_tune_cache(tmp_path):
+    import torch
+    from paper_2402_16712_amd import binding as B
+    path = str(tmp_path / "tune.txt")
+    c = B.Context(0, tune_cache_path=path)
+    try:
+        Y = wl.random_small(10, 100, 5)
+        Y[3, 2] = np.nan
+        c.fit(B.device_matrix(np.asfortranarray(Y)), 0.5)
+        torch.cuda.synchronize()
+        assert c.last_error() == B.ENONFINITE
+        assert c.last_error() == B.OK
+        probs = [(B.device_matrix(wl.random_small(40 + q, 60, 5)), np.array([0.1, 1.0])) for q in range(3)]
+        best = c.autotune(probs)
+        assert open(path).read().split() == ["l1line-tune"] + [str(x) for x in best]
+    finally:
+        c.close()
+    c2 = B.Context(0, tune_cache_path=path)
+    try:
+        assert c2.tune_get() == best
+    finally:
+        c2.close()

@@ -181,8 +181,8 @@ def test_fit_ranked_candidates(ctx, n, m, K, seed):
     _say(f"fit_ranked {n}x{m} K={K}")
     X = wl.rank_one_matrix(n, m, max(1, m // 10), n // 10, 20.0, 0.01, (21, seed))
     lam = 0.05 * wl.max_column_mass(X)
-    P = _dev(_params(seed))
-    r = ctx.fit_ranked(B.device_matrix(X), lam, P, K, 0.0)
+    ctx.ranker_set_params(_dev(_params(seed)))
+    r = ctx.fit_ranked(B.device_matrix(X), lam, K, 0.0)
     assert int(r["status"].item()) == 0
     assert int(r["used_fallback"].item()) == 0
     scores = r["scores"].cpu().numpy()
@@ -204,7 +204,8 @@ def test_fit_ranked_fallback(ctx, K):
     from paper_2402_16712_amd import binding as B
     X = wl.rank_one_matrix(500, 30, 3, 50, 20.0, 0.01, (22, K))
     lam = 0.05 * wl.max_column_mass(X)
-    r = ctx.fit_ranked(B.device_matrix(X), lam, _dev(_params(9)), K, 1e30)
+    ctx.ranker_set_params(_dev(_params(9)))
+    r = ctx.fit_ranked(B.device_matrix(X), lam, K, 1e30)
     ref = O.fit(X, lam)
     assert int(r["status"].item()) == 0
     assert int(r["used_fallback"].item()) == 1
@@ -217,10 +218,94 @@ def test_fit_ranked_fallback(ctx, K):
 def test_fit_ranked_bad_args(ctx):
     from paper_2402_16712_amd import binding as B
     X = B.device_matrix(wl.random_small(1, 20, 5))
-    P = _dev(_params(0))
+    ctx.ranker_set_params(_dev(_params(0)))
+    ctx.last_error()                           # clear
     for K, thr in ((0, 0.1), (6, 0.1), (2, -1.0), (2, float("nan")), (2, float("inf"))):
         with pytest.raises(B.L1LineError):
-            ctx.fit_ranked(X, 1.0, P, K, thr)
+            ctx.fit_ranked(X, 1.0, K, thr)
+    assert ctx.last_error() == B.EINVAL        # the first rejected call, then cleared
+    assert ctx.last_error() == B.OK
+
+
+def test_fit_ranked_needs_weights():
+    from paper_2402_16712_amd import binding as B
+    c = B.Context(0)
+    try:
+        with pytest.raises(B.L1LineError) as e:
+            c.fit_ranked(B.device_matrix(wl.random_small(2, 30, 6)), 1.0, 2, 0.1)
+        assert e.value.code == B.ENOMODEL
+    finally:
+        c.close()
+
+
+def test_ranker_save_load_roundtrip(ctx, tmp_path):
+    from paper_2402_16712_amd import binding as B
+    P = _dev(_params(5))
+    ctx.ranker_set_params(P)
+    path = str(tmp_path / "w.l1rk")
+    ctx.ranker_save(path)
+    w, state, head = B.read_ranker_file(path)
+    assert w.tobytes() == P.cpu().numpy().tobytes() and state is None
+    c = B.Context(0)
+    try:
+        c.ranker_load(path)
+        assert c.ranker_get_params().cpu().numpy().tobytes() == w.tobytes()
+        bad = tmp_path / "bad.l1rk"
+        bad.write_bytes(open(path, "rb").read()[:64])
+        with pytest.raises(B.L1LineError) as e:
+            c.ranker_load(str(bad))
+        assert e.value.code == B.EIO
+    finally:
+        c.close()
+
+
+def test_shipped_weights_rank_exactly():
+    """The shipped weights through l1line_ranker_load: the ranked fit is the
+    oracle's exact optimum over the candidates it chose."""
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import ranker
+    c = B.Context(0)
+    try:
+        c.ranker_load(ranker.WEIGHTS)
+        X = wl.rank_one_matrix(600, 70, 7, 60, 20.0, 0.01, (23, 0))
+        lam = 0.05 * wl.max_column_mass(X)
+        r = c.fit_ranked(B.device_matrix(X), lam, 8, 0.0)
+        cand, _ = _topk_ref(r["scores"].cpu().numpy(), 8)
+        ref = O.fit(X, lam)
+        z = ref["z_all"][cand]
+        jbest = int(cand[np.lexsort((cand, z))[0]])
+        assert int(r["j"].item()) == jbest
+        assert np.float64(r["obj"].item()).tobytes() == np.float64(ref["z_all"][jbest]).tobytes()
+    finally:
+        c.close()
+
+
+def test_native_train_resume(tmp_path):
+    """l1line_ranker_train: 6 steps in one run equal 3 steps, a checkpoint
+    and 3 more in a fresh context, bit for bit."""
+    from paper_2402_16712_amd import binding as B
+    a, b = str(tmp_path / "a.l1rk"), str(tmp_path / "b.l1rk")
+    c1 = B.Context(0)
+    try:
+        c1.ranker_train(6, seed=3, ckpt_path=a)
+    finally:
+        c1.close()
+    c2 = B.Context(0)
+    try:
+        c2.ranker_train(3, seed=3, ckpt_path=b)
+    finally:
+        c2.close()
+    c3 = B.Context(0)
+    try:
+        c3.ranker_train(6, seed=99, ckpt_path=b)     # resumes: the file's seed wins
+    finally:
+        c3.close()
+    wa, sa, ha = B.read_ranker_file(a)
+    wb, sb, hb = B.read_ranker_file(b)
+    assert ha == hb == dict(step=6, seed=3, cursor=6)
+    assert sa is not None and np.all(np.isfinite(wa))
+    assert wa.tobytes() == wb.tobytes()
+    assert sa[0].tobytes() == sb[0].tobytes() and sa[1].tobytes() == sb[1].tobytes()
 
 
 def test_trainer_resume(ctx, tmp_path):
