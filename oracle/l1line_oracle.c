@@ -59,6 +59,11 @@
  *   -4  a selected ratio overflowed to +-inf (results then unspecified)
  *   -5  out of host memory
  *
+ * ALGORITHM 2 (oracle_breakpoints): the breakpoints of every segment's
+ *   solution path v_k(lambda) and the lambda_max beyond which v_k = 0, from
+ *   the paper's loop over the sorted points with exact sums (see the
+ *   function's comment for the one reading it takes).
+ *
  * PINS (tests/test_oracle_*.py): the worked example of Sec. 3.1 (Table I,
  * Fig. 1 lines, the breakpoints and the maximum useful lambda), exact
  * rational brute force over every breakpoint on tiny inputs, an LP solver on
@@ -462,6 +467,120 @@ int oracle_fit_path(const double *X, int64_t n, int64_t m, int64_t ld,
 }
 
 /* Threads OpenMP will use for oracle_fit_path (1 without OpenMP). */
+/* ------------------------------------------------------------ Algorithm 2 */
+/* r = a - b for a >= b */
+static void big_sub(big *r, const big *a, const big *b)
+{
+    uint64_t borrow = 0;
+    for (int t = 0; t < NLIMB; ++t) {
+        unsigned __int128 d = (unsigned __int128)a->d[t] - b->d[t] - borrow;
+        r->d[t] = (uint64_t)d;
+        borrow = (uint64_t)(d >> 64) ? 1 : 0;
+    }
+}
+
+/* The double nearest to a * 2^-1074 (ties to even). */
+static double big_to_double(const big *a)
+{
+    int top = -1;
+    for (int t = NLIMB - 1; t >= 0 && top < 0; --t)
+        if (a->d[t]) top = t * 64 + 63 - __builtin_clzll(a->d[t]);
+    if (top < 0) return 0.0;
+    if (top <= 52) {                         /* exact: at most 53 bits */
+        uint64_t v = a->d[0];
+        return ldexp((double)v, -1074);
+    }
+    int lo = top - 52;                       /* keep bits top..lo */
+    uint64_t q = 0;
+    for (int b = top; b >= lo; --b) q = (q << 1) | ((a->d[b / 64] >> (b % 64)) & 1u);
+    int half = (a->d[(lo - 1) / 64] >> ((lo - 1) % 64)) & 1u;
+    int sticky = 0;
+    for (int b = lo - 2; b >= 0 && !sticky; --b) sticky = (a->d[b / 64] >> (b % 64)) & 1u;
+    if (half && (sticky || (q & 1u))) ++q;  /* q may become 2^53: still exact */
+    return ldexp((double)q, lo - 1074);
+}
+
+/* Algorithm 2 for one segment (preserved j, column k), in the paper's
+ * notation: over the sorted points r_p (weights w_p = |x_pj|),
+ *   lambda_p = sgn(r_p) (sum of the weights after p - sum before p) - w_p,
+ * a breakpoint max(0, lambda_p) with v_k = r_p wherever lambda_p + 2 w_p > 0,
+ * and lambda_max = the largest lambda_p + 2 w_p (at least 0), where v_k
+ * becomes 0.  Every sum is exact (big integers); each lambda is then rounded
+ * once to the nearest double.
+ * Reading: zero ratios (sgn 0) are left out of the loop -- by Lemma 1 a
+ * point at 0 never moves the minimiser away from 0 and v_k = 0 is the
+ * terminal entry -- so lambda_max is Lemma 1's exact threshold
+ * max(0, 2A - W, W - 2B).  The entries are returned in increasing lambda:
+ * on the negative side the sorted order, on the positive side its reverse,
+ * and then the terminal entry (lambda_max, 0, row -1).  With the R3 rule the
+ * solution on [lam[t], lam[t+1]) is (v[t], row[t]).
+ *   cap      capacity of lam, v, row (nullable when cap = 0)
+ *   count    entries of the segment (the terminal one included)
+ *   lmax     lambda_max */
+int oracle_breakpoints(const double *X, int64_t n, int64_t m, int64_t ld, int64_t j,
+                       int64_t k, int64_t cap, double *lam, double *v, int32_t *row,
+                       int64_t *count, double *lmax)
+{
+    int st = check_x(X, n, m, ld);
+    if (st) return st;
+    if (j < 0 || j >= m || k < 0 || k >= m || j == k || !count || !lmax) return OR_EINVAL;
+    point *pts = (point *)malloc((size_t)n * sizeof(point) + 1);
+    big *prefix = (big *)malloc(((size_t)n + 1) * sizeof(big));   /* weight before p */
+    if (!pts || !prefix) { free(pts); free(prefix); return OR_ENOMEM; }
+    int64_t np = build_points(X, n, ld, j, k, pts);
+    big_zero(&prefix[0]);
+    for (int64_t p = 0; p < np; ++p) {
+        prefix[p + 1] = prefix[p];
+        big_add_double(&prefix[p + 1], pts[p].w);
+    }
+    big W = prefix[np], before, after, lp, lp2, best;
+    big_zero(&best);
+    int64_t c = 0;
+    /* visit the points in the order the entries are listed: negative side in
+     * sorted order, positive side from 0 outwards */
+    int64_t N = 0, Z = 0;
+    while (N < np && pts[N].r < 0.0) ++N;
+    while (N + Z < np && pts[N + Z].r == 0.0) ++Z;
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t first = pass == 0 ? 0 : np - 1, last = pass == 0 ? N : N + Z - 1, step = pass == 0 ? 1 : -1;
+        for (int64_t p = first; p != last; p += step) {
+            /* weight before p and after p in sorted order */
+            before = prefix[p];
+            big_sub(&after, &W, &before);
+            big wp;
+            big_zero(&wp);
+            big_add_double(&wp, pts[p].w);
+            big_sub(&after, &after, &wp);
+            /* lambda_p + 2 w_p = sgn (after - before) + w_p, kept as a signed
+             * pair (positive part, negative part) */
+            big pos, neg;
+            if (pts[p].r < 0.0) { pos = before; neg = after; }    /* before - after */
+            else { pos = after; neg = before; }                   /* after - before */
+            big_add(&lp2, &pos, &wp);                             /* lambda_p + 2 w_p = pos + w_p - neg */
+            if (big_cmp(&lp2, &neg) <= 0) continue;               /* not > 0 */
+            big_sub(&lp2, &lp2, &neg);
+            if (big_cmp(&lp2, &best) > 0) best = lp2;
+            /* max(0, lambda_p) = max(0, pos - neg - w_p) */
+            big negw;
+            big_add(&negw, &neg, &wp);
+            if (big_cmp(&pos, &negw) > 0) big_sub(&lp, &pos, &negw); else big_zero(&lp);
+            if (c < cap) {
+                lam[c] = big_to_double(&lp);
+                v[c] = pts[p].r;
+                row[c] = (int32_t)pts[p].row;
+            }
+            ++c;
+        }
+    }
+    if (c < cap) { lam[c] = big_to_double(&best); v[c] = 0.0; row[c] = -1; }
+    ++c;
+    *count = c;
+    *lmax = big_to_double(&best);
+    free(pts);
+    free(prefix);
+    return OR_OK;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -56,6 +56,7 @@ def _load():
         lib.oracle_segment.argtypes = [P, I64, I64, I64, I64, I64, P, I64, I, P, P, P]
         lib.oracle_fit_j.argtypes = [P, I64, I64, I64, I64, P, I64, I, P, P, P, P, P, P]
         lib.oracle_fit_path.argtypes = [P, I64, I64, I64, P, I64, I, I, P, P, P, P, P]
+        lib.oracle_breakpoints.argtypes = [P, I64, I64, I64, I64, I64, I64, P, P, P, P, P]
         for f in (lib.oracle_column_stats, lib.oracle_segment, lib.oracle_fit_j,
                   lib.oracle_fit_path):
             f.restype = ctypes.c_int
@@ -147,3 +148,42 @@ def fit(X, lam, tie_rule=TIE_R3, nthreads=0):
     r = fit_path(X, [lam], tie_rule, nthreads)
     return dict(v=r["V"][0], j=int(r["J"][0]), obj=float(r["OBJ"][0]), row=r["ROW"][0],
                 z_all=r["ZALL"][0], status=r["status"])
+
+
+def breakpoints_segment(X, j, k):
+    """Algorithm 2 for one segment: (lam, v, row) entries in increasing lambda
+    (the terminal entry (lambda_max, 0, -1) last) and lambda_max."""
+    X, n, m = _prep(X)
+    cnt = ctypes.c_int64()
+    lmax = ctypes.c_double()
+    _check(_load().oracle_breakpoints(_ptr(X), n, m, n, int(j), int(k), 0, None, None, None,
+                                      ctypes.byref(cnt), ctypes.byref(lmax)), "breakpoints")
+    c = cnt.value
+    lam, v, row = np.empty(c), np.empty(c), np.empty(c, dtype=np.int32)
+    _check(_load().oracle_breakpoints(_ptr(X), n, m, n, int(j), int(k), c, _ptr(lam), _ptr(v), _ptr(row),
+                                      ctypes.byref(cnt), ctypes.byref(lmax)), "breakpoints")
+    return lam, v, row, lmax.value
+
+
+def breakpoints(X):
+    """Algorithm 2 for every segment, as the GPU lays it out: offsets[m*m+1]
+    (segment g = j*m + k; the diagonal has no entries), lambda_max[m*m] (0 on
+    the diagonal), and the concatenated lam, v, row."""
+    X, n, m = _prep(X)
+    offs = [0]
+    lmax = np.zeros(m * m)
+    lams, vs, rows = [], [], []
+    for j in range(m):
+        for k in range(m):
+            if k == j:
+                offs.append(offs[-1])
+                continue
+            la, v, r, lm = breakpoints_segment(X, j, k)
+            lmax[j * m + k] = lm
+            lams.append(la)
+            vs.append(v)
+            rows.append(r)
+            offs.append(offs[-1] + len(la))
+    cat = (lambda a, dt: np.concatenate(a) if a else np.empty(0, dtype=dt))
+    return dict(offsets=np.array(offs, dtype=np.int64), lambda_max=lmax, lam=cat(lams, np.float64),
+                v=cat(vs, np.float64), row=cat(rows, np.int32))
