@@ -279,12 +279,47 @@ int l1line_ranker_get_params(l1line_ctx ctx, float *params, void *stream);
 int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps,
                         uint64_t seed);
 
+/* ------------------------------------------------------------------------
+ * Algorithm 2 (Sec. 2): the breakpoints of every segment's solution path.
+ * For preserved column j and column k (segment g = j*m + k), v_k(lambda) of
+ * Algorithm 1 (tie rule as above) is piecewise constant in lambda; its
+ * entries, in increasing lambda, are (lam, v, row) triples: v_k = v (median
+ * row `row`) for lambda in [lam[t], lam[t+1]), starting at lam = 0, and a
+ * terminal entry (lambda_max, 0, -1) from which v_k = 0.  With the points
+ * sorted by (ratio, row), exact prefix weights S_p, W = sum of the weights,
+ * A = weight of the negative ratios, B = A + weight of the zero ratios:
+ *   negative side (2A > W): points p from the lambda = 0 minimiser up to the
+ *     last negative one, lam = max(0, 2 S_{p-1} - W); lambda_max = 2A - W;
+ *   positive side (W > 2B): points from the lambda = 0 minimiser down to the
+ *     first positive one, lam = max(0, W - 2 S_p); lambda_max = W - 2B;
+ *   otherwise the single entry (0, 0, -1).
+ * These are Algorithm 2's lambda_p = sgn(r_p)(weight after p - weight before
+ * p) - w_p kept where lambda_p + 2 w_p > 0, zero ratios left out (they never
+ * move the minimiser off 0).  Each lam is exact and rounded once to the
+ * nearest double.  Segments with j = k, and every segment of a column j
+ * with a NaN, an infinity or too wide a range, have no entries.
+ *   offsets     [m*m + 1] int64 (DEVICE, required): entries of segment g are
+ *               [offsets[g], offsets[g+1]); offsets[m*m] = total entries
+ *   lambda_max  [m*m] (DEVICE, nullable); 0 where a segment has no entries
+ *   lam, v, row [capacity] (DEVICE; nullable when capacity = 0)
+ *   status      as l1line_fit, and ESIZE (nothing written to lam, v, row)
+ *               when the total exceeds capacity
+ * Usage: a call with capacity 0 fills offsets; read offsets[m*m], size the
+ * arrays, call again.  Host errors: as l1line_fit; ESIZE for m >
+ * L1LINE_BP_MAX_M. */
+#define L1LINE_BP_MAX_M 8192
+int l1line_breakpoints(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                       int64_t ld, int64_t *offsets, double *lambda_max,
+                       double *lam, double *v, int32_t *row, int64_t capacity,
+                       int32_t *status, void *stream);
+
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.
  * l1line_profile_read waits for the recorded events, returns the summed
  * duration (ms) and launch count of the kernels whose name is `kernel`
  * ("colprep", "signsum", "fit_seg", "reduce", "argmin", "features",
- * "mlp_fwd", "mlp_bwd"; NULL = all), and with reset != 0
+ * "mlp_fwd", "mlp_bwd", "bp_count", "bp_emit"; NULL = all), and with
+ * reset != 0
  * forgets every record.  Outputs are HOST pointers (nullable). */
 int l1line_profile(l1line_ctx ctx, int enable);
 int l1line_profile_read(l1line_ctx ctx, const char *kernel, double *total_ms,

@@ -23,7 +23,8 @@ EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_er
            "l1line_fit", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
            "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
-           "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train"]
+           "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train",
+           "l1line_breakpoints"]
 BATCH_GRAPH = 1
 FEATURES = 32
 MLP_PARAMS = 20865
@@ -62,6 +63,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_ranker_set_params.argtypes = [P, P, P]
         L.l1line_ranker_get_params.argtypes = [P, P, P]
         L.l1line_ranker_train.argtypes = [P, ctypes.c_char_p, I64, ctypes.c_uint64]
+        L.l1line_breakpoints.argtypes = [P, P, I64, I64, I64, P, P, P, P, P, I64, P, P]
         L.l1line_destroy.argtypes = [P]
         L.l1line_strerror.argtypes = [I32]
         L.l1line_strerror.restype = ctypes.c_char_p
@@ -86,7 +88,7 @@ def lib() -> ctypes.CDLL:
                   "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
                   "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked",
                   "l1line_last_error", "l1line_ranker_load", "l1line_ranker_save", "l1line_ranker_set_params",
-                  "l1line_ranker_get_params", "l1line_ranker_train"):
+                  "l1line_ranker_get_params", "l1line_ranker_train", "l1line_breakpoints"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -336,6 +338,26 @@ class Context:
                                        _ptr(out["v"]), _ptr(out["j"]), _ptr(out["obj"]), _ptr(out["row"]),
                                        _ptr(out["used_fallback"]), _ptr(out["scores"]), _ptr(out["status"]),
                                        self._stream()), "l1line_fit_ranked")
+        return out
+
+    def breakpoints(self, X):
+        """Algorithm 2 for every segment: dict offsets [m*m+1], lambda_max
+        [m*m], lam, v, row [total], status (device tensors).  Two calls: the
+        first sizes the outputs (one host synchronisation)."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        offsets = self._empty((m * m + 1,), torch.int64)
+        lmax = self._empty((m * m,), torch.float64)
+        status = self._empty((1,), torch.int32)
+        _check(lib().l1line_breakpoints(self._h, _ptr(X), n, m, ld, _ptr(offsets), _ptr(lmax), None, None, None,
+                                        0, _ptr(status), self._stream()), "l1line_breakpoints")
+        total = int(offsets[-1].item())
+        out = dict(offsets=offsets, lambda_max=lmax, lam=self._empty((total,), torch.float64),
+                   v=self._empty((total,), torch.float64), row=self._empty((total,), torch.int32), status=status)
+        if total > 0:
+            _check(lib().l1line_breakpoints(self._h, _ptr(X), n, m, ld, _ptr(offsets), _ptr(lmax), _ptr(out["lam"]),
+                                            _ptr(out["v"]), _ptr(out["row"]), total, _ptr(status),
+                                            self._stream()), "l1line_breakpoints")
         return out
 
     def ranker_load(self, path):

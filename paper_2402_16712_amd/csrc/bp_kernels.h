@@ -1,0 +1,324 @@
+// bp_kernels.h -- Algorithm 2 (Sec. 2): the breakpoints of every segment's
+// solution path v_k(lambda) and the lambda_max beyond which v_k = 0.
+//
+// For the segment (j, k) with the points sorted by (ratio, row), exact prefix
+// weights S_p, W = S_n', A the weight of the negative ratios and B = A + the
+// weight of the zero ratios:
+//   * 0 minimises at lambda = 0 (2A <= W <= 2B): one entry (0, 0, row -1);
+//   * negative side (2A > W): from the lambda = 0 minimiser p0 up to the last
+//     negative point, the entry of point p is (max(0, 2 S_{p-1} - W), r_p, i_p),
+//     then the terminal entry (2A - W, 0, -1);
+//   * positive side (W > 2B): from p0 down to the first positive point, the
+//     entry of p is (max(0, W - 2 S_p), r_p, i_p), then (W - 2B, 0, -1).
+// This is the paper's loop (lambda_p = sgn(r_p)(weight after p - weight
+// before p) - w_p, kept where lambda_p + 2 w_p > 0) with the zero ratios left
+// out, listed in increasing lambda.  Each lambda is exact in 128-bit fixed
+// point and rounded once to the nearest double.  The lambda = 0 minimiser
+// (v, row) comes from the segment kernel run at lambda = 0.
+//
+// Two kernels, one wave per segment: k_bp_count (entries per segment and
+// lambda_max), then, after the host scans the counts into offsets,
+// k_bp_emit (the entries).  Column j is read from global memory (it stays in
+// L2 across the segments of one j); the entries of a window of keys are
+// sorted in the wave's LDS list, windows too large for it are halved in key
+// space, and a single key with more tied rows than the list holds is
+// streamed in row order (its rows are already in sorted order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fit_kernels.h"
+
+// The double nearest to x * 2^e0 (ties to even); x < 2^127, e0 >= -1074.
+__device__ __forceinline__ double fixed_to_double(u128 x, int e0) {
+  if (x == 0) return 0.0;
+  const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+  const int h = hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);   // top bit
+  // bits kept: 53 in the normal range, fewer where the result is subnormal
+  int keep = 53;
+  if (e0 + h < -1022) keep = 53 - (-1022 - (e0 + h));
+  const int shift = h + 1 - keep;                  // bits rounded away
+  if (shift <= 0) return ldexp((double)lo, e0);    // exact (x < 2^53)
+  // e0 >= -1074 keeps keep >= 1: the result is at least the smallest subnormal
+  u128 q = x >> shift;
+  const u128 rem = x & (((u128)1 << shift) - 1), half = (u128)1 << (shift - 1);
+  if (rem > half || (rem == half && (q & 1))) q += 1;
+  return ldexp((double)(uint64_t)q, e0 + shift);
+}
+
+// Is element (key, row) at or above the pair (lk, lr) in sorted order?
+__device__ __forceinline__ bool pair_ge(uint64_t key, int row, uint64_t lk, int lr) {
+  return key > lk || (key == lk && row >= lr);
+}
+__device__ __forceinline__ bool pair_le(uint64_t key, int row, uint64_t hk, int hr) {
+  return key < hk || (key == hk && row <= hr);
+}
+
+// ------------------------------------------------------------------ counts
+// counts[g] (int64, written to offsets + 1 + g) and lambda_max[g] of segment
+// g = j m + k; V0, R0: v_k and its row at lambda = 0 (m x m, row -1 for 0).
+__global__ void __launch_bounds__(256)
+k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColInfo *__restrict__ ci,
+           const double *__restrict__ V0, const int *__restrict__ R0, long long *__restrict__ counts,
+           double *__restrict__ lmax) {
+  const int lane = threadIdx.x & 63;
+  const long long nseg = (long long)m * m;
+  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+  const int T = (n + 63) >> 6;
+  int Tp = 1;
+  while (Tp < T) Tp <<= 1;
+  for (long long g = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < nseg; g += waves) {
+    const int j = (int)(g / m), k = (int)(g % m);
+    const ColInfo cj = ci[j];
+    if (j == k || cj.flags) {
+      if (lane == 0) {
+        counts[g] = 0;
+        lmax[g] = 0.0;
+      }
+      continue;
+    }
+    const SegIO s{X + (long long)k * ld, X + (long long)j * ld, n, T, Tp, cj.e0, lane};
+    const int r0 = R0[g];
+    const double v0 = V0[g];
+    const uint64_t mkey = key_of(v0 + 0.0);
+    const bool neg = v0 < 0.0;
+    u128 a128 = 0, z128 = 0;
+    int cnt = 0;
+    for (int t = 0; t < T; ++t) {
+      const int i = lane + 64 * t;
+      const uint64_t key = seg_key(s, i);
+      const bool valid = key != KEY_NONE;
+      const u128 w = seg_weight(s, i, valid);
+      a128 += (valid && key < KEY_ZERO) ? w : (u128)0;
+      z128 += (valid && key == KEY_ZERO) ? w : (u128)0;
+      if (r0 >= 0 && valid) {
+        const bool in = neg ? (key < KEY_ZERO && pair_ge(key, i, mkey, r0))
+                            : (key > KEY_ZERO && pair_le(key, i, mkey, r0));
+        cnt += in ? 1 : 0;
+      }
+    }
+    const u128 A = wave_sum_u128(a128), B = A + wave_sum_u128(z128), W = cj.wfix;
+    cnt = wave_sum_int(cnt);
+    u128 lm = 0;
+    if ((A << 1) > W) lm = (A << 1) - W;
+    else if (W > (B << 1)) lm = W - (B << 1);
+    if (lane == 0) {
+      counts[g] = (long long)((r0 >= 0 ? cnt : 0) + 1);
+      lmax[g] = fixed_to_double(lm, cj.e0);
+    }
+  }
+}
+
+// In-place inclusive scan of offsets[1 .. count] with offsets[0] = 0 (one
+// workgroup of 1024: contiguous chunks per thread, then a scan of the chunk
+// totals).
+__global__ void __launch_bounds__(1024) k_bp_scan(long long *__restrict__ offsets, long long count) {
+  __shared__ long long part[1024];
+  const int tid = threadIdx.x;
+  const long long chunk = (count + 1023) / 1024;
+  const long long b = 1 + tid * chunk, e = min(count + 1, b + chunk);
+  long long sum = 0;
+  for (long long q = b; q < e; ++q) sum += offsets[q];
+  part[tid] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const long long add = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  long long run = part[tid] - sum;
+  for (long long q = b; q < e; ++q) {
+    run += offsets[q];
+    offsets[q] = run;
+  }
+  if (tid == 0) offsets[0] = 0;
+}
+
+// ------------------------------------------------------------------ entries
+constexpr int BP_CAP = 512;                     // window list entries per wave
+constexpr int BP_WAVES = 4;
+constexpr int BP_MAX_ROUNDS = 4096;             // windows and halvings per segment
+
+// writes one entry if `at` lies inside the segment's range [lo, hi); returns
+// false (nothing written) otherwise
+__device__ __forceinline__ bool bp_write(double *lam, double *v, int *row, long long at, long long lo,
+                                         long long hi, double l, double vv, int r) {
+  if (at < lo || at >= hi) return false;
+  lam[at] = l;
+  v[at] = vv;
+  row[at] = r;
+  return true;
+}
+
+__global__ void __launch_bounds__(256)
+k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInfo *__restrict__ ci,
+          const double *__restrict__ V0, const int *__restrict__ R0, const long long *__restrict__ offsets,
+          const double *__restrict__ lmax, long long capacity, double *__restrict__ lam, double *__restrict__ v,
+          int *__restrict__ row, int *__restrict__ status, int *__restrict__ sticky) {
+  __shared__ uint64_t skeys[BP_WAVES][BP_CAP];
+  __shared__ unsigned short srows[BP_WAVES][BP_CAP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t *lk = skeys[wave];
+  unsigned short *lr = srows[wave];
+  const long long nseg = (long long)m * m;
+  if (offsets[nseg] > capacity) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+      if (status) atomicCAS(status, 0, L1LINE_ESIZE);
+      if (sticky) atomicCAS(sticky, 0, L1LINE_ESIZE);
+    }
+    return;
+  }
+  const long long waves = (long long)gridDim.x * BP_WAVES;
+  const int T = (n + 63) >> 6;
+  int Tp = 1;
+  while (Tp < T) Tp <<= 1;
+  for (long long g = (long long)blockIdx.x * BP_WAVES + wave; g < nseg; g += waves) {
+    const long long base = offsets[g], cnt = offsets[g + 1] - base;
+    if (cnt == 0) continue;
+    const int j = (int)(g / m), k = (int)(g % m);
+    const ColInfo cj = ci[j];
+    const int r0 = R0[g];
+    if (r0 >= 0) {
+      const SegIO s{X + (long long)k * ld, X + (long long)j * ld, n, T, Tp, cj.e0, lane};
+      const u128 W = cj.wfix;
+      const bool neg = V0[g] < 0.0;
+      long long emitted = 0;
+      // the window is [lo, hi] in (key, row) order, sweeping away from the
+      // lambda = 0 minimiser towards 0
+      uint64_t lo_k = key_of(V0[g] + 0.0), hi_k = KEY_ZERO - 1;
+      int lo_r = r0, hi_r = 0xFFFF;
+      if (!neg) {
+        hi_k = lo_k;
+        hi_r = r0;
+        lo_k = KEY_ZERO + 1;
+        lo_r = 0;
+      }
+      const uint64_t end_k = neg ? KEY_ZERO - 1 : KEY_ZERO + 1;   // the window edge nearest 0
+      uint64_t w_lo = lo_k, w_hi = hi_k;          // current window keys (halved on overflow)
+      int rounds = 0;
+      bool bad = false;
+      while (emitted < cnt - 1) {
+        if (++rounds > BP_MAX_ROUNDS) {
+          bad = true;
+          break;
+        }
+        // one exact pass: weight of everything below the window, the
+        // window's elements to the list
+        const uint64_t wk_lo = neg ? lo_k : w_lo, wk_hi = neg ? w_hi : hi_k;
+        const int wr_lo = neg ? lo_r : (w_lo == lo_k ? lo_r : 0);
+        const int wr_hi = neg ? (w_hi == hi_k ? hi_r : 0xFFFF) : hi_r;
+        u128 below = 0;
+        int nwin = 0;
+        for (int t = 0; t < T; ++t) {
+          const int i = lane + 64 * t;
+          const uint64_t key = seg_key(s, i);
+          const bool valid = key != KEY_NONE;
+          const bool lt = valid && !pair_ge(key, i, wk_lo, wr_lo);
+          const bool in = valid && !lt && pair_le(key, i, wk_hi, wr_hi);
+          below += lt ? seg_weight(s, i, true) : (u128)0;
+          const uint64_t wm = __ballot(in);
+          const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
+          nwin += __builtin_popcountll(wm);
+          if (in && pos < BP_CAP) {
+            lk[pos] = key;
+            lr[pos] = (unsigned short)i;
+          }
+        }
+        const u128 Sb = wave_sum_u128(below);
+        nwin = uni_int(nwin);
+        wave_lds_sync();
+        if (nwin > BP_CAP) {
+          if (wk_lo == wk_hi) {
+            // one key with more tied rows than the list: rows are in sorted
+            // order already; stream them tile by tile
+            u128 run = Sb;
+            int done = 0;
+            for (int t = 0; t < T; ++t) {
+              const int i = lane + 64 * t;
+              const uint64_t key = seg_key(s, i);
+              const bool valid = key != KEY_NONE;
+              const bool in = valid && pair_ge(key, i, wk_lo, wr_lo) && pair_le(key, i, wk_hi, wr_hi);
+              const u128 w = seg_weight(s, i, in);
+              const u128 incl = wave_incl_scan_u128(w, lane);
+              const uint64_t wm = __ballot(in);
+              const int rank = done + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
+              if (in) {
+                const u128 Sprev = run + incl - w, Sp = run + incl;
+                u128 lb = 0;
+                long long at;
+                if (neg) {
+                  lb = (Sprev << 1) > W ? (Sprev << 1) - W : (u128)0;
+                  at = base + emitted + rank;
+                } else {
+                  lb = W > (Sp << 1) ? W - (Sp << 1) : (u128)0;
+                  at = base + emitted + (nwin - 1 - rank);
+                }
+                if (!bp_write(lam, v, row, at, base, base + cnt - 1, fixed_to_double(lb, cj.e0), ratio_of_key(key), i))
+                  bad = true;
+              }
+              run += shfl_u128(incl, 63);
+              done += __builtin_popcountll(wm);
+            }
+            emitted += nwin;
+          } else {
+            // halve the window in key space, keeping the edge nearest the
+            // lambda = 0 minimiser
+            if (neg) w_hi = wk_lo + (wk_hi - wk_lo) / 2;
+            else w_lo = wk_hi - (wk_hi - wk_lo) / 2;
+            continue;
+          }
+        } else {
+          const int N = wave_sort_lds(lk, lr, nwin, lane);
+          const int E = N >> 6;
+          u128 tot, incl;
+          wave_list_sums(s, lk, lr, E, tot, incl);
+          u128 run = Sb + incl - tot;                 // weight before this lane's entries
+          for (int q = 0; q < E; ++q) {
+            const int e = E * lane + q;
+            const uint64_t key = lk[e];
+            if (key == KEY_NONE) break;
+            const int rr = (int)lr[e];
+            const u128 w = seg_weight(s, rr, true);
+            const u128 Sprev = run, Sp = run + w;
+            run = Sp;
+            u128 lb = 0;
+            long long at;
+            if (neg) {
+              lb = (Sprev << 1) > W ? (Sprev << 1) - W : (u128)0;
+              at = base + emitted + e;
+            } else {
+              lb = W > (Sp << 1) ? W - (Sp << 1) : (u128)0;
+              at = base + emitted + (nwin - 1 - e);
+            }
+            if (!bp_write(lam, v, row, at, base, base + cnt - 1, fixed_to_double(lb, cj.e0), ratio_of_key(key), rr))
+              bad = true;
+          }
+          wave_lds_sync();
+          emitted += nwin;
+        }
+        // next window: the keys between this one and 0
+        if (neg) {
+          if (wk_hi >= end_k) break;
+          lo_k = wk_hi + 1;
+          lo_r = 0;
+          w_hi = end_k;
+        } else {
+          if (wk_lo <= end_k) break;
+          hi_k = wk_lo - 1;
+          hi_r = 0xFFFF;
+          w_lo = end_k;
+        }
+      }
+      bad = __ballot(bad) != 0;
+      if (bad || emitted != cnt - 1) {
+        if (lane == 0) {
+          if (status) atomicCAS(status, 0, L1LINE_EINTERNAL);
+          if (sticky) atomicCAS(sticky, 0, L1LINE_EINTERNAL);
+        }
+      }
+    }
+    if (lane == 0) bp_write(lam, v, row, base + cnt - 1, base, base + cnt, lmax[g], 0.0, -1);
+  }
+}

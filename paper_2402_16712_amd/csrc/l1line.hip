@@ -19,6 +19,7 @@
 
 #include "fit_kernels.h"
 #include "ranker_kernels.h"
+#include "bp_kernels.h"
 
 // ------------------------------------------------------------------- context
 struct ProfRec {
@@ -241,8 +242,18 @@ static const RunOpts kNoOpts = {nullptr, 0, nullptr, nullptr, 0};
 
 // Build the layout, stage the metadata, launch (or replay) the sequence.
 // `only_seg_ms` (autotuner): time the segment kernel alone.
+// Workspace arrays of the last run, for follow-up kernels on the same stream
+// (valid until the context's next run): per-(j, k) v and median row of
+// lambda index 0 of problem 0, and the column info.
+struct BatchPtrs {
+  double *V;
+  int *R;
+  ColInfo *ci;
+};
+
 static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, hipStream_t s,
-                     const TuneParams &tp, float *only_seg_ms, const RunOpts &ro = kNoOpts) {
+                     const TuneParams &tp, float *only_seg_ms, const RunOpts &ro = kNoOpts,
+                     BatchPtrs *outp = nullptr) {
   BatchLayout Ly;
   memset(&Ly, 0, sizeof Ly);
   Ly.B = (int)B;
@@ -389,6 +400,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   double *dV = (double *)(d + Ly.o_V), *dE = (double *)(d + Ly.o_E), *dZ = (double *)(d + Ly.o_Z);
   int *dR = (int *)(d + Ly.o_R), *dzflag = (int *)(d + Ly.o_zflag);
   double2 *dDZ = (double2 *)(d + Ly.o_DZ);
+  if (outp) *outp = BatchPtrs{dV, dR, dci};
 
   uint64_t key = fnv1a(h, Ly.meta_bytes, 1469598103934665603ull);
   key = fnv1a(&tp, sizeof tp, key);
@@ -649,7 +661,7 @@ const char *l1line_strerror(int code) {
     case L1LINE_ERANGE: return "a selected ratio overflowed";
     case L1LINE_ENOMEM: return "workspace allocation failed";
     case L1LINE_EWIDE: return "column magnitudes too spread for exact 128-bit weight sums";
-    case L1LINE_ESIZE: return "a size exceeds the library limit (L1LINE_MAX_N rows, L1LINE_RANKER_MAX_M ranked columns)";
+    case L1LINE_ESIZE: return "a size exceeds a library limit (L1LINE_MAX_N rows, L1LINE_RANKER_MAX_M ranked columns, L1LINE_BP_MAX_M columns for breakpoints, or the breakpoint capacity)";
     case L1LINE_EINTERNAL: return "selection round bound exceeded";
     case L1LINE_EIO: return "file missing, unreadable or malformed";
     case L1LINE_ENOMODEL: return "the context holds no ranker weights";
@@ -1198,6 +1210,53 @@ int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps, ui
   if (hipDeviceSynchronize() != hipSuccess && st == L1LINE_OK) st = L1LINE_EHIP;
   (void)hipFree(buf);
   return note(ctx, st);
+}
+
+// ------------------------------------------------------------ Algorithm 2
+static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, int64_t *offsets,
+                            double *lambda_max, double *lam, double *v, int32_t *row, int64_t capacity,
+                            int32_t *status, void *stream) {
+  if (!ctx || !offsets || capacity < 0 || (capacity > 0 && (!lam || !v || !row))) return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  if (m > L1LINE_BP_MAX_M) return L1LINE_ESIZE;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  // scratch: the lambda = 0 fit's outputs and lambda_max when not requested
+  const size_t o_v = 0, o_j = align_up(sizeof(double) * m, 256), o_obj = o_j + 256, o_lm = o_obj + 256,
+               total = o_lm + (lambda_max ? 0 : align_up(sizeof(double) * m * m, 256));
+  st = ensure_rk(ctx, total, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  double *lm = lambda_max ? lambda_max : (double *)(b + o_lm);
+  const double zero = 0.0;
+  const l1line_problem p = single(X, n, m, ld, &zero, 1, (double *)(b + o_v), (int64_t *)(b + o_j),
+                                  (double *)(b + o_obj), nullptr, nullptr, status);
+  BatchPtrs bp;
+  st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
+  if (st) return st;
+  const long long nseg = (long long)m * m;
+  const unsigned grid = (unsigned)std::max(1ll, std::min((nseg + 3) / 4, (long long)ctx->num_cu * 8));
+  {
+    ProfScope ps(ctx, s, "bp_count");
+    hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                       (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (long long *)offsets + 1, lm);
+    hipLaunchKernelGGL(k_bp_scan, dim3(1), dim3(1024), 0, s, (long long *)offsets, nseg);
+  }
+  if (capacity > 0) {
+    ProfScope ps(ctx, s, "bp_emit");
+    hipLaunchKernelGGL(k_bp_emit, dim3(grid), dim3(64 * BP_WAVES), 0, s, X, (int)n, (int)m, (long long)ld,
+                       (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (const long long *)offsets,
+                       (const double *)lm, (long long)capacity, lam, v, (int *)row, (int *)status, ctx->sticky);
+  }
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_breakpoints(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, int64_t *offsets,
+                       double *lambda_max, double *lam, double *v, int32_t *row, int64_t capacity, int32_t *status,
+                       void *stream) {
+  return note(ctx, breakpoints_impl(ctx, X, n, m, ld, offsets, lambda_max, lam, v, row, capacity, status, stream));
 }
 
 }  // extern "C"
