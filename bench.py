@@ -7,7 +7,8 @@ weighted median with its residual, the per-j objectives, the argmin) on a
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs path,batch,ranked]
 
 Besides the main line it reports, as extra fields, the 64-penalty path on
-the same matrix, the 512-matrix uneven batch and the learned top-K fit.
+the same matrix, the 512-matrix uneven batch, the learned top-K fit and
+Algorithm 2 (every segment's breakpoints) on the same matrix.
 """
 from __future__ import annotations
 
@@ -43,7 +44,7 @@ def _args():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (scale for HBM byte counters)")
-    ap.add_argument("--legs", default="path,batch,ranked",
+    ap.add_argument("--legs", default="path,batch,ranked,breakpoints",
                     help="extra workloads reported beside the main line (comma list; '' for none)")
     ap.add_argument("--ranked-instances", type=int, default=3)
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -208,6 +209,31 @@ def leg_batch(ctx, steps, stream):
             "medians_per_s": medians * 1000.0 / ms, "nonzero_status": bad}
 
 
+def leg_breakpoints(ctx, seed, steps, stream):
+    """Algorithm 2 on the main workload's 2000 x 2000 matrix: every
+    segment's breakpoints and lambda_max (count pass, offsets, entries)."""
+    import torch
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import workloads as wl
+    p = wl.large_fit(seed)
+    X = B.device_matrix(p.X)
+    n, m = p.X.shape
+    out = ctx.breakpoints(X)                      # sizes the outputs
+    total = int(out["offsets"][-1].item())
+    lib, ptr = B.lib(), B._ptr
+
+    def call():
+        return lib.l1line_breakpoints(ctx._h, ptr(X), n, m, n, ptr(out["offsets"]), ptr(out["lambda_max"]),
+                                      ptr(out["lam"]), ptr(out["v"]), ptr(out["row"]), total, ptr(out["status"]),
+                                      ctx._stream())
+    call()
+    _, ms = _timed(call, steps, stream)
+    torch.cuda.synchronize()
+    return {"workload": f"Algorithm 2, all {m * (m - 1)} segments of the {n}x{m} matrix",
+            "ms_per_call": ms, "entries": total, "entries_per_s": total * 1000.0 / ms,
+            "segments_per_s": m * (m - 1) * 1000.0 / ms, "status": int(out["status"].item())}
+
+
 def leg_ranked(ctx, count):
     """Learned top-K (K = 32) vs exhaustive on 10000 x 4000 matrices."""
     import os
@@ -321,6 +347,8 @@ def main():
         line["batch"] = leg_batch(ctx, 3, stream)
     if "ranked" in legs:
         line["ranked"] = leg_ranked(ctx, a.ranked_instances)
+    if "breakpoints" in legs:
+        line["breakpoints"] = leg_breakpoints(ctx, a.seed, 3, stream)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, lam, z_gpu, a.cpu_columns)
     ctx.close()

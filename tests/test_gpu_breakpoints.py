@@ -117,3 +117,31 @@ def test_capacity_too_small_reports_esize(ctx):
     torch.cuda.synchronize()
     assert rc == 0 and int(offs[-1].item()) > 1 and int(st.item()) == B.ESIZE
     ctx.last_error()
+
+
+def test_full_size_sampled(ctx):
+    """2000 x 2000 (the benchmark's matrix): sampled segments against the
+    oracle, every segment's count consistent with its entries."""
+    import torch
+    from paper_2402_16712_amd import binding as B
+    p = wl.large_fit(0)
+    _say("case bp 2000x2000")
+    out = ctx.breakpoints(B.device_matrix(p.X))
+    torch.cuda.synchronize()
+    g = {k: t.cpu().numpy() for k, t in out.items()}
+    assert int(g["status"][0]) == 0
+    off, m = g["offsets"], p.X.shape[1]
+    cnt = np.diff(off)
+    assert np.all(cnt[np.arange(m) * m + np.arange(m)] == 0)
+    term = off[1:][cnt > 0] - 1                  # every segment ends in (lambda_max, 0, -1)
+    assert np.all(g["row"][term] == -1) and np.all(g["v"][term] == 0.0)
+    assert np.array_equal(g["lam"][term], g["lambda_max"][cnt > 0])
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        j, k = (int(x) for x in rng.choice(m, 2, replace=False))
+        gs = j * m + k
+        lam, v, row, lm = O.breakpoints_segment(p.X, j, k)
+        a, b = off[gs], off[gs + 1]
+        assert g["lam"][a:b].tobytes() == lam.tobytes(), (j, k)
+        assert g["v"][a:b].tobytes() == v.tobytes() and np.array_equal(g["row"][a:b], row), (j, k)
+        assert g["lambda_max"][gs] == lm
