@@ -102,7 +102,8 @@ def _pmc_per_dispatch(path, counter):
         for r in csv.DictReader(f):
             if r["Counter_Name"] != counter:
                 continue
-            k = r["Kernel_Name"].split("(")[0]
+            # kernel name without "void ", template arguments and parameters
+            k = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").strip()
             tot[k] += float(r["Counter_Value"])
             disp[k].add(r["Dispatch_Id"])
     return {k: tot[k] / len(disp[k]) for k in tot}

@@ -645,6 +645,7 @@ k_signsum_one(const double *__restrict__ X, int n, int m, long long ld, double2 
 //  Whatever the window does not settle goes to the general rounds.
 constexpr int SEG_WAVES = 4;
 constexpr int SAMPLE_ROWS = 128;
+constexpr int SXJ_LDS_MAX = 4096;   // longest column j copied to LDS (32 KB)
 
 __host__ __device__ constexpr size_t seg_sxj_bytes(int n) {
   return ((size_t)((n + 63) / 64) * 64 * 8 + 15) / 16 * 16;
@@ -686,16 +687,22 @@ __device__ __forceinline__ ExactSides exact_sides(const SegIO &s) {
 }
 
 // One work item, by the whole workgroup (every thread calls it).  ci, V, E,
-// R and segflags are this problem's slices.
+// R and segflags are this problem's slices.  kLdsJ: column j is copied to LDS
+// (the pointer's address space is then known to the compiler: LDS loads).
+template <bool kLdsJ>
 __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, int m, long long ld,
                                          const ColInfo *__restrict__ ci, const double *__restrict__ lam, int L,
                                          const double2 *__restrict__ DZ, int j, int kbeg, int kend,
                                          double *__restrict__ V,
                                          double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
-                                         int lcap, unsigned char *smem) {
+                                         int lcap, int sxj_rows, unsigned char *smem) {
   const int T = (n + 63) >> 6;
-  double *sxj = (double *)smem;                     // T*64 entries, zero padded
-  int *srow = (int *)(smem + seg_sxj_bytes(n));
+  // column j in LDS when the launch reserved room for it (n <= sxj_rows),
+  // else read from global memory (it stays in L2 across the item's k)
+  constexpr bool lds_j = kLdsJ;
+  (void)sxj_rows;
+  double *sxj_lds = (double *)smem;                 // T*64 entries, zero padded
+  int *srow = (int *)(smem + (lds_j ? seg_sxj_bytes(n) : 0));
   u128 *slam = (u128 *)(srow + SAMPLE_ROWS);
   WaveScratch *wsc = (WaveScratch *)(slam + L);
   uint64_t *lkeys = (uint64_t *)(wsc + SEG_WAVES);
@@ -704,7 +711,9 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 
   const ColInfo cj = ci[j];
   const double *xjg = X + (long long)j * ld;
-  for (int i = threadIdx.x; i < T * 64; i += blockDim.x) sxj[i] = i < n ? xjg[i] : 0.0;
+  if constexpr (kLdsJ)
+    for (int i = threadIdx.x; i < T * 64; i += blockDim.x) sxj_lds[i] = i < n ? xjg[i] : 0.0;
+  const double *__restrict__ sxj = kLdsJ ? (const double *)sxj_lds : xjg;
   for (int t = threadIdx.x; t < L; t += blockDim.x) slam[t] = lambda_fixed(lam[t], cj.e0);
   if (threadIdx.x == 0) *knext = kbeg;
   __syncthreads();
@@ -990,18 +999,21 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 // the columns k that the workgroups of one XCD stream stay in its L2.
 // Workgroups are dispatched to the XCDs round-robin (blockIdx mod 8); one
 // whose XCD has no item left takes items of the next XCDs (the routing only
-// affects where data is cached, never the results).  nitems = items per XCD
+// affects where data is cached, never the results).  kLdsJ: every problem's
+// column j fits the launch's LDS copy (n <= sxj_rows), else all are read from
+// global memory.  nitems = items per XCD
 // (implicit) or in total (explicit).  gate (optional): the kernel does
 // nothing unless *gate == gate_on.
 constexpr int SEG_XCDS = 8;
 
+template <bool kLdsJ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int chunks,
             int *__restrict__ counter, const int *__restrict__ xstart, const double *__restrict__ lam_all,
             const ColInfo *__restrict__ ci,
             const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
             int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand, int ncand,
-            const int *__restrict__ gate, int gate_on, int lcap) {
+            const int *__restrict__ gate, int gate_on, int lcap, int sxj_rows) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_item, s_tried;                  // s_tried: XCD partitions found empty
   if (gate && *gate != gate_on) return;
@@ -1042,8 +1054,9 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
       if (it.kbeg >= it.kend) continue;            // an empty part of a narrow matrix
     }
     const ProbDesc d = P[it.b];
-    seg_item(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j, it.kbeg,
-             it.kend, V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap, smem);
+    seg_item<kLdsJ>(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j,
+                    it.kbeg, it.kend, V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap,
+                    sxj_rows, smem);
   }
 }
 

@@ -294,6 +294,14 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     int chunks = (int)ceil(part_bytes / (2.0 * 1024 * 1024));
     const int kmin = std::max(kImplicitKmin, tp.kchunk_min);
     chunks = std::max(1, std::min(chunks, std::max(1, m / (SEG_XCDS * kmin))));
+    // few preserved columns (a candidate list): cut finer so that every
+    // persistent workgroup gets items, down to 16 columns k per item
+    const int mj = ro.cand ? ro.ncand : m;
+    const long long want = 2ll * tp.blocks_per_cu * ctx->num_cu;
+    if ((long long)mj * chunks * SEG_XCDS < want) {
+      const int need = (int)((want + (long long)mj * SEG_XCDS - 1) / ((long long)mj * SEG_XCDS));
+      chunks = std::max(chunks, std::min(need, std::max(1, m / (SEG_XCDS * 16))));
+    }
     Ly.ksplit = chunks;
     Ly.nitems = (ro.cand ? ro.ncand : m) * chunks;     // per XCD
     (void)target;
@@ -419,10 +427,15 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
 
   // window list capacity: the larger path list where the LDS allows it
   const size_t lds_max = seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS, WIN_CAP);
-  const int lcap = (Ly.Lmax > 1 && seg_lds_bytes(Ly.nmax, Ly.Lmax, PATH_CAP) <= lds_max) ? PATH_CAP : WIN_CAP;
-  const size_t lds = seg_lds_bytes(Ly.nmax, Ly.Lmax, lcap);
+  // column j goes to LDS up to SXJ_LDS_MAX rows; longer ones are read from
+  // global memory, which keeps room for more workgroups per CU
+  const int sxj_rows = Ly.nmax <= SXJ_LDS_MAX ? Ly.nmax : 0;
+  const int lcap = (Ly.Lmax > 1 && seg_lds_bytes(sxj_rows, Ly.Lmax, PATH_CAP) <= lds_max) ? PATH_CAP : WIN_CAP;
+  const size_t lds = seg_lds_bytes(sxj_rows, Ly.Lmax, lcap);
   if (!lds_attr_set) {
-    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_max));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_max));
     lds_attr_set = true;
   }
@@ -456,10 +469,10 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   }
   {
     ProfScope ps(ctx, ls, "fit_seg");
-    hipLaunchKernelGGL(k_seg_batch, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
+    hipLaunchKernelGGL(sxj_rows > 0 ? k_seg_batch<true> : k_seg_batch<false>, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
                        Ly.nitems, Ly.ksplit, dcounter, dxstart, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand,
                        ro.ncand,
-                       ro.gate, ro.gate_on, lcap);
+                       ro.gate, ro.gate_on, lcap, sxj_rows);
   }
   if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
   {
