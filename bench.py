@@ -325,6 +325,15 @@ def main():
             "ops_per_element": OPS_PER_ELEMENT, "elements_per_launch": elements,
             "avg_launch_ms": seg_ms}
 
+    # the sign-sum contraction on the FP64 matrix units: 2 products of
+    # m x n x m, 2 flops per multiply-add (the zero-indicator product is
+    # skipped where a block has no zero, so this counts it in full)
+    ss_flops = 2.0 * 2.0 * m * m * n
+    roof_ss = {"bound": "mfma", "kernel": "k_signsum_batch", "achieved": ss_flops / (kern["signsum"] / 1000.0) / 1e12,
+               "peak": 78.6, "unit": "TFLOP/s (FP64 matrix)",
+               "frac": ss_flops / (kern["signsum"] / 1000.0) / 78.6e12, "flops_per_launch": ss_flops,
+               "avg_launch_ms": kern["signsum"]}
+
     line = {
         "metric": "fits/s & weighted-medians/s, 2000x2000 FP64; learned top-K vs exhaustive",
         "value": fits_per_s,
@@ -339,6 +348,7 @@ def main():
                                f"all {m} candidate j", "n": n, "m": m, "L": 1, "seed": a.seed},
         "kernels_ms": kern,
         "roofline": roof,
+        "roofline_signsum": roof_ss,
         "j_star": j_star,
     }
     legs = [x for x in a.legs.split(",") if x]

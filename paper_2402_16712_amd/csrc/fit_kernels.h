@@ -585,7 +585,8 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
         const double sg = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
         const double zr = x == 0.0 ? 1.0 : 0.0;
         accD[t] = mfma_f64(a, sg, accD[t]);
-        accZ[t] = mfma_f64(aa, zr, accZ[t]);
+        // exact zeros are rare: skip the product when this 4 x 16 block has none
+        if (__ballot(x == 0.0)) accZ[t] = mfma_f64(aa, zr, accZ[t]);
       }
     }
     __syncthreads();
