@@ -91,6 +91,20 @@ def test_batch_graph_capture_and_replay(ctx):
         _eq(g, p, f"graph after switch problem {q}")
 
 
+def test_batch_with_long_columns(ctx):
+    # one problem longer than the LDS copy of column j: the whole launch
+    # reads columns j from global memory
+    from paper_2402_16712_amd import binding as B
+    probs = [(wl.random_small(900 + q, n, m, zero_frac=0.02), None) for q, (n, m) in
+             enumerate([(5000, 4), (300, 9), (37, 5), (1200, 6)])]
+    probs = [(X, np.array([0.0, 0.02, 0.3]) * float(np.abs(X).sum(0).max())) for X, _ in probs]
+    dev = [(B.device_matrix(X), lam) for X, lam in probs]
+    _say("case batch long columns")
+    outs = _np(ctx.fit_batch(dev))
+    for q, ((X, lam), g) in enumerate(zip(probs, outs)):
+        _eq(g, O.fit_path(X, lam), f"long-column problem {q} {X.shape}")
+
+
 def test_batch_equals_path_per_problem(ctx):
     from paper_2402_16712_amd import binding as B
     probs = wl.uneven_batch(12345, B=6, L=16, n_range=(50, 900), m_range=(10, 60))
