@@ -466,6 +466,74 @@ int oracle_fit_path(const double *X, int64_t n, int64_t m, int64_t ld,
     return status;
 }
 
+/* ------------------------------------------------------- components */
+/* Successive components (Sec. 2, after Algorithm 3: a component is found by
+ * Algorithm 1 on the data projected onto the null space of the components
+ * derived so far).  With X_0 = X and the same lambda for every component:
+ *   v_c    = Algorithm 1 on X_c (j_c, z_c its preserved column and objective)
+ *   w_c    = v_c made orthogonal to w_0 .. w_{c-1} (classical Gram-Schmidt,
+ *            unnormalised): w = v_c; for l < c:
+ *            w_k = fl(w_k - fl(fl(R64_k(w_lk * v_ck) / R64_k(w_lk^2)) * w_lk))
+ *   X_c+1  = X_c projected off w_c:  s_i = R64_k fl(x_ik * w_ck),
+ *            u_k = fl(w_ck / R64_k(w_ck^2)),  x_ik = fl(x_ik - fl(s_i * u_k))
+ * (every product rounded on its own, no fused multiply-add; R64 as above).
+ *   V [p*m], J [p], OBJ [p]; Xout (n x m, ld = n, nullable): X_p-1, the data
+ *   the last component was fitted on. */
+static double r64_dot(const double *a, const double *b, int64_t m, double *terms)
+{
+    for (int64_t k = 0; k < m; ++k) terms[k] = a[k] * b[k];
+    return r64_sum(terms, m);
+}
+
+int oracle_components(const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                      int64_t p, double *V, int64_t *J, double *OBJ, double *Xout)
+{
+    int st = check_x(X, n, m, ld);
+    if (st) return st;
+    st = check_lambdas(&lambda, 1);
+    if (st) return st;
+    if (p < 1 || p > m || !V || !J || !OBJ) return OR_EINVAL;
+    double *Xc = (double *)malloc((size_t)(n * m) * sizeof(double));
+    double *Wb = (double *)malloc((size_t)(p * m) * sizeof(double));
+    double *cw = (double *)malloc((size_t)p * sizeof(double));
+    double *terms = (double *)malloc((size_t)(m > n ? m : n) * sizeof(double));
+    double *row = (double *)malloc((size_t)m * sizeof(double));
+    if (!Xc || !Wb || !cw || !terms || !row) {
+        free(Xc); free(Wb); free(cw); free(terms); free(row);
+        return OR_ENOMEM;
+    }
+    for (int64_t k = 0; k < m; ++k)
+        for (int64_t i = 0; i < n; ++i) Xc[i + k * n] = XAT(X, ld, i, k);
+    int status = OR_OK;
+    for (int64_t c = 0; c < p; ++c) {
+        st = oracle_fit_path(Xc, n, m, n, &lambda, 1, 0, 0, V + c * m, J + c, OBJ + c, NULL, NULL);
+        if (st && st != OR_ERANGE) { status = st; break; }
+        if (st) status = st;
+        if (c == p - 1) break;
+        const double *v = V + c * m;
+        double *w = Wb + c * m;
+        for (int64_t k = 0; k < m; ++k) w[k] = v[k];
+        for (int64_t l = 0; l < c; ++l) {
+            const double coef = r64_dot(Wb + l * m, v, m, terms) / cw[l];
+            for (int64_t k = 0; k < m; ++k) w[k] = w[k] - coef * Wb[l * m + k];
+        }
+        cw[c] = r64_dot(w, w, m, terms);
+        if (!(cw[c] > 0.0)) { status = OR_EINVAL; break; }
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t k = 0; k < m; ++k) row[k] = Xc[i + k * n];
+            const double si = r64_dot(row, w, m, terms);
+            for (int64_t k = 0; k < m; ++k) {
+                const double uk = w[k] / cw[c];
+                const double prod = si * uk;
+                Xc[i + k * n] = Xc[i + k * n] - prod;
+            }
+        }
+    }
+    if (Xout) memcpy(Xout, Xc, (size_t)(n * m) * sizeof(double));
+    free(Xc); free(Wb); free(cw); free(terms); free(row);
+    return status;
+}
+
 /* Threads OpenMP will use for oracle_fit_path (1 without OpenMP). */
 /* ------------------------------------------------------------ Algorithm 2 */
 /* r = a - b for a >= b */

@@ -57,6 +57,7 @@ def _load():
         lib.oracle_fit_j.argtypes = [P, I64, I64, I64, I64, P, I64, I, P, P, P, P, P, P]
         lib.oracle_fit_path.argtypes = [P, I64, I64, I64, P, I64, I, I, P, P, P, P, P]
         lib.oracle_breakpoints.argtypes = [P, I64, I64, I64, I64, I64, I64, P, P, P, P, P]
+        lib.oracle_components.argtypes = [P, I64, I64, I64, ctypes.c_double, I64, P, P, P, P]
         for f in (lib.oracle_column_stats, lib.oracle_segment, lib.oracle_fit_j,
                   lib.oracle_fit_path):
             f.restype = ctypes.c_int
@@ -187,3 +188,14 @@ def breakpoints(X):
     cat = (lambda a, dt: np.concatenate(a) if a else np.empty(0, dtype=dt))
     return dict(offsets=np.array(offs, dtype=np.int64), lambda_max=lmax, lam=cat(lams, np.float64),
                 v=cat(vs, np.float64), row=cat(rows, np.int32))
+
+
+def components(X, lam, p):
+    """p successive components: dict V (p x m), J (p), OBJ (p), Xlast (the
+    projected data the last component was fitted on, n x m)."""
+    X, n, m = _prep(X)
+    V, J, OBJ = np.empty((p, m)), np.empty(p, dtype=np.int64), np.empty(p)
+    Xl = np.empty((n, m), order="F")
+    code = _load().oracle_components(_ptr(X), n, m, n, float(lam), int(p), _ptr(V), _ptr(J), _ptr(OBJ), _ptr(Xl))
+    st = _check(code, "components", allow_erange=True)
+    return dict(V=V, J=J, OBJ=OBJ, Xlast=Xl, status=st)
