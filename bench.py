@@ -7,8 +7,9 @@ weighted median with its residual, the per-j objectives, the argmin) on a
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs path,batch,ranked]
 
 Besides the main line it reports, as extra fields, the 64-penalty path on
-the same matrix, the 512-matrix uneven batch, the learned top-K fit and
-Algorithm 2 (every segment's breakpoints) on the same matrix.
+the same matrix, the 512-matrix uneven batch, the learned top-K fit,
+Algorithm 2 (every segment's breakpoints) and three successive components
+of the same matrix.
 """
 from __future__ import annotations
 
@@ -44,7 +45,7 @@ def _args():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (scale for HBM byte counters)")
-    ap.add_argument("--legs", default="path,batch,ranked,breakpoints",
+    ap.add_argument("--legs", default="path,batch,ranked,breakpoints,components",
                     help="extra workloads reported beside the main line (comma list; '' for none)")
     ap.add_argument("--ranked-instances", type=int, default=3)
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -235,6 +236,21 @@ def leg_breakpoints(ctx, seed, steps, stream):
             "segments_per_s": m * (m - 1) * 1000.0 / ms, "status": int(out["status"].item())}
 
 
+def leg_components(ctx, seed, steps, stream):
+    """Three successive components of the main workload's matrix (fit,
+    projection, fit, projection, fit)."""
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import workloads as wl
+    p = wl.large_fit(seed)
+    X = B.device_matrix(p.X)
+    lam = float(p.lambdas[0])
+    ctx.components(X, lam, 3)
+    out, ms = _timed(lambda: ctx.components(X, lam, 3), steps, stream)
+    n, m = p.X.shape
+    return {"workload": f"3 successive components of the {n}x{m} matrix, lambda = 0.05 x max column mass",
+            "ms_per_call": ms, "components_per_s": 3000.0 / ms, "status": int(out["status"].item())}
+
+
 def leg_ranked(ctx, count):
     """Learned top-K (K = 32) vs exhaustive on 10000 x 4000 matrices."""
     import os
@@ -360,6 +376,8 @@ def main():
         line["ranked"] = leg_ranked(ctx, a.ranked_instances)
     if "breakpoints" in legs:
         line["breakpoints"] = leg_breakpoints(ctx, a.seed, 3, stream)
+    if "components" in legs:
+        line["components"] = leg_components(ctx, a.seed, 3, stream)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, lam, z_gpu, a.cpu_columns)
     ctx.close()

@@ -313,6 +313,31 @@ int l1line_breakpoints(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                        double *lam, double *v, int32_t *row, int64_t capacity,
                        int32_t *status, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Successive components (Sec. 2, after Algorithm 3: further components come
+ * from Algorithm 1 applied to the data projected onto the null space of the
+ * components found so far).  With X_0 = X and the same lambda throughout:
+ *   component c = Algorithm 1 on X_c  ->  V[c*m ..], J[c], OBJ[c]
+ *   w_c = v_c made orthogonal to w_0 .. w_{c-1} (classical Gram-Schmidt,
+ *         unnormalised: w_k = fl(w_k - fl(fl(R64(w_l . v_c) / |w_l|^2) w_lk)))
+ *   X_c+1: x_ik = fl(x_ik - fl(s_i u_k)), s_i = R64_k fl(x_ik w_ck),
+ *          u_k = fl(w_ck / |w_c|^2), |w|^2 = R64_k fl(w_k w_k)
+ * (products rounded on their own, R64 as above).
+ *   p      1 <= p <= min(m, L1LINE_MAX_COMPONENTS)
+ *   work   [n*m] DEVICE scratch owned by the caller (column-major, ld = n);
+ *          holds X_{p-1} on return
+ *   V [p*m], J [p], OBJ [p]  DEVICE outputs; OBJ[c] is z on X_c
+ *   status (nullable): the first fit status other than ERANGE in component
+ *          order (ERANGE is kept if nothing else occurs), or EINVAL when a
+ *          component lies in the span of the earlier ones (its projection
+ *          is 0; the later outputs are then unspecified).
+ * Host errors: as l1line_fit, EINVAL for a bad p or a null pointer. */
+#define L1LINE_MAX_COMPONENTS 1024
+int l1line_components(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                      int64_t ld, double lambda, int64_t p, double *work,
+                      double *V, int64_t *J, double *OBJ, int32_t *status,
+                      void *stream);
+
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.
  * l1line_profile_read waits for the recorded events, returns the summed

@@ -24,7 +24,7 @@ EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_er
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
            "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
            "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train",
-           "l1line_breakpoints"]
+           "l1line_breakpoints", "l1line_components"]
 BATCH_GRAPH = 1
 FEATURES = 32
 MLP_PARAMS = 20865
@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_ranker_get_params.argtypes = [P, P, P]
         L.l1line_ranker_train.argtypes = [P, ctypes.c_char_p, I64, ctypes.c_uint64]
         L.l1line_breakpoints.argtypes = [P, P, I64, I64, I64, P, P, P, P, P, I64, P, P]
+        L.l1line_components.argtypes = [P, P, I64, I64, I64, D, I64, P, P, P, P, P, P]
         L.l1line_destroy.argtypes = [P]
         L.l1line_strerror.argtypes = [I32]
         L.l1line_strerror.restype = ctypes.c_char_p
@@ -88,7 +89,8 @@ def lib() -> ctypes.CDLL:
                   "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
                   "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked",
                   "l1line_last_error", "l1line_ranker_load", "l1line_ranker_save", "l1line_ranker_set_params",
-                  "l1line_ranker_get_params", "l1line_ranker_train", "l1line_breakpoints"):
+                  "l1line_ranker_get_params", "l1line_ranker_train", "l1line_breakpoints",
+                  "l1line_components"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -358,6 +360,20 @@ class Context:
             _check(lib().l1line_breakpoints(self._h, _ptr(X), n, m, ld, _ptr(offsets), _ptr(lmax), _ptr(out["lam"]),
                                             _ptr(out["v"]), _ptr(out["row"]), total, _ptr(status),
                                             self._stream()), "l1line_breakpoints")
+        return out
+
+    def components(self, X, lam: float, p: int):
+        """p successive components: dict V [p, m], J [p], OBJ [p], work (the
+        projected data of the last component), status."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        out = dict(V=self._empty((p, m), torch.float64), J=self._empty((p,), torch.int64),
+                   OBJ=self._empty((p,), torch.float64),
+                   work=torch.empty_strided((n, m), (1, n), dtype=torch.float64, device=self._torch_device),
+                   status=self._empty((1,), torch.int32))
+        _check(lib().l1line_components(self._h, _ptr(X), n, m, ld, float(lam), int(p), _ptr(out["work"]),
+                                       _ptr(out["V"]), _ptr(out["J"]), _ptr(out["OBJ"]), _ptr(out["status"]),
+                                       self._stream()), "l1line_components")
         return out
 
     def ranker_load(self, path):

@@ -20,6 +20,7 @@
 #include "fit_kernels.h"
 #include "ranker_kernels.h"
 #include "bp_kernels.h"
+#include "comp_kernels.h"
 
 // ------------------------------------------------------------------- context
 struct ProfRec {
@@ -1270,6 +1271,53 @@ int l1line_breakpoints(l1line_ctx ctx, const double *X, int64_t n, int64_t m, in
                        double *lambda_max, double *lam, double *v, int32_t *row, int64_t capacity, int32_t *status,
                        void *stream) {
   return note(ctx, breakpoints_impl(ctx, X, n, m, ld, offsets, lambda_max, lam, v, row, capacity, status, stream));
+}
+
+// ------------------------------------------------------------ components
+static int components_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                           int64_t p, double *work, double *V, int64_t *J, double *OBJ, int32_t *status,
+                           void *stream) {
+  if (!ctx || !work || !V || !J || !OBJ || p < 1 || p > m || p > L1LINE_MAX_COMPONENTS) return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  st = check_lambdas(&lambda, 1);
+  if (st) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t o_W = 0, o_cw = align_up(sizeof(double) * p * m, 256), o_U = o_cw + align_up(sizeof(double) * p, 256),
+               o_s = o_U + align_up(sizeof(double) * m, 256), o_cst = o_s + align_up(sizeof(double) * n, 256),
+               o_flag = o_cst + align_up(sizeof(int) * p, 256), total = o_flag + align_up(sizeof(int) * p, 256);
+  st = ensure_rk(ctx, total, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  double *Wb = (double *)(b + o_W), *cw = (double *)(b + o_cw), *U = (double *)(b + o_U), *sv = (double *)(b + o_s);
+  int *cst = (int *)(b + o_cst), *flag = (int *)(b + o_flag);
+  const long long nm = (long long)n * m;
+  hipLaunchKernelGGL(k_copy_matrix, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, X, (long long)ld, (int)n,
+                     (int)m, work);
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((2 * p + 63) / 64)), dim3(64), 0, s, cst, 2ll * p, 0);
+  for (int64_t c = 0; c < p; ++c) {
+    const l1line_problem pr = single(work, n, m, n, &lambda, 1, V + c * m, J + c, OBJ + c, nullptr, nullptr,
+                                     cst + c);
+    st = run_batch(ctx, &pr, 1, 0, s, ctx->tune, nullptr);
+    if (st) return st;
+    if (c == p - 1) break;
+    hipLaunchKernelGGL(k_gs, dim3(1), dim3(64), 0, s, (const double *)(V + c * m), Wb, cw, (int)c, (int)m, U,
+                       flag + c);
+    hipLaunchKernelGGL(k_rowdot, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, (const double *)work, (int)n,
+                       (int)m, (const double *)(Wb + c * m), sv);
+    hipLaunchKernelGGL(k_deflate, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, work, (int)n, (int)m,
+                       (const double *)sv, (const double *)U);
+  }
+  hipLaunchKernelGGL(k_comp_status, dim3(1), dim3(64), 0, s, (const int *)cst, (const int *)flag, (int)p, status,
+                     ctx->sticky);
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_components(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, int64_t p,
+                      double *work, double *V, int64_t *J, double *OBJ, int32_t *status, void *stream) {
+  return note(ctx, components_impl(ctx, X, n, m, ld, lambda, p, work, V, J, OBJ, status, stream));
 }
 
 }  // extern "C"

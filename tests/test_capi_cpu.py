@@ -174,3 +174,18 @@ def test_shipped_ranker_weights_readable():
     from paper_2402_16712_amd import ranker
     w, _, _ = B.read_ranker_file(ranker.WEIGHTS)
     assert w.shape == (B.MLP_PARAMS,) and np.all(np.isfinite(w))
+
+
+def test_components_and_breakpoints_host_checks():
+    lib = B.lib()
+    f = _Fake()
+    P = ctypes.c_void_p
+    o = [P(1)] * 3
+    assert lib.l1line_components(f.h, P(1), 10, 4, 10, 0.5, 0, P(1), *o, None, None) == B.EINVAL     # p < 1
+    assert lib.l1line_components(f.h, P(1), 10, 4, 10, 0.5, 5, P(1), *o, None, None) == B.EINVAL     # p > m
+    assert lib.l1line_components(f.h, P(1), 10, 4, 10, 0.5, 2, None, *o, None, None) == B.EINVAL     # no work
+    assert lib.l1line_components(f.h, P(1), 10, 4, 10, -0.5, 2, P(1), *o, None, None) == B.EINVAL   # lambda
+    assert lib.l1line_breakpoints(f.h, P(1), 10, 4, 10, None, None, None, None, None, 0, None, None) == B.EINVAL
+    assert lib.l1line_breakpoints(f.h, P(1), 10, 4, 10, P(1), None, None, None, None, 5, None, None) == B.EINVAL
+    assert lib.l1line_breakpoints(f.h, P(1), 10, 9000, 10, P(1), None, None, None, None, 0, None,
+                                  None) == B.ESIZE
