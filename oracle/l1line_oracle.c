@@ -64,6 +64,10 @@
  *   the paper's loop over the sorted points with exact sums (see the
  *   function's comment for the one reading it takes).
  *
+ * ALGORITHM 3 lives in oracle.py (solution_path, exact rationals); from this
+ *   file it uses oracle_breakpoints and oracle_residual (the score of one
+ *   breakpoint entry, as Algorithm 1 computes it).
+ *
  * PINS (tests/test_oracle_*.py): the worked example of Sec. 3.1 (Table I,
  * Fig. 1 lines, the breakpoints and the maximum useful lambda), exact
  * rational brute force over every breakpoint on tiny inputs, an LP solver on
@@ -646,6 +650,20 @@ int oracle_breakpoints(const double *X, int64_t n, int64_t m, int64_t ld, int64_
     *lmax = big_to_double(&best);
     free(pts);
     free(prefix);
+    return OR_OK;
+}
+
+/* The residual e_jk = R64 over i of |x_ik - fl(v * x_ij)| at a given v, as
+ * Algorithm 1 scores it; Algorithm 3 scores every breakpoint entry with it. */
+int oracle_residual(const double *X, int64_t n, int64_t m, int64_t ld, int64_t j,
+                    int64_t k, double v, double *e)
+{
+    if (!X || n < 1 || m < 1 || ld < n || j < 0 || j >= m || k < 0 || k >= m || !e || !isfinite(v))
+        return OR_EINVAL;
+    double *terms = (double *)malloc((size_t)n * sizeof(double));
+    if (!terms) return OR_ENOMEM;
+    *e = residual(X, n, ld, j, k, v, terms);
+    free(terms);
     return OR_OK;
 }
 

@@ -58,6 +58,7 @@ def _load():
         lib.oracle_fit_path.argtypes = [P, I64, I64, I64, P, I64, I, I, P, P, P, P, P]
         lib.oracle_breakpoints.argtypes = [P, I64, I64, I64, I64, I64, I64, P, P, P, P, P]
         lib.oracle_components.argtypes = [P, I64, I64, I64, ctypes.c_double, I64, P, P, P, P]
+        lib.oracle_residual.argtypes = [P, I64, I64, I64, I64, I64, ctypes.c_double, P]
         for f in (lib.oracle_column_stats, lib.oracle_segment, lib.oracle_fit_j,
                   lib.oracle_fit_path):
             f.restype = ctypes.c_int
@@ -199,3 +200,114 @@ def components(X, lam, p):
     code = _load().oracle_components(_ptr(X), n, m, n, float(lam), int(p), _ptr(V), _ptr(J), _ptr(OBJ), _ptr(Xl))
     st = _check(code, "components", allow_erange=True)
     return dict(V=V, J=J, OBJ=OBJ, Xlast=Xl, status=st)
+
+
+def residual(X, j, k, v):
+    """e_jk at a given v, R64 over the rows of |x_ik - fl(v x_ij)| (the score
+    Algorithm 1 gives a selection)."""
+    X, n, m = _prep(X)
+    e = ctypes.c_double()
+    _check(_load().oracle_residual(_ptr(X), n, m, n, int(j), int(k), float(v), ctypes.byref(e)), "residual")
+    return e.value
+
+
+def solution_path(X):
+    """Algorithm 3 (Sec. 2): the exact solution path z*(lambda), v*(lambda)
+    over every lambda >= 0, merged from the per-coordinate paths that
+    Algorithm 2 gives.  Pure Python with exact rationals; small inputs only.
+
+    Reading taken.  For a preserved coordinate j the path of Algorithm 2 fixes,
+    on each interval of lambda, every v_k and so a line
+        z_j(lambda) = E_j + lambda P_j,
+        E_j = sum_k e_jk(v_k)  (e_jk as Algorithm 1 scores it, e_jj = 0),
+        P_j = 1 + sum_{k != j} |v_k|.
+    Entry t of segment (j, k) (Algorithm 2's list, lambda_t rounded once to a
+    double) holds for lambda >= lambda_t until the next entry; entries that
+    share a lambda apply in (k, t) order.  E_j and P_j are EXACT sums of the
+    doubles e_jk and |v_k| (rationals here).  Algorithm 3 compares the lines
+    of all j between consecutive breakpoints; its beta_L/beta_U are the
+    crossings of the best line with the others.  Here the same merge is a
+    sweep over lambda: between two consecutive breakpoints the best line at
+    the left end (smallest value, then smallest slope, then smallest j) is
+    followed through its crossings with lines of smaller slope; the preserved
+    coordinate changes at the first crossing, to the smallest slope (then j)
+    among the lines that meet there.
+
+    Returns the records of the path in lambda order, each a dict with
+      lam  where the change happens (a breakpoint, or a crossing rounded
+           once to the nearest double),
+      j    the preserved coordinate from there on,
+      k, v, row  the coordinate of v* that takes value v (row: the median
+           row, -1 when v is 0 or k = j),
+      E, P the line z* = E + lambda P from there on (each rounded once).
+    A change of the preserved coordinate (and the start at lambda = 0) lists
+    all m coordinates k = 0..m-1 at that lambda; otherwise one record per
+    breakpoint entry of the current j."""
+    from fractions import Fraction as Fr
+
+    X, n, m = _prep(X)
+    one = Fr(1)
+    # per j: events (lam, k, t, dE, dP, v, row) sorted by (lam, k, t)
+    events = []
+    for j in range(m):
+        ev = []
+        for k in range(m):
+            if k == j:
+                continue
+            lam, v, row, _ = breakpoints_segment(X, j, k)
+            pe, pp = Fr(0), Fr(0)
+            for t in range(len(lam)):
+                e = Fr(residual(X, j, k, v[t]))
+                a = Fr(abs(float(v[t])))
+                ev.append((float(lam[t]), k, t, e - pe, a - pp, float(v[t]), int(row[t])))
+                pe, pp = e, a
+        ev.sort(key=lambda x: (x[0], x[1], x[2]))
+        events.append(ev)
+    points = sorted({0.0} | {e[0] for ev in events for e in ev})
+    E = [Fr(0)] * m
+    P = [one] * m
+    vcur = [[(1.0 if k == j else 0.0, -1) for k in range(m)] for j in range(m)]
+    ptr = [0] * m
+    out = []
+
+    def batch(lam, j):
+        for k in range(m):
+            vv, rr = vcur[j][k]
+            out.append(dict(lam=lam, j=j, k=k, v=vv, row=rr, E=float(E[j]), P=float(P[j])))
+
+    cur = None
+    for idx, p in enumerate(points):
+        q = points[idx + 1] if idx + 1 < len(points) else None
+        fp = Fr(p)
+        applied = {}
+        for j in range(m):
+            ev = events[j]
+            while ptr[j] < len(ev) and ev[ptr[j]][0] == p:
+                lam, k, t, dE, dP, v, row = ev[ptr[j]]
+                E[j] += dE
+                P[j] += dP
+                vcur[j][k] = (v, row)
+                applied.setdefault(j, []).append((k, v, row, float(E[j]), float(P[j])))
+                ptr[j] += 1
+        new = min(range(m), key=lambda j: (E[j] + fp * P[j], P[j], j))
+        if cur is None or new != cur:
+            batch(p, new)
+        else:
+            for k, v, row, e, pp in applied.get(cur, []):
+                out.append(dict(lam=p, j=cur, k=k, v=v, row=row, E=e, P=pp))
+        cur = new
+        # crossings strictly inside (p, q)
+        while True:
+            best, tied = None, []
+            for s in range(m):
+                if P[s] < P[cur]:
+                    x = (E[s] - E[cur]) / (P[cur] - P[s])
+                    if best is None or x < best:
+                        best, tied = x, [s]
+                    elif x == best:
+                        tied.append(s)
+            if best is None or (q is not None and best >= Fr(q)):
+                break
+            cur = min(tied, key=lambda s: (P[s], s))
+            batch(float(best), cur)
+    return out
