@@ -338,12 +338,57 @@ int l1line_components(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                       double *V, int64_t *J, double *OBJ, int32_t *status,
                       void *stream);
 
+/* Algorithm 3 (Sec. 2; Table I for the worked example): the exact solution
+ * path z*(lambda), v*(lambda) over every lambda >= 0, merged over the
+ * preserved coordinates from the per-coordinate paths of Algorithm 2.
+ *
+ * For a preserved coordinate j, Algorithm 2's entries (l1line_breakpoints)
+ * fix every v_k between breakpoints; entry t of segment (j, k) holds for
+ * lambda >= its breakpoint (the double it reports), entries at equal lambda
+ * applying in (k, t) order.  With them z_j is the line E_j + lambda P_j,
+ * E_j = sum_k e_jk(v_k) (each e_jk the R64 residual Algorithm 1 reports) and
+ * P_j = 1 + sum_{k != j} |v_k|, both summed EXACTLY.  The path follows the
+ * lowest line (value, then slope, then the lower j) through every lambda:
+ * the preserved coordinate changes where lines cross (the crossings the
+ * paper's Algorithm 3 adds), each crossing compared exactly and reported
+ * rounded once to the nearest double.
+ *
+ * Output: `count` records in lambda order (DEVICE arrays of `capacity`):
+ *   lam[r]  where the change happens
+ *   j[r]    the preserved coordinate from there on
+ *   k[r], v[r], row[r]  coordinate k of v* becomes v (row: its median row,
+ *           -1 when v is 0 and for k = j, where v = 1)
+ *   E[r], P[r]  z*(lambda) = E + lambda P from there on (each rounded once)
+ * The start (lambda = 0) and every change of the preserved coordinate list
+ * all m coordinates k = 0..m-1 at one lambda; otherwise each record is one
+ * breakpoint entry of the current j.  Replaying the records up to lambda gives
+ * v*(lambda); lambda beyond the last record keeps the last line.
+ *
+ *   count    HOST: the number of records (always written on success)
+ *   capacity records the outputs hold; 0 (outputs may be null) only counts
+ *   status   nullable DEVICE int32: 0 or the error returned
+ * Synchronous in part: the call waits for `stream` to learn the count; the
+ * records are written asynchronously after it returns.
+ * Errors (returned): EINVAL (arguments, null count), ESIZE (m above
+ * L1LINE_BP_MAX_M, more than 2^32 - 1 breakpoint entries, or count above
+ * a nonzero capacity: nothing is written, count holds the size needed),
+ * ENONFINITE / EWIDE as l1line_fit, EWIDE also when some residual or |v| has
+ * bits more than 110 places below the largest (the exact lines would not fit
+ * 128 bits), ENOMEM for the workspace: about 120 bytes per breakpoint entry
+ * plus 28 bytes per (tile, column) for 4096 tiles. */
+int l1line_solution_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                         int64_t ld, int64_t capacity, int64_t *count,
+                         double *lam, int64_t *j, int32_t *k, double *v,
+                         int32_t *row, double *E, double *P, int32_t *status,
+                         void *stream);
+
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.
  * l1line_profile_read waits for the recorded events, returns the summed
  * duration (ms) and launch count of the kernels whose name is `kernel`
  * ("colprep", "signsum", "fit_seg", "reduce", "argmin", "features",
- * "mlp_fwd", "mlp_bwd", "bp_count", "bp_emit"; NULL = all), and with
+ * "mlp_fwd", "mlp_bwd", "bp_count", "bp_emit", "sp_resid", "sp_delta",
+ * "sp_sort", "sp_bounds", "sp_sweep"; NULL = all), and with
  * reset != 0
  * forgets every record.  Outputs are HOST pointers (nullable). */
 int l1line_profile(l1line_ctx ctx, int enable);

@@ -24,7 +24,7 @@ EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_er
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
            "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
            "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train",
-           "l1line_breakpoints", "l1line_components"]
+           "l1line_breakpoints", "l1line_components", "l1line_solution_path"]
 BATCH_GRAPH = 1
 FEATURES = 32
 MLP_PARAMS = 20865
@@ -65,6 +65,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_ranker_train.argtypes = [P, ctypes.c_char_p, I64, ctypes.c_uint64]
         L.l1line_breakpoints.argtypes = [P, P, I64, I64, I64, P, P, P, P, P, I64, P, P]
         L.l1line_components.argtypes = [P, P, I64, I64, I64, D, I64, P, P, P, P, P, P]
+        L.l1line_solution_path.argtypes = [P, P, I64, I64, I64, I64, P, P, P, P, P, P, P, P, P, P]
         L.l1line_destroy.argtypes = [P]
         L.l1line_strerror.argtypes = [I32]
         L.l1line_strerror.restype = ctypes.c_char_p
@@ -360,6 +361,33 @@ class Context:
             _check(lib().l1line_breakpoints(self._h, _ptr(X), n, m, ld, _ptr(offsets), _ptr(lmax), _ptr(out["lam"]),
                                             _ptr(out["v"]), _ptr(out["row"]), total, _ptr(status),
                                             self._stream()), "l1line_breakpoints")
+        return out
+
+    def solution_path(self, X, capacity: int | None = None):
+        """Algorithm 3: the records of the exact solution path (dict of device
+        tensors lam, j, k, v, row, E, P, and count).  Without a capacity the
+        library is asked for the count first (two calls)."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        cnt = ctypes.c_int64(0)
+        status = self._empty((1,), torch.int32)
+        if capacity is None:
+            _check(lib().l1line_solution_path(self._h, _ptr(X), n, m, ld, 0, ctypes.byref(cnt), None, None, None,
+                                              None, None, None, None, _ptr(status), self._stream()),
+                   "l1line_solution_path")
+            capacity = cnt.value
+        c = max(int(capacity), 1)
+        out = dict(lam=self._empty((c,), torch.float64), j=self._empty((c,), torch.int64),
+                   k=self._empty((c,), torch.int32), v=self._empty((c,), torch.float64),
+                   row=self._empty((c,), torch.int32), E=self._empty((c,), torch.float64),
+                   P=self._empty((c,), torch.float64), status=status)
+        _check(lib().l1line_solution_path(self._h, _ptr(X), n, m, ld, c, ctypes.byref(cnt), _ptr(out["lam"]),
+                                          _ptr(out["j"]), _ptr(out["k"]), _ptr(out["v"]), _ptr(out["row"]),
+                                          _ptr(out["E"]), _ptr(out["P"]), _ptr(status), self._stream()),
+               "l1line_solution_path")
+        out["count"] = cnt.value
+        for key in ("lam", "j", "k", "v", "row", "E", "P"):
+            out[key] = out[key][:cnt.value]
         return out
 
     def components(self, X, lam: float, p: int):

@@ -21,6 +21,7 @@
 #include "ranker_kernels.h"
 #include "bp_kernels.h"
 #include "comp_kernels.h"
+#include "path_kernels.h"
 
 // ------------------------------------------------------------------- context
 struct ProfRec {
@@ -51,6 +52,8 @@ struct l1line_ctx_s {
   std::vector<ProfRec> prof;
   void *rk;                 // ranker scratch (features, sign sums, MLP buffers)
   size_t rk_bytes;
+  void *sp;                 // solution-path scratch (per breakpoint entry, per tile and column)
+  size_t sp_bytes;
   int *sticky;              // device: first data-dependent error of any call on the context
   int host_err;             // first argument / runtime error an entry point returned
   std::string tune_path;    // launch-parameter cache file ("" = none)
@@ -131,6 +134,23 @@ static int ensure_rk(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
     return L1LINE_ENOMEM;
   }
   ctx->rk_bytes = want;
+  return L1LINE_OK;
+}
+
+static int ensure_sp(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
+  if (bytes <= ctx->sp_bytes) return L1LINE_OK;
+  if (ctx->sp) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipFree(ctx->sp));
+    ctx->sp = nullptr;
+    ctx->sp_bytes = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 8, 1 << 20);
+  if (hipMalloc(&ctx->sp, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return L1LINE_ENOMEM;
+  }
+  ctx->sp_bytes = want;
   return L1LINE_OK;
 }
 
@@ -581,6 +601,8 @@ int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path) {
   c->profiling = false;
   c->rk = nullptr;
   c->rk_bytes = 0;
+  c->sp = nullptr;
+  c->sp_bytes = 0;
   c->sticky = nullptr;
   c->host_err = L1LINE_OK;
   c->rk_w = nullptr;
@@ -634,6 +656,7 @@ int l1line_destroy(l1line_ctx ctx) {
   if (ctx->ws && hipFree(ctx->ws) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->stage && hipHostFree(ctx->stage) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->rk && hipFree(ctx->rk) != hipSuccess) st = L1LINE_EHIP;
+  if (ctx->sp && hipFree(ctx->sp) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->sticky && hipFree(ctx->sticky) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->rk_w && hipFree(ctx->rk_w) != hipSuccess) st = L1LINE_EHIP;
   (void)hipEventDestroy(ctx->stage_done);
@@ -1318,6 +1341,165 @@ static int components_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
 int l1line_components(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, int64_t p,
                       double *work, double *V, int64_t *J, double *OBJ, int32_t *status, void *stream) {
   return note(ctx, components_impl(ctx, X, n, m, ld, lambda, p, work, V, J, OBJ, status, stream));
+}
+
+// ------------------------------------------------------------ solution path
+static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, int64_t capacity,
+                              int64_t *count, double *lam, int64_t *jo, int32_t *ko, double *vo, int32_t *ro,
+                              double *Eo, double *Po, int32_t *status, void *stream) {
+  if (!ctx || !count || capacity < 0 ||
+      (capacity > 0 && (!lam || !jo || !ko || !vo || !ro || !Eo || !Po)))
+    return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  if (m > L1LINE_BP_MAX_M) return L1LINE_ESIZE;
+  *count = 0;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const long long mm = (long long)m * m;
+  // small scratch: the lambda = 0 fit, Algorithm 2's offsets, per-segment and
+  // per-tile values
+  const size_t o_v = 0, o_j = align_up(sizeof(double) * m, 256), o_obj = o_j + 256, o_fst = o_obj + 256,
+               o_off = o_fst + 256, o_lm = o_off + align_up(sizeof(long long) * (mm + 1), 256),
+               o_segv = o_lm + align_up(sizeof(double) * mm, 256), o_gmax = o_segv + align_up(sizeof(double) * mm, 256),
+               o_sc = o_gmax + 256, o_T = o_sc + 256, o_tot = o_T + 256, o_D = o_tot + 256,
+               o_bnd = o_D + align_up(sizeof(double) * m, 256), o_U = o_bnd + align_up(sizeof(double) * SP_TMAX, 256),
+               o_cnt = o_U + align_up(sizeof(double) * SP_TMAX, 256),
+               o_info = o_cnt + align_up(sizeof(int) * SP_TMAX, 256),
+               o_sw = o_info + align_up(sizeof(TileInfo) * SP_TMAX, 256),
+               o_toff = o_sw + align_up(sizeof(int) * SP_TMAX, 256),
+               small = o_toff + align_up(sizeof(long long) * (SP_TMAX + 1), 256);
+  st = ensure_rk(ctx, small, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  int *fst = (int *)(b + o_fst);
+  long long *offsets = (long long *)(b + o_off);
+  double *lm = (double *)(b + o_lm), *segv = (double *)(b + o_segv), *D = (double *)(b + o_D);
+  unsigned long long *gmax = (unsigned long long *)(b + o_gmax);
+  PathScale *sc = (PathScale *)(b + o_sc);
+  int *Tp = (int *)(b + o_T), *cnt = (int *)(b + o_cnt), *sw = (int *)(b + o_sw);
+  long long *tot = (long long *)(b + o_tot), *toff = (long long *)(b + o_toff);
+  double *bnd = (double *)(b + o_bnd), *U = (double *)(b + o_U);
+  TileInfo *info = (TileInfo *)(b + o_info);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, fst, 1ll, 0);
+  const double zero = 0.0;
+  const l1line_problem p0 = single(X, n, m, ld, &zero, 1, (double *)(b + o_v), (int64_t *)(b + o_j),
+                                   (double *)(b + o_obj), nullptr, nullptr, fst);
+  BatchPtrs bp;
+  st = run_batch(ctx, &p0, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
+  if (st) return st;
+  const unsigned grid = (unsigned)std::max(1ll, std::min((mm + 3) / 4, (long long)ctx->num_cu * 8));
+  {
+    ProfScope ps(ctx, s, "bp_count");
+    hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                       (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, offsets + 1, lm);
+    hipLaunchKernelGGL(k_bp_scan, dim3(1), dim3(1024), 0, s, offsets, mm);
+  }
+  long long NE = 0;
+  int h_fst = 0;
+  HIP_TRY(hipMemcpyAsync(&NE, offsets + mm, sizeof NE, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&h_fst, fst, sizeof h_fst, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h_fst) return h_fst;
+  if (NE < 0 || NE > (long long)UINT32_MAX) return L1LINE_ESIZE;
+  // per-entry arrays, then per (tile, column) arrays
+  const size_t e8 = align_up(sizeof(double) * NE, 256), e4 = align_up(sizeof(int) * NE, 256),
+               e16 = align_up(sizeof(u128) * NE, 256), tm = (size_t)SP_TMAX * m;
+  const size_t q_lam = 0, q_v = q_lam + e8, q_row = q_v + e8, q_e = q_row + e4, q_dE = q_e + e8, q_dP = q_dE + e16,
+               q_kA = q_dP + e16, q_kB = q_kA + e8, q_iA = q_kB + e8, q_iB = q_iA + e4, q_sE = q_iB + e4,
+               q_sP = q_sE + e16, q_LB = q_sP + e16, q_list = q_LB + align_up(sizeof(double) * tm, 256),
+               q_pos = q_list + align_up(sizeof(int) * tm, 256), q_pb = q_pos + align_up(sizeof(long long) * tm, 256),
+               big = q_pb + align_up(sizeof(long long) * tm, 256);
+  st = ensure_sp(ctx, big, s);
+  if (st) return st;
+  char *c = (char *)ctx->sp;
+  double *elam = (double *)(c + q_lam), *ev = (double *)(c + q_v), *ee = (double *)(c + q_e),
+         *LB = (double *)(c + q_LB);
+  int *erow = (int *)(c + q_row), *list = (int *)(c + q_list);
+  u128 *dE = (u128 *)(c + q_dE), *dP = (u128 *)(c + q_dP), *stE = (u128 *)(c + q_sE), *stP = (u128 *)(c + q_sP);
+  uint64_t *keyA = (uint64_t *)(c + q_kA), *keyB = (uint64_t *)(c + q_kB);
+  uint32_t *idA = (uint32_t *)(c + q_iA), *idB = (uint32_t *)(c + q_iB);
+  long long *spos = (long long *)(c + q_pos), *spb = (long long *)(c + q_pb);
+  {
+    ProfScope ps(ctx, s, "bp_emit");
+    hipLaunchKernelGGL(k_bp_emit, dim3(grid), dim3(64 * BP_WAVES), 0, s, X, (int)n, (int)m, (long long)ld,
+                       (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (const long long *)offsets,
+                       (const double *)lm, (long long)NE, elam, ev, erow, fst, ctx->sticky);
+  }
+  HIP_TRY(hipMemsetAsync(gmax, 0, 4 * sizeof(unsigned long long), s));
+  {
+    ProfScope ps(ctx, s, "sp_resid");
+    hipLaunchKernelGGL(k_sp_resid, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                       (const long long *)offsets, (const double *)elam, (const double *)ev, ee, segv, gmax);
+  }
+  hipLaunchKernelGGL(k_sp_scale, dim3(1), dim3(1), 0, s, (const unsigned long long *)gmax, sc);
+  {
+    ProfScope ps(ctx, s, "sp_delta");
+    hipLaunchKernelGGL(k_sp_delta, dim3(grid), dim3(256), 0, s, (int)m, (const long long *)offsets,
+                       (const double *)ev, (const double *)ee, sc, dE, dP);
+  }
+  {
+    ProfScope ps(ctx, s, "sp_sort");
+    hipLaunchKernelGGL(k_sp_sort, dim3((unsigned)m), dim3(1024), 0, s, (int)m, (const long long *)offsets,
+                       (const double *)elam, keyA, idA, keyB, idB, (const u128 *)dE, (const u128 *)dP,
+                       (const PathScale *)sc, stE, stP);
+  }
+  {
+    ProfScope ps(ctx, s, "sp_bounds");
+    hipLaunchKernelGGL(k_sp_tiles, dim3(1), dim3(1024), 0, s, NE, (const double *)elam, (const PathScale *)sc, bnd,
+                       Tp);
+    hipLaunchKernelGGL(k_sp_slack, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, (int)n, (int)m,
+                       (const ColInfo *)bp.ci, (const double *)segv, (const PathScale *)sc, D);
+    hipLaunchKernelGGL(k_sp_bounds, dim3(SP_TMAX), dim3(256), 0, s, (int)m, (const long long *)offsets,
+                       (const uint64_t *)keyA, (const u128 *)stE, (const u128 *)stP, (const PathScale *)sc,
+                       (const double *)bnd, (const int *)Tp, (const double *)D, LB, U);
+    hipLaunchKernelGGL(k_sp_surv, dim3(SP_TMAX), dim3(256), 0, s, (int)m, (const long long *)offsets,
+                       (const u128 *)stE, (const double *)LB, (const double *)U, (const int *)Tp, list, cnt);
+  }
+  PathOut out{lam, (long long *)jo, (int *)ko, vo, (int *)ro, Eo, Po};
+  {
+    ProfScope ps(ctx, s, "sp_sweep");
+    hipLaunchKernelGGL(k_sp_sweep, dim3(SP_TMAX), dim3(64), 0, s, (int)m, (const long long *)offsets,
+                       (const double *)elam, (const double *)ev, (const int *)erow, (const uint64_t *)keyA,
+                       (const uint32_t *)idA, (const u128 *)stE, (const u128 *)stP, sc,
+                       (const double *)bnd, (const int *)Tp, (const int *)list, (const int *)cnt, spos, spb, info,
+                       (const long long *)toff, (const int *)sw, 0, out, 0ll);
+    hipLaunchKernelGGL(k_sp_toff, dim3(1), dim3(1024), 0, s, (int)m, (const int *)Tp, (const TileInfo *)info, sw,
+                       toff, tot);
+  }
+  PathScale hsc;
+  long long total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, tot, sizeof total, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&hsc, sc, sizeof hsc, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&h_fst, fst, sizeof h_fst, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  if (h_fst) return h_fst;
+  if (hsc.bad) {
+    const int code = (hsc.bad & 1) ? L1LINE_EWIDE : L1LINE_EINTERNAL;
+    if (status) hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, (int *)status, 1ll, code);
+    return code;
+  }
+  *count = total;
+  if (capacity == 0) return L1LINE_OK;
+  if (total > capacity) return L1LINE_ESIZE;
+  {
+    ProfScope ps(ctx, s, "sp_sweep");
+    hipLaunchKernelGGL(k_sp_sweep, dim3(SP_TMAX), dim3(64), 0, s, (int)m, (const long long *)offsets,
+                       (const double *)elam, (const double *)ev, (const int *)erow, (const uint64_t *)keyA,
+                       (const uint32_t *)idA, (const u128 *)stE, (const u128 *)stP, sc,
+                       (const double *)bnd, (const int *)Tp, (const int *)list, (const int *)cnt, spos, spb, info,
+                       (const long long *)toff, (const int *)sw, 1, out, (long long)capacity);
+  }
+  if (status) hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, (int *)status, 1ll, 0);
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_solution_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, int64_t capacity,
+                         int64_t *count, double *lam, int64_t *j, int32_t *k, double *v, int32_t *row, double *E,
+                         double *P, int32_t *status, void *stream) {
+  return note(ctx, solution_path_impl(ctx, X, n, m, ld, capacity, count, lam, j, k, v, row, E, P, status, stream));
 }
 
 }  // extern "C"

@@ -189,3 +189,21 @@ def test_components_and_breakpoints_host_checks():
     assert lib.l1line_breakpoints(f.h, P(1), 10, 4, 10, P(1), None, None, None, None, 5, None, None) == B.EINVAL
     assert lib.l1line_breakpoints(f.h, P(1), 10, 9000, 10, P(1), None, None, None, None, 0, None,
                                   None) == B.ESIZE
+
+
+def test_solution_path_host_checks():
+    lib = B.lib()
+    f = _Fake()
+    P = ctypes.c_void_p
+    cnt = ctypes.c_int64(0)
+    o = [P(1)] * 7
+    assert lib.l1line_solution_path(None, P(1), 10, 4, 10, 0, ctypes.byref(cnt), *([None] * 7), None,
+                                    None) == B.EINVAL
+    assert lib.l1line_solution_path(f.h, P(1), 10, 4, 10, 0, None, *([None] * 7), None, None) == B.EINVAL
+    assert lib.l1line_solution_path(f.h, P(1), 10, 4, 10, -1, ctypes.byref(cnt), *o, None, None) == B.EINVAL
+    assert lib.l1line_solution_path(f.h, P(1), 10, 4, 10, 5, ctypes.byref(cnt), *([None] * 7), None,
+                                    None) == B.EINVAL                                     # outputs missing
+    assert lib.l1line_solution_path(f.h, None, 10, 4, 10, 0, ctypes.byref(cnt), *([None] * 7), None,
+                                    None) == B.EINVAL                                     # null X
+    assert lib.l1line_solution_path(f.h, P(1), 10, 9000, 10, 0, ctypes.byref(cnt), *([None] * 7), None,
+                                    None) == B.ESIZE
