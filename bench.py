@@ -8,8 +8,8 @@ weighted median with its residual, the per-j objectives, the argmin) on a
 
 Besides the main line it reports, as extra fields, the 64-penalty path on
 the same matrix, the 512-matrix uneven batch, the learned top-K fit,
-Algorithm 2 (every segment's breakpoints) and three successive components
-of the same matrix.
+Algorithm 2 (every segment's breakpoints), three successive components of
+the same matrix and Algorithm 3 (the exact solution path over every lambda).
 """
 from __future__ import annotations
 
@@ -45,7 +45,7 @@ def _args():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (scale for HBM byte counters)")
-    ap.add_argument("--legs", default="path,batch,ranked,breakpoints,components",
+    ap.add_argument("--legs", default="path,batch,ranked,breakpoints,components,solution_path",
                     help="extra workloads reported beside the main line (comma list; '' for none)")
     ap.add_argument("--ranked-instances", type=int, default=3)
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -251,6 +251,35 @@ def leg_components(ctx, seed, steps, stream):
             "ms_per_call": ms, "components_per_s": 3000.0 / ms, "status": int(out["status"].item())}
 
 
+def leg_solution_path(ctx, seed, steps, stream):
+    """Algorithm 3 on the main workload's 2000 x 2000 matrix: the exact
+    solution path over every lambda (Algorithm 2's entries, their residuals,
+    per-coordinate sort into exact lines, tile pruning, the sweep), with the
+    time of each stage."""
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import workloads as wl
+    p = wl.large_fit(seed)
+    X = B.device_matrix(p.X)
+    n, m = p.X.shape
+    first = ctx.solution_path(X)                  # sizes the outputs
+    cap = first["count"]
+    out, ms = _timed(lambda: ctx.solution_path(X, capacity=cap), steps, stream)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    ctx.solution_path(X, capacity=cap)
+    stages = {name: ctx.profile_read(name)[0] for name in ("bp_count", "bp_emit", "sp_resid", "sp_delta", "sp_sort",
+                                                           "sp_bounds", "sp_sweep")}
+    ctx.profile_read(reset=True)
+    ctx.profile(False)
+    lam = out["lam"].cpu().numpy()
+    jj = out["j"].cpu().numpy()
+    switches = int(np.count_nonzero(jj[1:] != jj[:-1]))
+    return {"workload": f"Algorithm 3, the exact solution path of the {n}x{m} matrix over every lambda >= 0",
+            "ms_per_call": ms, "records": int(out["count"]), "preserved_coordinate_changes": switches,
+            "lambda_top": float(lam[-1]) if lam.size else 0.0, "stage_ms": stages,
+            "status": int(out["status"].item())}
+
+
 def leg_ranked(ctx, count):
     """Learned top-K (K = 32) vs exhaustive on 10000 x 4000 matrices."""
     import os
@@ -378,6 +407,8 @@ def main():
         line["breakpoints"] = leg_breakpoints(ctx, a.seed, 3, stream)
     if "components" in legs:
         line["components"] = leg_components(ctx, a.seed, 3, stream)
+    if "solution_path" in legs:
+        line["solution_path"] = leg_solution_path(ctx, a.seed, 3, stream)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, lam, z_gpu, a.cpu_columns)
     ctx.close()

@@ -25,7 +25,7 @@
 //   6. k_sp_slack, k_sp_bounds, k_sp_surv: per (tile, j) a lower bound of
 //      z_j and per tile an upper bound of z*; a j whose lower bound exceeds
 //      the upper bound cannot be on the path in that tile.  The bounds come
-//      from the line just before the tile's left end plus a proven slack:
+//      from the line just right of the tile's left end plus a proven slack:
 //      each z_j differs from a concave, increasing function (the same
 //      objective with the residuals summed exactly in real arithmetic) by at
 //      most Delta_j, which covers the rounding of every residual and of every
@@ -210,6 +210,16 @@ __device__ __forceinline__ long long lower_bound_u64(const uint64_t *__restrict_
   while (lo < hi) {
     const long long mid = (lo + hi) >> 1;
     if (a[mid] < kb) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// first position in [0, len) whose key is > kb (len if none)
+__device__ __forceinline__ long long upper_bound_u64(const uint64_t *__restrict__ a, long long len, uint64_t kb) {
+  long long lo = 0, hi = len;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (a[mid] <= kb) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -442,8 +452,8 @@ k_sp_sort(int m, const long long *__restrict__ offsets, const double *__restrict
 
 // ---------------------------------------------------------------------- tiles
 // Tile boundaries b_0 = 0 < b_1 < ... < b_{T-1} = lambda_top at quantiles of
-// a strided sample of the breakpoints; tile i is [b_i, b_{i+1}), the last
-// [lambda_top, inf).  T = 1 when lambda_top is 0.
+// a strided sample of the breakpoints and on a uniform grid; tile i is
+// [b_i, b_{i+1}), the last [lambda_top, inf).  T = 1 when lambda_top is 0.
 __global__ void __launch_bounds__(1024)
 k_sp_tiles(long long NE, const double *__restrict__ elam, const PathScale *__restrict__ sc, double *__restrict__ bnd,
            int *__restrict__ T) {
@@ -469,12 +479,26 @@ k_sp_tiles(long long NE, const double *__restrict__ elam, const PathScale *__res
     }
   }
   if (tid == 0) {
+    // half the boundaries at quantiles of the sample, half on a uniform grid
+    // over (0, lambda_top) (wide stretches with few breakpoints still get
+    // narrow tiles), merged in order without repeats
     const double top = sc->lam_top;
+    constexpr int H = SP_TMAX / 2;
     int c = 1;
     bnd[0] = 0.0;
     if (top > 0.0) {
-      for (int q = 1; q < SP_TMAX - 1; ++q) {
-        const double x = dofbits(smp[((long long)q * SP_SAMPLES) / (SP_TMAX - 1)]);
+      int qa = 1, ua = 1;
+      while (qa < H || ua < H) {
+        const double xq = qa < H ? dofbits(smp[((long long)qa * SP_SAMPLES) / H]) : INFINITY;
+        const double xu = ua < H ? top * ((double)ua / (double)H) : INFINITY;
+        double x;
+        if (xq <= xu) {
+          x = xq;
+          ++qa;
+        } else {
+          x = xu;
+          ++ua;
+        }
         if (x > bnd[c - 1] && x < top) bnd[c++] = x;
       }
       bnd[c++] = top;
@@ -506,7 +530,11 @@ __global__ void k_sp_slack(int n, int m, const ColInfo *__restrict__ ci, const d
 }
 
 // Per tile i < T - 1 (one block): LB[i m + j] = lower bound of z_j on the tile,
-// U[i] = the smallest upper bound of any z_j over the tile.
+// U[i] = the smallest upper bound of any z_j over the tile.  With c_j the
+// concave increasing function within Delta_j of z_j and (E, P) the line of z_j
+// just right of b_i: z_j >= c_j(b_i) - Delta_j >= E + b_i P - 2 Delta_j on the
+// tile, and z_j(lambda) <= (the objective with v held at that line's v) +
+// Delta_j <= E + lambda P + 2 Delta_j.
 __global__ void __launch_bounds__(256)
 k_sp_bounds(int m, const long long *__restrict__ offsets, const uint64_t *__restrict__ key,
             const u128 *__restrict__ stE, const u128 *__restrict__ stP, const PathScale *__restrict__ sc,
@@ -523,7 +551,7 @@ k_sp_bounds(int m, const long long *__restrict__ offsets, const uint64_t *__rest
   double umin = INFINITY;
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     const long long a = offsets[(long long)j * m], N = offsets[(long long)j * m + m] - a;
-    const long long pos = lower_bound_u64(key + a, N, kb);
+    const long long pos = upper_bound_u64(key + a, N, kb);   // the line right of b_i
     const u128 E = pos > 0 ? stE[a + pos - 1] : (u128)0, P = pos > 0 ? stP[a + pos - 1] : one;
     const double Ed = fixed_to_double(E, sE), Pd = fixed_to_double(P, sP);
     const double zl = Ed + bl * Pd, zu = Ed + br * Pd;
@@ -620,7 +648,7 @@ struct PathOut {
 // Per tile: j at the start (after the entries at b_i), j at the end, the
 // records after the start point, and the entries of the start's j at b_i.
 struct TileInfo {
-  int jstart, jend, nstart, pad;
+  int jstart, jend, nstart, npoints;   // npoints: breakpoint values the sweep visited
   long long ninner;
 };
 
@@ -726,9 +754,10 @@ k_sp_sweep(int m, const long long *__restrict__ offsets, const double *__restric
   }
   __syncthreads();
   long long at = emit ? toff[i] : 0, ninner = 0;
-  int jstart = -1, nstart = 0, cur = -1;   // cur: survivor index of the lowest line
+  int jstart = -1, nstart = 0, cur = -1, npoints = 0;   // cur: survivor index of the lowest line
   double p = bl;
   while (true) {
+    ++npoints;
     // apply the entries at p; the next breakpoint of any survivor
     const uint64_t kp = dbits(p);
     uint64_t qk = ~0ull;
@@ -880,7 +909,7 @@ k_sp_sweep(int m, const long long *__restrict__ offsets, const double *__restric
     t.jstart = jstart;
     t.jend = L[cur];
     t.nstart = nstart;
-    t.pad = 0;
+    t.npoints = npoints;
     t.ninner = ninner;
     info[i] = t;
   }
