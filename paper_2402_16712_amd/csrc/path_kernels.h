@@ -15,7 +15,7 @@
 //
 // Pipeline (one GPU, everything on the device):
 //   1. Algorithm 2's entries (bp_kernels.h).
-//   2. k_sp_resid: e for every entry, 8 entries per pass over the rows; the
+//   2. k_sp_resid: e for every entry, 16 entries per pass over the rows; the
 //      global maxima that fix the scales.
 //   3. k_sp_delta: each entry's change of (E, P) in fixed point.
 //   4. k_sp_sort: one workgroup per j sorts j's entries by breakpoint (stable
@@ -41,7 +41,7 @@
 
 constexpr int SP_TMAX = 4096;      // lambda tiles
 constexpr int SP_SAMPLES = 4096;   // breakpoints sampled to place them
-constexpr int SP_RG = 8;           // entries scored per pass over the rows
+constexpr int SP_RG = 16;          // entries scored per pass over the rows
 
 struct PathScale {
   int sE, sP;        // units of E and P: 2^sE, 2^sP
@@ -256,6 +256,7 @@ k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long 
         v[r] = t0 + r < b ? ev[t0 + r] : 0.0;
         p[r] = 0.0;
       }
+#pragma unroll 2
       for (int i = lane; i < n; i += 64) {
         const double x = xj[i], y = xk[i];
 #pragma unroll
