@@ -110,30 +110,67 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
   }
 }
 
-// In-place inclusive scan of offsets[1 .. count] with offsets[0] = 0 (one
-// workgroup of 1024: contiguous chunks per thread, then a scan of the chunk
-// totals).
-__global__ void __launch_bounds__(1024) k_bp_scan(long long *__restrict__ offsets, long long count) {
-  __shared__ long long part[1024];
-  const int tid = threadIdx.x;
-  const long long chunk = (count + 1023) / 1024;
-  const long long b = 1 + tid * chunk, e = min(count + 1, b + chunk);
-  long long sum = 0;
-  for (long long q = b; q < e; ++q) sum += offsets[q];
-  part[tid] = sum;
+constexpr int BP_SCAN_BLOCKS = 1024;
+
+// Inclusive block scan of one value per thread (1024 threads); returns the
+// thread's inclusive prefix and leaves the block total in *tot.
+__device__ __forceinline__ long long block_scan_ll(long long x, long long *sh, long long *tot) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  long long v = x;
+  for (int d = 1; d < 64; d <<= 1) {
+    const long long o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  if (lane == 63) sh[w] = v;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const long long add = tid >= d ? part[tid - d] : 0;
-    __syncthreads();
-    part[tid] += add;
-    __syncthreads();
+  long long before = 0, all = 0;
+  for (int q = 0; q < 16; ++q) {
+    if (q < w) before += sh[q];
+    all += sh[q];
   }
-  long long run = part[tid] - sum;
-  for (long long q = b; q < e; ++q) {
-    run += offsets[q];
-    offsets[q] = run;
+  __syncthreads();
+  *tot = all;
+  return before + v;
+}
+
+// Offsets: counts sit in offsets[1..count]; afterwards offsets[q] = the sum
+// of counts 1..q and offsets[0] = 0.  Three passes: chunk sums, their scan,
+// the chunks' scans.
+__global__ void __launch_bounds__(1024)
+k_bp_scan_sums(const long long *__restrict__ offsets, long long count, long long *__restrict__ part) {
+  __shared__ long long sh[16];
+  const long long chunk = (count + gridDim.x - 1) / gridDim.x;
+  const long long b0 = (long long)blockIdx.x * chunk, e = min(count, b0 + chunk);
+  long long sum = 0;
+  for (long long q = b0 + threadIdx.x; q < e; q += 1024) sum += offsets[1 + q];
+  long long tot;
+  (void)block_scan_ll(sum, sh, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_bp_scan_top(long long *__restrict__ part, int nb) {
+  __shared__ long long sh[16];
+  const long long x = threadIdx.x < nb ? part[threadIdx.x] : 0;
+  long long tot;
+  const long long incl = block_scan_ll(x, sh, &tot);
+  if (threadIdx.x < nb) part[threadIdx.x] = incl - x;   // exclusive
+}
+
+__global__ void __launch_bounds__(1024)
+k_bp_scan_fin(long long *__restrict__ offsets, long long count, const long long *__restrict__ part) {
+  __shared__ long long sh[16];
+  const long long chunk = (count + gridDim.x - 1) / gridDim.x;
+  const long long b0 = (long long)blockIdx.x * chunk, e = min(count, b0 + chunk);
+  long long carry = part[blockIdx.x];
+  for (long long t0 = b0; t0 < e; t0 += 1024) {
+    const long long q = t0 + threadIdx.x;
+    const long long x = q < e ? offsets[1 + q] : 0;
+    long long tot;
+    const long long incl = block_scan_ll(x, sh, &tot);
+    if (q < e) offsets[1 + q] = carry + incl;
+    carry += tot;
   }
-  if (tid == 0) offsets[0] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
 }
 
 // ------------------------------------------------------------------ entries

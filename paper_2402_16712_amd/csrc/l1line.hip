@@ -1250,6 +1250,15 @@ int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps, ui
 }
 
 // ------------------------------------------------------------ Algorithm 2
+// offsets[1..count] (per-segment counts) into offsets (offsets[0] = 0);
+// part: BP_SCAN_BLOCKS scratch values
+static void scan_offsets(hipStream_t s, long long *offsets, long long count, long long *part) {
+  const int nb = (int)std::max(1ll, std::min((long long)BP_SCAN_BLOCKS, (count + 4095) / 4096));
+  hipLaunchKernelGGL(k_bp_scan_sums, dim3(nb), dim3(1024), 0, s, (const long long *)offsets, count, part);
+  hipLaunchKernelGGL(k_bp_scan_top, dim3(1), dim3(1024), 0, s, part, nb);
+  hipLaunchKernelGGL(k_bp_scan_fin, dim3(nb), dim3(1024), 0, s, offsets, count, (const long long *)part);
+}
+
 static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, int64_t *offsets,
                             double *lambda_max, double *lam, double *v, int32_t *row, int64_t capacity,
                             int32_t *status, void *stream) {
@@ -1260,7 +1269,8 @@ static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   // scratch: the lambda = 0 fit's outputs and lambda_max when not requested
-  const size_t o_v = 0, o_j = align_up(sizeof(double) * m, 256), o_obj = o_j + 256, o_lm = o_obj + 256,
+  const size_t o_v = 0, o_j = align_up(sizeof(double) * m, 256), o_obj = o_j + 256,
+               o_part = o_obj + 256, o_lm = o_part + align_up(sizeof(long long) * BP_SCAN_BLOCKS, 256),
                total = o_lm + (lambda_max ? 0 : align_up(sizeof(double) * m * m, 256));
   st = ensure_rk(ctx, total, s);
   if (st) return st;
@@ -1278,7 +1288,7 @@ static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
     ProfScope ps(ctx, s, "bp_count");
     hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
                        (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (long long *)offsets + 1, lm);
-    hipLaunchKernelGGL(k_bp_scan, dim3(1), dim3(1024), 0, s, (long long *)offsets, nseg);
+    scan_offsets(s, (long long *)offsets, nseg, (long long *)(b + o_part));
   }
   if (capacity > 0) {
     ProfScope ps(ctx, s, "bp_emit");
@@ -1368,7 +1378,8 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
                o_info = o_cnt + align_up(sizeof(int) * SP_TMAX, 256),
                o_sw = o_info + align_up(sizeof(TileInfo) * SP_TMAX, 256),
                o_toff = o_sw + align_up(sizeof(int) * SP_TMAX, 256),
-               small = o_toff + align_up(sizeof(long long) * (SP_TMAX + 1), 256);
+               o_part = o_toff + align_up(sizeof(long long) * (SP_TMAX + 1), 256),
+               small = o_part + align_up(sizeof(long long) * BP_SCAN_BLOCKS, 256);
   st = ensure_rk(ctx, small, s);
   if (st) return st;
   char *b = (char *)ctx->rk;
@@ -1393,7 +1404,7 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
     ProfScope ps(ctx, s, "bp_count");
     hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
                        (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, offsets + 1, lm);
-    hipLaunchKernelGGL(k_bp_scan, dim3(1), dim3(1024), 0, s, offsets, mm);
+    scan_offsets(s, offsets, mm, (long long *)(b + o_part));
   }
   long long NE = 0;
   int h_fst = 0;
