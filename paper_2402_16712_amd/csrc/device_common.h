@@ -24,6 +24,13 @@ __device__ __forceinline__ double ratio_of_key(uint64_t k) {
   return __longlong_as_double((long long)b);
 }
 
+// A load through the global address space: for pointers into device memory
+// whose address space the compiler cannot see (struct fields), so that it
+// emits a global load and waits for the memory counter only.
+__device__ __forceinline__ double gld(const double *p) {
+  return *(const __attribute__((address_space(1))) double *)p;
+}
+
 // ---------------------------------------------------------------- fixed point
 // A finite nonzero |x| is M * 2^E with M < 2^53 (E = -1074 for subnormals).
 __device__ __forceinline__ void dbl_parts(double a, uint64_t &M, int &E) {

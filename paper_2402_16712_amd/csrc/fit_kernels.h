@@ -149,7 +149,7 @@ k_colprep_batch(const ProbDesc *__restrict__ P, const int *__restrict__ colstart
 // is kept in registers: every pass recomputes the ratio it needs, which keeps
 // the register count low and the occupancy high.
 struct SegIO {
-  const double *__restrict__ xk;   // column k
+  const double *__restrict__ xk;   // column k (device memory)
   const double *__restrict__ sxj;  // column j (LDS)
   int n, T, Tp, e0, lane;          // rows, slots, pow2 >= T, fixed-point exponent
 };
@@ -158,10 +158,20 @@ struct SegIO {
 __device__ __forceinline__ uint64_t seg_key(const SegIO &s, int i) {
   const bool in = i < s.n;
   const int ic = in ? i : 0;
-  const double a = s.sxj[ic], b = s.xk[ic];
+  const double a = s.sxj[ic], b = gld(s.xk + ic);
   double r = b / a;
   r = r + 0.0;
   return (in && a != 0.0) ? key_of(r) : KEY_NONE;
+}
+
+// the same key from x_ij = a and x_ik = b already loaded (in: the row is
+// inside the matrix); branch-free, so that loads of the next slot issued
+// before it stay in flight across the divide
+__device__ __forceinline__ uint64_t key_of_pair(bool in, double a, double b) {
+  const bool ok = in && a != 0.0;
+  double r = b / (ok ? a : 1.0);
+  r = r + 0.0;
+  return ok ? key_of(r) : KEY_NONE;
 }
 
 // exact weight |x_ij| / 2^e0 of row i, 0 where !valid
@@ -493,7 +503,7 @@ __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
     const bool in = i < s.n;
     const int ic = in ? i : 0;
     const double prod = v * s.sxj[ic];
-    const double d = s.xk[ic] - prod;
+    const double d = gld(s.xk + ic) - prod;
     p = p + (in ? fabs(d) : 0.0);
   }
   return wave_r64_tree(p);
@@ -892,14 +902,22 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         // go to the LDS list (in row order)
         u128 slo128 = 0;
         int nwin = 0;
-#pragma unroll 2
+        // columns j and k are read one slot ahead so the loads overlap the
+        // divide; the weight reuses x_ij
+        double anext = s.sxj[lane < n ? lane : 0], bnext = gld(s.xk + (lane < n ? lane : 0));
         for (int tt = 0; tt < T; ++tt) {
           const int i = lane + 64 * tt;
-          const uint64_t key = seg_key(s, i);
+          const double a = anext, b = bnext;
+          const int i2 = i + 64 < n ? i + 64 : 0;
+          if (tt + 1 < T) {
+            anext = s.sxj[i2];
+            bnext = gld(s.xk + i2);
+          }
+          const uint64_t key = key_of_pair(i < n, a, b);
           const bool valid = key != KEY_NONE;
           const bool le_lo = valid && key <= plo;
           const bool inwin = valid && key > plo && key <= phi;
-          slo128 += le_lo ? seg_weight(s, i, true) : (u128)0;
+          slo128 += le_lo ? fixed_of(fabs(a), s.e0) : (u128)0;
           const uint64_t wm = __ballot(inwin);
           const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
           nwin += __builtin_popcountll(wm);
