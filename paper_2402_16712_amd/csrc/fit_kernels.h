@@ -935,15 +935,67 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           if (pass == 0 && __builtin_popcountll(nzg) == 1) break;
           continue;
         }
+        const u128 lamf = act ? slam[tl] : (u128)0;
+        const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
+        const bool want = mine && !hit;
+        const uint64_t wantm = __ballot(want);
+        u128 Slo = Slw;
+        if (__builtin_popcountll(wantm) == 1 && nwin > 128) {
+          // one target: only the quarter of the window that holds it is
+          // sorted.  Three sample keys around the target split the list; the
+          // exact weights below them pick the part (a contiguous range of the
+          // sorted order), which is compacted to the list's front.
+          const u128 tau1 = uni_u128(shfl_u128(tau, __builtin_ctzll(wantm)));
+          uint64_t piv[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            int ix = (int)floor((wlo + 0.06 * (c - 1)) * SAMPLE_ROWS);
+            ix = ix < 0 ? 0 : (ix >= SAMPLE_ROWS ? SAMPLE_ROWS - 1 : ix);
+            piv[c] = uni_u64(shfl_u64((ix & 1) ? sb : sa, ix >> 1));
+          }
+          piv[1] = piv[1] < piv[0] ? piv[0] : piv[1];
+          piv[2] = piv[2] < piv[1] ? piv[1] : piv[2];
+          u128 a0 = 0, a1 = 0, a2 = 0;
+          for (int e = lane; e < nwin; e += 64) {
+            const uint64_t key = lk[e];
+            const u128 w = fixed_of(fabs(s.sxj[lr[e]]), s.e0);
+            a0 += key < piv[0] ? w : (u128)0;
+            a1 += key < piv[1] ? w : (u128)0;
+            a2 += key < piv[2] ? w : (u128)0;
+          }
+          a0 = wave_sum_u128(a0);
+          a1 = wave_sum_u128(a1);
+          a2 = wave_sum_u128(a2);
+          const int c = (Slw + a0 < tau1 ? 1 : 0) + (Slw + a1 < tau1 ? 1 : 0) + (Slw + a2 < tau1 ? 1 : 0);
+          const uint64_t plo2 = c == 0 ? 0 : piv[c - 1], phi2 = c == 3 ? KEY_NONE : piv[c];
+          Slo = Slw + (c == 0 ? (u128)0 : (c == 1 ? a0 : (c == 2 ? a1 : a2)));
+          // stable in-place compaction: an element never moves above its own
+          // slot, so slots not yet read are never overwritten
+          int kept = 0;
+          for (int e0 = 0; e0 < nwin; e0 += 64) {
+            const int e = e0 + lane;
+            const bool in = e < nwin;
+            const uint64_t key = in ? lk[e] : 0;
+            const unsigned short row = in ? lr[e] : 0;
+            const bool keep = in && (c == 0 || key >= plo2) && (c == 3 || key < phi2);
+            const uint64_t km = __ballot(keep);
+            const int d = kept + __builtin_popcountll(km & ((1ull << lane) - 1ull));
+            kept += __builtin_popcountll(km);
+            if (keep) {
+              lk[d] = key;
+              lr[d] = row;
+            }
+          }
+          nwin = uni_int(kept);
+          wave_lds_sync();
+        }
         const int N = wave_sort_lds(lk, lr, nwin, lane);
         u128 tot, incl;
         wave_list_sums(s, lk, lr, N >> 6, tot, incl);
-        const u128 lamf = act ? slam[tl] : (u128)0;
-        const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
         uint64_t k2 = KEY_NONE;
         int r2 = -1;
         bool h2 = false;
-        wave_resolve(s, lk, lr, N >> 6, Slw, tot, incl, mine && !hit, tau, k2, r2, h2);
+        wave_resolve(s, lk, lr, N >> 6, Slo, tot, incl, want, tau, k2, r2, h2);
         if (h2) {
           okey = k2;
           orow = r2;
