@@ -68,6 +68,22 @@ __device__ __forceinline__ u128 fixed_of(double a, int e0) {
   return (sh >= 0) ? (sh < 128 ? up : (u128)0) : (-sh < 64 ? dn : (u128)0);
 }
 
+// fixed_of for a weight of a column that passed the range check
+// (lowest_bit_exp(a) >= e0, highest_bit_exp(a) - e0 < 124; 0 gives 0).  When
+// E < e0 the bits shifted out of M are zeros.  Branch-free (64-bit shifts and
+// selects).
+__device__ __forceinline__ u128 fixed_of_col(double a, int e0) {
+  uint64_t M; int E;
+  dbl_parts(a, M, E);
+  const int d = E - e0;
+  M = d < 0 ? M >> ((-d) & 63) : M;
+  const int sh = d < 0 ? 0 : d;
+  const bool low = sh < 64;
+  const uint64_t lo = low ? M << (sh & 63) : 0;
+  const uint64_t hi = low ? ((M >> 1) >> (63 - (sh & 63))) : M << ((sh - 64) & 63);
+  return (((u128)hi) << 64) | lo;
+}
+
 // floor(lambda / 2^e0), saturated at 2^126 (beyond every weight sum of a
 // column that passed the range check, so it acts as +infinity).
 __device__ __forceinline__ u128 lambda_fixed(double lam, int e0) {

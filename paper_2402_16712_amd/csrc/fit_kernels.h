@@ -176,8 +176,8 @@ __device__ __forceinline__ uint64_t key_of_pair(bool in, double a, double b) {
 
 // exact weight |x_ij| / 2^e0 of row i, 0 where !valid
 __device__ __forceinline__ u128 seg_weight(const SegIO &s, int i, bool valid) {
-  const double a = valid ? fabs(s.sxj[valid ? i : 0]) : 0.0;
-  return valid ? fixed_of(a, s.e0) : (u128)0;
+  const double a = s.sxj[valid ? i : 0];
+  return valid ? fixed_of_col(a, s.e0) : (u128)0;
 }
 
 __device__ __forceinline__ void take_sample(bool c, int pri, uint64_t key, int t, int &bp, uint64_t &bk,
@@ -917,7 +917,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           const bool valid = key != KEY_NONE;
           const bool le_lo = valid && key <= plo;
           const bool inwin = valid && key > plo && key <= phi;
-          slo128 += le_lo ? fixed_of(fabs(a), s.e0) : (u128)0;
+          slo128 += le_lo ? fixed_of_col(a, s.e0) : (u128)0;
           const uint64_t wm = __ballot(inwin);
           const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
           nwin += __builtin_popcountll(wm);
@@ -958,7 +958,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           u128 a0 = 0, a1 = 0, a2 = 0;
           for (int e = lane; e < nwin; e += 64) {
             const uint64_t key = lk[e];
-            const u128 w = fixed_of(fabs(s.sxj[lr[e]]), s.e0);
+            const u128 w = fixed_of_col(s.sxj[lr[e]], s.e0);
             a0 += key < piv[0] ? w : (u128)0;
             a1 += key < piv[1] ? w : (u128)0;
             a2 += key < piv[2] ? w : (u128)0;
