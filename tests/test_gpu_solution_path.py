@@ -1,7 +1,8 @@
 """GPU parity of Algorithm 3 (l1line_solution_path) against the oracle's
 exact path: every record (lambda, j, k, v, row, E, P) bit for bit on small
 and mid-size inputs (the worked example, random and integer matrices with
-ties, duplicate and zero columns, one column, long columns, a 400 x 40
+ties, duplicate and zero columns, 70 equal columns (more than a wave of
+tied lines in a tile), one column, long columns, a 400 x 40
 workload whose breakpoints fill all 4096 lambda tiles), and on the
 2000 x 2000 workload the records checked where the oracle can score them one
 preserved coordinate at a time."""
@@ -50,6 +51,10 @@ def _cases():
     dup[:, 3] = dup[:, 8]
     zc = wl.random_small(1005, 15, 6, zero_frac=0.1)
     zc[:, 2] = 0.0
+    # 70 equal columns: their lines tie everywhere, so more than 64 lines
+    # survive the bounds of a tile
+    base = wl.random_small(1010, 30, 12)
+    many = np.asfortranarray(np.concatenate([np.repeat(base[:, :1], 70, axis=1), base[:, 1:]], axis=1))
     return {
         "toy": np.asfortranarray(np.array([[4, -2, 3, -6], [-3, 4, 2, -1], [2, 3, -3, -2], [-3, 4, 2, 3],
                                            [5, 3, 2, -1]], dtype=float)),
@@ -60,6 +65,7 @@ def _cases():
         "int_8x10_switches": wl.random_small(1003, 8, 10, integer=True, span=2),
         "random_12x12": wl.random_small(1004, 12, 12),
         "duplicate_columns": dup,
+        "seventy_equal_columns": many,
         "zero_column": zc,
         "one_column": wl.random_small(1006, 7, 1),
         "rank_one_exact": np.asfortranarray(np.outer(np.arange(1.0, 9.0), [1.0, -2.0, 0.5, 4.0])),
