@@ -78,7 +78,7 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
       }
       continue;
     }
-    const SegIO s{X + (long long)k * ld, X + (long long)j * ld, n, T, Tp, cj.e0, lane};
+    const SegIO s{X + (long long)k * ld, X + (long long)j * ld, n, T, Tp, cj.e0, lane, false};
     const int r0 = R0[g];
     const double v0 = V0[g];
     const uint64_t mkey = key_of(v0 + 0.0);
@@ -218,7 +218,7 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
     const ColInfo cj = ci[j];
     const int r0 = R0[g];
     if (r0 >= 0) {
-      const SegIO s{X + (long long)k * ld, X + (long long)j * ld, n, T, Tp, cj.e0, lane};
+      const SegIO s{X + (long long)k * ld, X + (long long)j * ld, n, T, Tp, cj.e0, lane, false};
       const u128 W = cj.wfix;
       const bool neg = V0[g] < 0.0;
       long long emitted = 0;

@@ -150,15 +150,21 @@ k_colprep_batch(const ProbDesc *__restrict__ P, const int *__restrict__ colstart
 // the register count low and the occupancy high.
 struct SegIO {
   const double *__restrict__ xk;   // column k (device memory)
-  const double *__restrict__ sxj;  // column j (LDS)
+  const double *__restrict__ sxj;  // column j (LDS when lds, else device memory)
   int n, T, Tp, e0, lane;          // rows, slots, pow2 >= T, fixed-point exponent
+  bool lds;                        // a compile-time constant at every construction
 };
+
+// x_ij of row i, through the address space column j lives in
+__device__ __forceinline__ double sxj_at(const SegIO &s, int i) {
+  return s.lds ? s.sxj[i] : gld(s.sxj + i);
+}
 
 // key of fl(x_ik / x_ij) + 0.0; KEY_NONE outside the matrix or where x_ij = 0
 __device__ __forceinline__ uint64_t seg_key(const SegIO &s, int i) {
   const bool in = i < s.n;
   const int ic = in ? i : 0;
-  const double a = s.sxj[ic], b = gld(s.xk + ic);
+  const double a = sxj_at(s, ic), b = gld(s.xk + ic);
   double r = b / a;
   r = r + 0.0;
   return (in && a != 0.0) ? key_of(r) : KEY_NONE;
@@ -176,7 +182,7 @@ __device__ __forceinline__ uint64_t key_of_pair(bool in, double a, double b) {
 
 // exact weight |x_ij| / 2^e0 of row i, 0 where !valid
 __device__ __forceinline__ u128 seg_weight(const SegIO &s, int i, bool valid) {
-  const double a = s.sxj[valid ? i : 0];
+  const double a = sxj_at(s, valid ? i : 0);
   return valid ? fixed_of_col(a, s.e0) : (u128)0;
 }
 
@@ -308,7 +314,7 @@ __device__ __forceinline__ void wave_select_rounds(const SegIO &s, const Src &sr
     }
     uint64_t plo, phi;
     if (!bisect) {
-      double sw = (sk != KEY_NONE) ? fabs(s.sxj[sr]) : 0.0;
+      double sw = (sk != KEY_NONE) ? fabs(sxj_at(s, sr)) : 0.0;
       wave_sort_key_dbl(sk, sw, lane);
       const double cw = wave_incl_scan_dbl(sw, lane);
       const double tot = __shfl(cw, 63);
@@ -502,7 +508,7 @@ __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
     const int i = s.lane + 64 * t;
     const bool in = i < s.n;
     const int ic = in ? i : 0;
-    const double prod = v * s.sxj[ic];
+    const double prod = v * sxj_at(s, ic);
     const double d = gld(s.xk + ic) - prod;
     p = p + (in ? fabs(d) : 0.0);
   }
@@ -791,7 +797,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       continue;
     }
     const ColInfo ck = ci[k];
-    const SegIO s{X + (long long)k * ld, sxj, n, T, Tp, cj.e0, lane};
+    const SegIO s{X + (long long)k * ld, sxj, n, T, Tp, cj.e0, lane, kLdsJ};
     const double Wk = ck.W;
 
     // 1. sign sums.  |x_ik / x_ij| can underflow to 0 only if the exponent
@@ -904,13 +910,13 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         int nwin = 0;
         // columns j and k are read one slot ahead so the loads overlap the
         // divide; the weight reuses x_ij
-        double anext = s.sxj[lane < n ? lane : 0], bnext = gld(s.xk + (lane < n ? lane : 0));
+        double anext = sxj_at(s, lane < n ? lane : 0), bnext = gld(s.xk + (lane < n ? lane : 0));
         for (int tt = 0; tt < T; ++tt) {
           const int i = lane + 64 * tt;
           const double a = anext, b = bnext;
           const int i2 = i + 64 < n ? i + 64 : 0;
           if (tt + 1 < T) {
-            anext = s.sxj[i2];
+            anext = sxj_at(s, i2);
             bnext = gld(s.xk + i2);
           }
           const uint64_t key = key_of_pair(i < n, a, b);
@@ -958,7 +964,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           u128 a0 = 0, a1 = 0, a2 = 0;
           for (int e = lane; e < nwin; e += 64) {
             const uint64_t key = lk[e];
-            const u128 w = fixed_of_col(s.sxj[lr[e]], s.e0);
+            const u128 w = fixed_of_col(sxj_at(s, lr[e]), s.e0);
             a0 += key < piv[0] ? w : (u128)0;
             a1 += key < piv[1] ? w : (u128)0;
             a2 += key < piv[2] ? w : (u128)0;
