@@ -47,6 +47,39 @@ __device__ __forceinline__ double fixed_to_double(u128 x, int e0) {
   return ldexp((double)(uint64_t)q, e0 + shift);
 }
 
+// Segments (j, k) in tiles of ts x ts dealt to the 8 XCDs round robin (the
+// dispatcher places workgroups on XCDs round robin by blockIdx), so the 2 ts
+// columns a tile reads stay in one XCD's L2 while its waves work through the
+// tile.  Slot f of an XCD's sequence is tile x + 8 (f / ts^2), segment
+// f mod ts^2 of it.  Every tile belongs to the workgroups with blockIdx = its
+// index mod 8, so the grid must have at least 8 workgroups.
+struct XcdTiles {
+  int m, ts, nt, x;
+  long long ntiles, wx, nwx;
+  __device__ __forceinline__ XcdTiles(int m_, int ts_, int waves_per_block) : m(m_), ts(ts_) {
+    nt = (m + ts - 1) / ts;
+    ntiles = (long long)nt * nt;
+    x = blockIdx.x & 7;
+    const long long bx = blockIdx.x >> 3, nbx = (gridDim.x - x + 7) >> 3;
+    wx = bx * waves_per_block + (threadIdx.x >> 6);
+    nwx = nbx * waves_per_block;
+  }
+  // false past the end; g = -1 for a slot of a partial tile outside the matrix
+  __device__ __forceinline__ bool at(long long f, long long &g) const {
+    const long long per = (long long)ts * ts, r = f / per, t = x + 8 * r;
+    if (t >= ntiles) return false;
+    const int sl = (int)(f - r * per);
+    const int j = (int)(t / nt) * ts + sl / ts, k = (int)(t % nt) * ts + sl % ts;
+    g = (j < m && k < m) ? (long long)j * m + k : -1;
+    return true;
+  }
+};
+
+// tile edge for columns of n rows: 2 ts columns in about 2 MB
+__host__ __device__ constexpr int xcd_tile(int n) {
+  return (1 << 20) / (8 * n) > 64 ? 64 : ((1 << 20) / (8 * n) < 4 ? 4 : (1 << 20) / (8 * n));
+}
+
 // Is element (key, row) at or above the pair (lk, lr) in sorted order?
 __device__ __forceinline__ bool pair_ge(uint64_t key, int row, uint64_t lk, int lr) {
   return key > lk || (key == lk && row >= lr);
@@ -63,12 +96,15 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
            const double *__restrict__ V0, const int *__restrict__ R0, long long *__restrict__ counts,
            double *__restrict__ lmax) {
   const int lane = threadIdx.x & 63;
-  const long long nseg = (long long)m * m;
-  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+  const int ts = xcd_tile(n);
   const int T = (n + 63) >> 6;
   int Tp = 1;
   while (Tp < T) Tp <<= 1;
-  for (long long g = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < nseg; g += waves) {
+  const XcdTiles tl(m, ts, blockDim.x >> 6);
+  for (long long f = tl.wx;; f += tl.nwx) {
+    long long g;
+    if (!tl.at(f, g)) break;
+    if (g < 0) continue;
     const int j = (int)(g / m), k = (int)(g % m);
     const ColInfo cj = ci[j];
     if (j == k || cj.flags) {
@@ -207,11 +243,15 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
     }
     return;
   }
-  const long long waves = (long long)gridDim.x * BP_WAVES;
+  const int ts = xcd_tile(n);
   const int T = (n + 63) >> 6;
   int Tp = 1;
   while (Tp < T) Tp <<= 1;
-  for (long long g = (long long)blockIdx.x * BP_WAVES + wave; g < nseg; g += waves) {
+  const XcdTiles tl(m, ts, BP_WAVES);
+  for (long long f = tl.wx;; f += tl.nwx) {
+    long long g;
+    if (!tl.at(f, g)) break;
+    if (g < 0) continue;
     const long long base = offsets[g], cnt = offsets[g + 1] - base;
     if (cnt == 0) continue;
     const int j = (int)(g / m), k = (int)(g % m);

@@ -1283,7 +1283,7 @@ static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
   if (st) return st;
   const long long nseg = (long long)m * m;
-  const unsigned grid = (unsigned)std::max(1ll, std::min((nseg + 3) / 4, (long long)ctx->num_cu * 8));
+  const unsigned grid = (unsigned)std::max(8ll, std::min((nseg + 3) / 4, (long long)ctx->num_cu * 8));
   {
     ProfScope ps(ctx, s, "bp_count");
     hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
@@ -1399,7 +1399,7 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   BatchPtrs bp;
   st = run_batch(ctx, &p0, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
   if (st) return st;
-  const unsigned grid = (unsigned)std::max(1ll, std::min((mm + 3) / 4, (long long)ctx->num_cu * 8));
+  const unsigned grid = (unsigned)std::max(8ll, std::min((mm + 3) / 4, (long long)ctx->num_cu * 8));
   {
     ProfScope ps(ctx, s, "bp_count");
     hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,

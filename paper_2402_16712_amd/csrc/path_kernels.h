@@ -15,7 +15,7 @@
 //
 // Pipeline (one GPU, everything on the device):
 //   1. Algorithm 2's entries (bp_kernels.h).
-//   2. k_sp_resid: e for every entry, 16 entries per pass over the rows; the
+//   2. k_sp_resid: e for every entry, up to 16 entries per pass over the rows; the
 //      global maxima that fix the scales.
 //   3. k_sp_delta: each entry's change of (E, P) in fixed point.
 //   4. k_sp_sort: one workgroup per j sorts j's entries by breakpoint (stable
@@ -228,18 +228,60 @@ __device__ __forceinline__ uint64_t dbits(double x) { return (uint64_t)__double_
 __device__ __forceinline__ double dofbits(uint64_t b) { return __longlong_as_double((long long)b); }
 
 // ------------------------------------------------------------------ residuals
+// G entries of one segment scored in one pass over the rows: lane l sums
+// rows l, l + 64, ... in increasing order (the R64 partials), the rows of the
+// next slot loaded while this slot is scored; then the R64 tree per entry.
+template <int G>
+__device__ __forceinline__ void sp_score(const double *__restrict__ xj, const double *__restrict__ xk, int n, int lane,
+                                         const double *__restrict__ ev, long long t0, long long b,
+                                         double *__restrict__ ee, double &emax, double &vmax) {
+  double v[G], p[G];
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    v[r] = t0 + r < b ? ev[t0 + r] : 0.0;
+    p[r] = 0.0;
+  }
+  double xn = lane < n ? gld(xj + lane) : 0.0, yn = lane < n ? gld(xk + lane) : 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double x = xn, y = yn;
+    if (i + 64 < n) {
+      xn = gld(xj + i + 64);
+      yn = gld(xk + i + 64);
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const double prod = v[r] * x;
+      const double d = y - prod;
+      p[r] = p[r] + fabs(d);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const double e = __shfl(wave_r64_tree(p[r]), 0);
+    if (t0 + r < b) {
+      if (lane == 0) ee[t0 + r] = e;
+      emax = fmax(emax, e);
+      vmax = fmax(vmax, fabs(v[r]));
+    }
+  }
+}
+
 // One wave per segment g = j m + k: e_t = R64 over the rows of
 // |x_ik - fl(v_t x_ij)| for each entry (the order Algorithm 1 uses), the
 // largest |v| of the segment, and the global maxima of e, |v| and the
-// breakpoints (nonnegative doubles order as their bit patterns).
+// breakpoints (nonnegative doubles order as their bit patterns).  Entries in
+// groups of 16, the last group of 8 or 4 when that covers the rest; segments
+// in XCD tiles (at least 8 workgroups).
 __global__ void __launch_bounds__(256)
 k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long long *__restrict__ offsets,
            const double *__restrict__ elam, const double *__restrict__ ev, double *__restrict__ ee,
            double *__restrict__ segv, unsigned long long *__restrict__ gmax) {
   const int lane = threadIdx.x & 63;
-  const long long nseg = (long long)m * m;
-  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
-  for (long long g = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < nseg; g += waves) {
+  const XcdTiles tl(m, xcd_tile(n), blockDim.x >> 6);
+  for (long long f = tl.wx;; f += tl.nwx) {
+    long long g;
+    if (!tl.at(f, g)) break;
+    if (g < 0) continue;
     const int j = (int)(g / m), k = (int)(g % m);
     const long long a = offsets[g], b = offsets[g + 1];
     if (j == k || a == b) {
@@ -249,33 +291,10 @@ k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long 
     const double *__restrict__ xj = X + (long long)j * ld;
     const double *__restrict__ xk = X + (long long)k * ld;
     double emax = 0.0, vmax = 0.0;
-    for (long long t0 = a; t0 < b; t0 += SP_RG) {
-      double v[SP_RG], p[SP_RG];
-#pragma unroll
-      for (int r = 0; r < SP_RG; ++r) {
-        v[r] = t0 + r < b ? ev[t0 + r] : 0.0;
-        p[r] = 0.0;
-      }
-#pragma unroll 2
-      for (int i = lane; i < n; i += 64) {
-        const double x = xj[i], y = xk[i];
-#pragma unroll
-        for (int r = 0; r < SP_RG; ++r) {
-          const double prod = v[r] * x;
-          const double d = y - prod;
-          p[r] = p[r] + fabs(d);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < SP_RG; ++r) {
-        const double e = __shfl(wave_r64_tree(p[r]), 0);
-        if (t0 + r < b) {
-          if (lane == 0) ee[t0 + r] = e;
-          emax = fmax(emax, e);
-          vmax = fmax(vmax, fabs(v[r]));
-        }
-      }
-    }
+    long long t0 = a;
+    for (; b - t0 > 8; t0 += SP_RG) sp_score<SP_RG>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
+    if (b - t0 > 4) sp_score<8>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
+    else if (b - t0 > 0) sp_score<4>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
     if (lane == 0) {
       segv[g] = vmax;
       atomicMax(gmax + 0, (unsigned long long)dbits(emax));
