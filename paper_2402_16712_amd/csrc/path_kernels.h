@@ -278,6 +278,7 @@ k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long 
            double *__restrict__ segv, unsigned long long *__restrict__ gmax) {
   const int lane = threadIdx.x & 63;
   const XcdTiles tl(m, xcd_tile(n), blockDim.x >> 6);
+  double we = 0.0, wv = 0.0, wl = 0.0;   // the wave's maxima, one atomic each at the end
   for (long long f = tl.wx;; f += tl.nwx) {
     long long g;
     if (!tl.at(f, g)) break;
@@ -295,12 +296,15 @@ k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long 
     for (; b - t0 > 8; t0 += SP_RG) sp_score<SP_RG>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
     if (b - t0 > 4) sp_score<8>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
     else if (b - t0 > 0) sp_score<4>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
-    if (lane == 0) {
-      segv[g] = vmax;
-      atomicMax(gmax + 0, (unsigned long long)dbits(emax));
-      atomicMax(gmax + 1, (unsigned long long)dbits(vmax));
-      atomicMax(gmax + 2, (unsigned long long)dbits(elam[b - 1]));
-    }
+    if (lane == 0) segv[g] = vmax;
+    we = fmax(we, emax);
+    wv = fmax(wv, vmax);
+    wl = fmax(wl, elam[b - 1]);
+  }
+  if (lane == 0) {
+    atomicMax(gmax + 0, (unsigned long long)dbits(we));
+    atomicMax(gmax + 1, (unsigned long long)dbits(wv));
+    atomicMax(gmax + 2, (unsigned long long)dbits(wl));
   }
 }
 
