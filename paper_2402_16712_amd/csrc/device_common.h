@@ -84,6 +84,32 @@ __device__ __forceinline__ u128 fixed_of_col(double a, int e0) {
   return (((u128)hi) << 64) | lo;
 }
 
+// The same weight |a| / 2^e0 (a whole number) as three 37-bit chunks held
+// in doubles: |a| / 2^e0 = c2 2^74 + c1 2^37 + c0.  Scaling by powers of two,
+// floor and the fused remainders are exact.  With the column range check
+// (|a| / 2^e0 < 2^(124 - b), b the bit length of the column's nonzero count,
+// at most 15) every chunk sum over a column stays below 2^53, so FP64 adds of
+// chunks are exact in any order.
+__device__ __forceinline__ void weight_chunks(double a, int e0, double &c0, double &c1, double &c2) {
+  const double ws = ldexp(fabs(a), -e0);
+  c2 = floor(ws * 0x1p-74);
+  const double r = fma(-c2, 0x1p74, ws);
+  c1 = floor(r * 0x1p-37);
+  c0 = fma(-c1, 0x1p37, r);
+}
+
+// an exact whole double below 2^64 as an integer
+__device__ __forceinline__ uint64_t u64_of_whole(double v) {
+  const double hi = floor(v * 0x1p-32);
+  const double lo = fma(-hi, 0x1p32, v);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+// c2 2^74 + c1 2^37 + c0 for whole chunk sums below 2^53
+__device__ __forceinline__ u128 chunks_to_u128(double c0, double c1, double c2) {
+  return ((u128)u64_of_whole(c2) << 74) + ((u128)u64_of_whole(c1) << 37) + (u128)u64_of_whole(c0);
+}
+
 // floor(lambda / 2^e0), saturated at 2^126 (beyond every weight sum of a
 // column that passed the range check, so it acts as +infinity).
 __device__ __forceinline__ u128 lambda_fixed(double lam, int e0) {

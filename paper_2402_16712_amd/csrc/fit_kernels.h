@@ -906,7 +906,9 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 
         // exact pass: weight at or below the window; the window's elements
         // go to the LDS list (in row order)
-        u128 slo128 = 0;
+        // the weight below the window in three FP64 sums of 37-bit chunks
+        // (whole numbers below 2^53: every add is exact)
+        double c0s = 0.0, c1s = 0.0, c2s = 0.0;
         int nwin = 0;
         // columns j and k are read one slot ahead so the loads overlap the
         // divide; the weight reuses x_ij
@@ -923,7 +925,13 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           const bool valid = key != KEY_NONE;
           const bool le_lo = valid && key <= plo;
           const bool inwin = valid && key > plo && key <= phi;
-          slo128 += le_lo ? fixed_of_col(a, s.e0) : (u128)0;
+          {
+            double c0, c1, c2;
+            weight_chunks(a, s.e0, c0, c1, c2);
+            c0s = c0s + (le_lo ? c0 : 0.0);
+            c1s = c1s + (le_lo ? c1 : 0.0);
+            c2s = c2s + (le_lo ? c2 : 0.0);
+          }
           const uint64_t wm = __ballot(inwin);
           const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
           nwin += __builtin_popcountll(wm);
@@ -932,7 +940,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             lr[pos] = (unsigned short)i;
           }
         }
-        const u128 Slw = wave_sum_u128(slo128);
+        const u128 Slw = chunks_to_u128(wave_sum_dbl(c0s), wave_sum_dbl(c1s), wave_sum_dbl(c2s));
         nwin = uni_int(nwin);
         wave_lds_sync();
         if (nwin > lcap) {
