@@ -502,15 +502,25 @@ __device__ __forceinline__ void wave_resolve(const SegIO &s, const uint64_t *lk,
 
 // e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0)
 __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
+  // column k in batches of RB loads issued back to back (the sum is still
+  // taken slot by slot in increasing order)
+  constexpr int RB = 8;
   double p = 0.0;
-#pragma unroll 8
-  for (int t = 0; t < s.T; ++t) {
-    const int i = s.lane + 64 * t;
-    const bool in = i < s.n;
-    const int ic = in ? i : 0;
-    const double prod = v * sxj_at(s, ic);
-    const double d = gld(s.xk + ic) - prod;
-    p = p + (in ? fabs(d) : 0.0);
+  for (int t0 = 0; t0 < s.T; t0 += RB) {
+    double xk[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i = s.lane + 64 * (t0 + r);
+      xk[r] = gld(s.xk + (i < s.n ? i : 0));
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i = s.lane + 64 * (t0 + r);
+      const bool in = i < s.n;
+      const double prod = v * sxj_at(s, in ? i : 0);
+      const double d = xk[r] - prod;
+      p = p + (in ? fabs(d) : 0.0);
+    }
   }
   return wave_r64_tree(p);
 }
