@@ -547,6 +547,70 @@ __device__ __forceinline__ void wave_sort2(uint64_t &a, uint64_t &b, int lane) {
   }
 }
 
+// Bitonic sort of 128 (key, row) pairs held two per lane (element
+// 2 lane + r), ascending in (key, row).
+__device__ __forceinline__ void wave_sort2_kr(uint64_t &ka, int &ra, uint64_t &kb, int &rb, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const bool up = ((2 * lane) & size) == 0;
+      if (stride == 1) {
+        const bool sw = (kb < ka || (kb == ka && rb < ra)) == up;
+        const uint64_t tk = ka;
+        const int tr = ra;
+        ka = sw ? kb : ka;
+        ra = sw ? rb : ra;
+        kb = sw ? tk : kb;
+        rb = sw ? tr : rb;
+      } else {
+        const int ls = stride >> 1;
+        const bool keep_min = (((2 * lane) & stride) == 0) == up;
+        const uint64_t oka = shfl_xor_u64(ka, ls), okb = shfl_xor_u64(kb, ls);
+        const int ora = __shfl_xor(ra, ls), orb = __shfl_xor(rb, ls);
+        const bool la = oka < ka || (oka == ka && ora < ra), lb = okb < kb || (okb == kb && orb < rb);
+        if (la == keep_min) {
+          ka = oka;
+          ra = ora;
+        }
+        if (lb == keep_min) {
+          kb = okb;
+          rb = orb;
+        }
+      }
+    }
+  }
+}
+
+// Sorts the window list lk/lr[0, nlist) ascending in (key, row) and pads it
+// with (KEY_NONE, 0xFFFF) to N = the returned power of two (>= 64).  Lists of
+// up to 128 are sorted in registers (shuffles, no LDS round trips per stage)
+// and written back; longer ones by the LDS network.
+__device__ __forceinline__ int wave_sort_list(uint64_t *lk, unsigned short *lr, int nlist, int lane) {
+  if (nlist > 128) return wave_sort_lds(lk, lr, nlist, lane);
+  if (nlist <= 64) {
+    uint64_t k = lane < nlist ? lk[lane] : KEY_NONE;
+    int r = lane < nlist ? (int)lr[lane] : 0xFFFF;
+    wave_sort_key_row(k, r, lane);
+    wave_lds_sync();
+    lk[lane] = k;
+    lr[lane] = (unsigned short)r;
+    wave_lds_sync();
+    return 64;
+  }
+  const int e = 2 * lane;
+  uint64_t ka = e < nlist ? lk[e] : KEY_NONE, kb = e + 1 < nlist ? lk[e + 1] : KEY_NONE;
+  int ra = e < nlist ? (int)lr[e] : 0xFFFF, rb = e + 1 < nlist ? (int)lr[e + 1] : 0xFFFF;
+  wave_sort2_kr(ka, ra, kb, rb, lane);
+  wave_lds_sync();
+  lk[e] = ka;
+  lr[e] = (unsigned short)ra;
+  lk[e + 1] = kb;
+  lr[e + 1] = (unsigned short)rb;
+  wave_lds_sync();
+  return 128;
+}
+
 // --------------------------------------------------------------- sign sums
 // For the pair (j, k) the ratio of row i, x_ik / x_ij, is positive, negative
 // or zero with the signs of x_ik and x_ij (barring underflow, checked per
@@ -1013,7 +1077,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           nwin = uni_int(kept);
           wave_lds_sync();
         }
-        const int N = wave_sort_lds(lk, lr, nwin, lane);
+        const int N = wave_sort_list(lk, lr, nwin, lane);
         u128 tot, incl;
         wave_list_sums(s, lk, lr, N >> 6, tot, incl);
         uint64_t k2 = KEY_NONE;
