@@ -963,7 +963,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           wlo = whi = __shfl(q, t);
           mine = lane == t;
         }
-        constexpr double WDELTA = 0.12;
+        constexpr double WDELTA = 0.08;
         const int ilo = (int)floor((wlo - WDELTA) * SAMPLE_ROWS) - 1;
         const int ihi = (int)ceil((whi + WDELTA) * SAMPLE_ROWS);
         uint64_t plo = klo0, phi = khi0;
@@ -1037,7 +1037,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           uint64_t piv[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            int ix = (int)floor((wlo + 0.06 * (c - 1)) * SAMPLE_ROWS);
+            int ix = (int)floor((wlo + 0.04 * (c - 1)) * SAMPLE_ROWS);
             ix = ix < 0 ? 0 : (ix >= SAMPLE_ROWS ? SAMPLE_ROWS - 1 : ix);
             piv[c] = uni_u64(shfl_u64((ix & 1) ? sb : sa, ix >> 1));
           }
