@@ -31,6 +31,11 @@ __device__ __forceinline__ double gld(const double *p) {
   return *(const __attribute__((address_space(1))) double *)p;
 }
 
+// number of set bits of the wave mask m in lanes below this one
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // ---------------------------------------------------------------- fixed point
 // A finite nonzero |x| is M * 2^E with M < 2^53 (E = -1074 for subnormals).
 __device__ __forceinline__ void dbl_parts(double a, uint64_t &M, int &E) {

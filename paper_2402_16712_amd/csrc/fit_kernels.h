@@ -1007,7 +1007,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             c2s = c2s + (le_lo ? c2 : 0.0);
           }
           const uint64_t wm = __ballot(inwin);
-          const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
+          const int pos = nwin + lanes_below(wm);
           nwin += __builtin_popcountll(wm);
           if (inwin && pos < lcap) {
             lk[pos] = key;
@@ -1067,7 +1067,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             const unsigned short row = in ? lr[e] : 0;
             const bool keep = in && (c == 0 || key >= plo2) && (c == 3 || key < phi2);
             const uint64_t km = __ballot(keep);
-            const int d = kept + __builtin_popcountll(km & ((1ull << lane) - 1ull));
+            const int d = kept + lanes_below(km);
             kept += __builtin_popcountll(km);
             if (keep) {
               lk[d] = key;
