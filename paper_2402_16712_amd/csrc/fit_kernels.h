@@ -525,6 +525,35 @@ __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
   return wave_r64_tree(p);
 }
 
+// G residuals in one pass over the rows (the same sums as wave_residual,
+// G at a time); e[r] is the wave's R64 sum for v[r].
+template <int G>
+__device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double *v, double *e) {
+  double p[G];
+#pragma unroll
+  for (int r = 0; r < G; ++r) p[r] = 0.0;
+  const int l0 = s.lane < s.n ? s.lane : 0;
+  double an = sxj_at(s, l0), bn = gld(s.xk + l0);
+  for (int t = 0; t < s.T; ++t) {
+    const int i = s.lane + 64 * t;
+    const bool in = i < s.n;
+    const double a = an, b = bn;
+    if (t + 1 < s.T) {
+      const int i2 = i + 64 < s.n ? i + 64 : 0;
+      an = sxj_at(s, i2);
+      bn = gld(s.xk + i2);
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const double prod = v[r] * a;
+      const double d = b - prod;
+      p[r] = p[r] + (in ? fabs(d) : 0.0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree(p[r]), 0);
+}
+
 // Bitonic sort of 128 keys held two per lane (element 2*lane + r), ascending.
 __device__ __forceinline__ void wave_sort2(uint64_t &a, uint64_t &b, int lane) {
 #pragma unroll
@@ -1116,32 +1145,62 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         }
       }
 
-      // residuals, reused while the selected row repeats
+      // residuals, reused while the selected row repeats: the group's targets
+      // whose row differs from the previous target's are the jobs, scored up
+      // to RJ at a time in one pass over the rows
       const int tend = min(L, 64 * g + 64);
-      for (int t = 64 * g; t < tend; ++t) {
-        uint64_t ok = KEY_NONE;
-        int orw = -1;
-        if ((nzg >> (t & 63)) & 1ull) {
-          ok = uni_u64(shfl_u64(okey, t & 63));
-          orw = uni_int(__shfl(orow, t & 63));
-        }
-        const double v = (orw >= 0) ? ratio_of_key(ok) : 0.0;
-        double e;
-        if (orw < 0) {
-          e = Wk;                                    // R64 sum of |x_ik|
-        } else if (orw == prev_row) {
-          e = prev_e;
-        } else {
-          e = __shfl(wave_residual(s, v), 0);
-        }
-        prev_row = orw;
-        prev_e = e;
-        if (lane == 0) {
-          V[t * mm + base] = v;
-          E[t * mm + base] = e;
-          R[t * mm + base] = orw;
+      const int cnt = tend - 64 * g;
+      int orw_l = -1;
+      double v_l = 0.0;
+      if (lane < cnt && ((nzg >> lane) & 1ull)) {
+        orw_l = orow;
+        v_l = ratio_of_key(okey);
+      }
+      int prv = __shfl_up(orw_l, 1);
+      if (lane == 0) prv = prev_row;
+      const bool need = lane < cnt && orw_l >= 0 && orw_l != prv;
+      const uint64_t needm = __ballot(need);
+      double e_l = 0.0;
+      if (__builtin_popcountll(needm) == 1) {
+        const int jl = __builtin_ctzll(needm);
+        const double e1 = __shfl(wave_residual(s, __shfl(v_l, jl)), 0);
+        if (lane == jl) e_l = e1;
+      } else {
+        constexpr int RJ = 4;
+        uint64_t jm = needm;
+        while (jm) {
+          int jl[RJ];
+          double jv[RJ], je[RJ];
+#pragma unroll
+          for (int r = 0; r < RJ; ++r) {
+            jl[r] = jm ? __builtin_ctzll(jm) : -1;
+            jm &= jm ? jm - 1 : 0;
+            jv[r] = jl[r] >= 0 ? __shfl(v_l, jl[r]) : 0.0;
+          }
+          wave_residual_multi<RJ>(s, jv, je);
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+            if (lane == jl[r]) e_l = je[r];
         }
       }
+      // each target takes the e of the last job at or before it (or the
+      // previous group's last e when its row continues from there)
+      double e_t;
+      if (orw_l < 0) {
+        e_t = Wk;                                    // R64 sum of |x_ik|
+      } else {
+        const uint64_t upto = needm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+        const double ej = __shfl(e_l, upto ? 63 - __builtin_clzll(upto) : 0);
+        e_t = upto ? ej : prev_e;
+      }
+      if (lane < cnt) {
+        const int t = 64 * g + lane;
+        V[t * mm + base] = orw_l >= 0 ? v_l : 0.0;
+        E[t * mm + base] = e_t;
+        R[t * mm + base] = orw_l;
+      }
+      prev_row = __shfl(orw_l, cnt - 1);
+      prev_e = __shfl(e_t, cnt - 1);
     }
   }
   if (err && lane == 0) atomicOr(segflags + j, err);
