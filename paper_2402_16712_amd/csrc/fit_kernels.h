@@ -809,7 +809,7 @@ __device__ __forceinline__ ExactSides exact_sides(const SegIO &s) {
 // One work item, by the whole workgroup (every thread calls it).  ci, V, E,
 // R and segflags are this problem's slices.  kLdsJ: column j is copied to LDS
 // (the pointer's address space is then known to the compiler: LDS loads).
-template <bool kLdsJ>
+template <bool kLdsJ, bool kMulti>
 __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, int m, long long ld,
                                          const ColInfo *__restrict__ ci, const double *__restrict__ lam, int L,
                                          const double2 *__restrict__ DZ, int j, int kbeg, int kend,
@@ -918,32 +918,68 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     // penalty of the segment.
     uint64_t nz0 = 0, nz1 = 0;                     // bit t: v_k != 0 at penalty t
     int sd = 0;
-    for (int t = 0; t < L; ++t) {
-      const double lamt = lam[t];
-      // decision margin 2^-32 (W + lambda): far above the rounding error of
-      // the sign sums (at most ~n 2^-52 of W, plus n 2^-1022 should the
-      // matrix unit flush subnormal terms: hence the floor on M)
-      const double M = 0x1p-32 * (Wd + lamt);
-      const double d1 = lamt + dz.y + dz.x;        // >= 0  <=>  2A <= W + lambda
-      const double d2 = lamt + dz.y - dz.x;        // >= 0  <=>  W <= 2B + lambda
-      int side;
-      if (unc || !(M >= 0x1p-1000)) side = 3;
-      else if (d1 > M && d2 > M) side = 0;
-      else if (d1 < -M) side = 1;
-      else if (d2 < -M) side = 2;
-      else side = 3;
-      if (side == 3) {
-        if (!have_exact) {
-          ex = exact_sides(s);
-          have_exact = true;
+    if constexpr (kMulti) {
+      // one penalty per lane, in groups of 64
+      for (int g0 = 0; g0 < L; g0 += 64) {
+        const int t = g0 + lane;
+        const bool in = t < L;
+        int side = 0;
+        if (in) {
+          const double lamt = lam[t];
+          // decision margin 2^-32 (W + lambda), as below
+          const double M = 0x1p-32 * (Wd + lamt);
+          const double d1 = lamt + dz.y + dz.x;
+          const double d2 = lamt + dz.y - dz.x;
+          if (unc || !(M >= 0x1p-1000)) side = 3;
+          else if (d1 > M && d2 > M) side = 0;
+          else if (d1 < -M) side = 1;
+          else if (d2 < -M) side = 2;
+          else side = 3;
         }
-        const u128 lamf = slam[t], WpL = W + lamf;
-        side = ((ex.A << 1) <= WpL && W <= (ex.B << 1) + lamf) ? 0 : ((ex.A << 1) > WpL ? 1 : 2);
+        if (__ballot(side == 3)) {
+          if (!have_exact) {
+            ex = exact_sides(s);
+            have_exact = true;
+          }
+          if (side == 3) {
+            const u128 lamf = slam[t], WpL = W + lamf;
+            side = ((ex.A << 1) <= WpL && W <= (ex.B << 1) + lamf) ? 0 : ((ex.A << 1) > WpL ? 1 : 2);
+          }
+        }
+        const uint64_t nzm = __ballot(side != 0);
+        if (g0 == 0) nz0 = nzm;
+        else nz1 = nzm;
+        // every nonzero penalty has the same side (A <= B)
+        if (nzm) sd = __shfl(side, __builtin_ctzll(nzm));
       }
-      if (side) {
-        sd = side;
-        if (t < 64) nz0 |= 1ull << t;
-        else nz1 |= 1ull << (t - 64);
+    } else {
+      for (int t = 0; t < L; ++t) {
+        const double lamt = lam[t];
+        // decision margin 2^-32 (W + lambda): far above the rounding error of
+        // the sign sums (at most ~n 2^-52 of W, plus n 2^-1022 should the
+        // matrix unit flush subnormal terms: hence the floor on M)
+        const double M = 0x1p-32 * (Wd + lamt);
+        const double d1 = lamt + dz.y + dz.x;        // >= 0  <=>  2A <= W + lambda
+        const double d2 = lamt + dz.y - dz.x;        // >= 0  <=>  W <= 2B + lambda
+        int side;
+        if (unc || !(M >= 0x1p-1000)) side = 3;
+        else if (d1 > M && d2 > M) side = 0;
+        else if (d1 < -M) side = 1;
+        else if (d2 < -M) side = 2;
+        else side = 3;
+        if (side == 3) {
+          if (!have_exact) {
+            ex = exact_sides(s);
+            have_exact = true;
+          }
+          const u128 lamf = slam[t], WpL = W + lamf;
+          side = ((ex.A << 1) <= WpL && W <= (ex.B << 1) + lamf) ? 0 : ((ex.A << 1) > WpL ? 1 : 2);
+        }
+        if (side) {
+          sd = side;
+          if (t < 64) nz0 |= 1ull << t;
+          else nz1 |= 1ull << (t - 64);
+        }
       }
     }
     if ((nz0 | nz1) == 0) {
@@ -1224,7 +1260,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
 // nothing unless *gate == gate_on.
 constexpr int SEG_XCDS = 8;
 
-template <bool kLdsJ>
+template <bool kLdsJ, bool kMulti>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, int nitems, int chunks,
             int *__restrict__ counter, const int *__restrict__ xstart, const double *__restrict__ lam_all,
@@ -1272,7 +1308,7 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
       if (it.kbeg >= it.kend) continue;            // an empty part of a narrow matrix
     }
     const ProbDesc d = P[it.b];
-    seg_item<kLdsJ>(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j,
+    seg_item<kLdsJ, kMulti>(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j,
                     it.kbeg, it.kend, V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap,
                     sxj_rows, smem);
   }

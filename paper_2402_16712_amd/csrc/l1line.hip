@@ -454,9 +454,13 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   const int lcap = (Ly.Lmax > 1 && seg_lds_bytes(sxj_rows, Ly.Lmax, PATH_CAP) <= lds_max) ? PATH_CAP : WIN_CAP;
   const size_t lds = seg_lds_bytes(sxj_rows, Ly.Lmax, lcap);
   if (!lds_attr_set) {
-    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_max));
-    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<false, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_max));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_max));
     lds_attr_set = true;
   }
@@ -490,7 +494,11 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   }
   {
     ProfScope ps(ctx, ls, "fit_seg");
-    hipLaunchKernelGGL(sxj_rows > 0 ? k_seg_batch<true> : k_seg_batch<false>, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
+    // single-penalty problems take the instantiation tuned for one target
+    const bool multi = Ly.Lmax > 1;
+    auto kseg = sxj_rows > 0 ? (multi ? k_seg_batch<true, true> : k_seg_batch<true, false>)
+                             : (multi ? k_seg_batch<false, true> : k_seg_batch<false, false>);
+    hipLaunchKernelGGL(kseg, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
                        Ly.nitems, Ly.ksplit, dcounter, dxstart, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand,
                        ro.ncand,
                        ro.gate, ro.gate_on, lcap, sxj_rows);
