@@ -119,22 +119,39 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
     const double v0 = V0[g];
     const uint64_t mkey = key_of(v0 + 0.0);
     const bool neg = v0 < 0.0;
-    u128 a128 = 0, z128 = 0;
+    // weights as FP64 sums of 37-bit chunks (exact, see weight_chunks);
+    // the columns are read one slot ahead
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
     int cnt = 0;
+    const int l0 = lane < n ? lane : 0;
+    double an = gld(s.sxj + l0), bn = gld(s.xk + l0);
     for (int t = 0; t < T; ++t) {
       const int i = lane + 64 * t;
-      const uint64_t key = seg_key(s, i);
+      const double a = an, b = bn;
+      if (t + 1 < T) {
+        const int i2 = i + 64 < n ? i + 64 : 0;
+        an = gld(s.sxj + i2);
+        bn = gld(s.xk + i2);
+      }
+      const uint64_t key = key_of_pair(i < n, a, b);
       const bool valid = key != KEY_NONE;
-      const u128 w = seg_weight(s, i, valid);
-      a128 += (valid && key < KEY_ZERO) ? w : (u128)0;
-      z128 += (valid && key == KEY_ZERO) ? w : (u128)0;
+      const bool ng = key < KEY_ZERO, zr = key == KEY_ZERO;
+      double c0, c1, c2;
+      weight_chunks(a, s.e0, c0, c1, c2);
+      a0 = a0 + (ng ? c0 : 0.0);
+      a1 = a1 + (ng ? c1 : 0.0);
+      a2 = a2 + (ng ? c2 : 0.0);
+      z0 = z0 + (zr ? c0 : 0.0);
+      z1 = z1 + (zr ? c1 : 0.0);
+      z2 = z2 + (zr ? c2 : 0.0);
       if (r0 >= 0 && valid) {
         const bool in = neg ? (key < KEY_ZERO && pair_ge(key, i, mkey, r0))
                             : (key > KEY_ZERO && pair_le(key, i, mkey, r0));
         cnt += in ? 1 : 0;
       }
     }
-    const u128 A = wave_sum_u128(a128), B = A + wave_sum_u128(z128), W = cj.wfix;
+    const u128 A = chunks_to_u128(wave_sum_dbl(a0), wave_sum_dbl(a1), wave_sum_dbl(a2)),
+               B = A + chunks_to_u128(wave_sum_dbl(z0), wave_sum_dbl(z1), wave_sum_dbl(z2)), W = cj.wfix;
     cnt = wave_sum_int(cnt);
     u128 lm = 0;
     if ((A << 1) > W) lm = (A << 1) - W;
