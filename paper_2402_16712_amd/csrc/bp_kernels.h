@@ -303,24 +303,38 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
         const uint64_t wk_lo = neg ? lo_k : w_lo, wk_hi = neg ? w_hi : hi_k;
         const int wr_lo = neg ? lo_r : (w_lo == lo_k ? lo_r : 0);
         const int wr_hi = neg ? (w_hi == hi_k ? hi_r : 0xFFFF) : hi_r;
-        u128 below = 0;
+        // (weights as FP64 sums of 37-bit chunks, see weight_chunks; the
+        // columns read one slot ahead)
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
         int nwin = 0;
+        const int l0 = lane < n ? lane : 0;
+        double an = gld(s.sxj + l0), bn = gld(s.xk + l0);
         for (int t = 0; t < T; ++t) {
           const int i = lane + 64 * t;
-          const uint64_t key = seg_key(s, i);
+          const double a = an, b = bn;
+          if (t + 1 < T) {
+            const int i2 = i + 64 < n ? i + 64 : 0;
+            an = gld(s.sxj + i2);
+            bn = gld(s.xk + i2);
+          }
+          const uint64_t key = key_of_pair(i < n, a, b);
           const bool valid = key != KEY_NONE;
           const bool lt = valid && !pair_ge(key, i, wk_lo, wr_lo);
           const bool in = valid && !lt && pair_le(key, i, wk_hi, wr_hi);
-          below += lt ? seg_weight(s, i, true) : (u128)0;
+          double c0, c1, c2;
+          weight_chunks(a, s.e0, c0, c1, c2);
+          b0 = b0 + (lt ? c0 : 0.0);
+          b1 = b1 + (lt ? c1 : 0.0);
+          b2 = b2 + (lt ? c2 : 0.0);
           const uint64_t wm = __ballot(in);
-          const int pos = nwin + __builtin_popcountll(wm & ((1ull << lane) - 1ull));
+          const int pos = nwin + lanes_below(wm);
           nwin += __builtin_popcountll(wm);
           if (in && pos < BP_CAP) {
             lk[pos] = key;
             lr[pos] = (unsigned short)i;
           }
         }
-        const u128 Sb = wave_sum_u128(below);
+        const u128 Sb = chunks_to_u128(wave_sum_dbl(b0), wave_sum_dbl(b1), wave_sum_dbl(b2));
         nwin = uni_int(nwin);
         wave_lds_sync();
         if (nwin > BP_CAP) {
@@ -364,7 +378,7 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
             continue;
           }
         } else {
-          const int N = wave_sort_lds(lk, lr, nwin, lane);
+          const int N = wave_sort_list(lk, lr, nwin, lane);
           const int E = N >> 6;
           u128 tot, incl;
           wave_list_sums(s, lk, lr, E, tot, incl);
