@@ -248,6 +248,7 @@ static uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
 }
 
 static bool lds_attr_set = false;
+static bool sp_sort_attr_set = false;
 
 // Optional restrictions of a one-problem run (device pointers): cand / ncand
 // restrict the preserved columns to a list, jmask marks them for the
@@ -1459,7 +1460,12 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   }
   {
     ProfScope ps(ctx, s, "sp_sort");
-    hipLaunchKernelGGL(k_sp_sort, dim3((unsigned)m), dim3(1024), 0, s, (int)m, (const long long *)offsets,
+    if (!sp_sort_attr_set) {
+      HIP_TRY(hipFuncSetAttribute((const void *)k_sp_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)SP_SORT_LDS));
+      sp_sort_attr_set = true;
+    }
+    hipLaunchKernelGGL(k_sp_sort, dim3((unsigned)m), dim3(1024), SP_SORT_LDS, s, (int)m, (const long long *)offsets,
                        (const double *)elam, keyA, idA, keyB, idB, (const u128 *)dE, (const u128 *)dP,
                        (const PathScale *)sc, stE, stP);
   }

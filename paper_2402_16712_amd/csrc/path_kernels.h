@@ -19,8 +19,9 @@
 //      global maxima that fix the scales.
 //   3. k_sp_delta: each entry's change of (E, P) in fixed point.
 //   4. k_sp_sort: one workgroup per j sorts j's entries by breakpoint (stable
-//      LSD radix over the key bits, in global memory) and scans the changes
-//      into the exact line after every entry.
+//      LSD radix over the key bytes, tiles ranked and laid out by digit in
+//      LDS before coalesced stores) and scans the changes into the exact
+//      line after every entry.
 //   5. k_sp_tiles: lambda tiles at quantiles of a sample of the breakpoints.
 //   6. k_sp_slack, k_sp_bounds, k_sp_surv: per (tile, j) a lower bound of
 //      z_j and per tile an upper bound of z*; a j whose lower bound exceeds
@@ -352,125 +353,225 @@ k_sp_delta(int m, const long long *__restrict__ offsets, const double *__restric
 // [offsets[j m], offsets[j m + m]) sorted by breakpoint, stably (ties keep
 // the (k, t) order), then the exact line after every entry:
 // stE/stP[s] = (0, 1) + the changes of sorted entries 0..s.
-__global__ void __launch_bounds__(1024)
+//
+// The sort is a least-significant-digit radix over the 8 bytes of the key
+// (the bits of a nonnegative double order like the double). One read of the
+// breakpoints counts all 8 digits; a pass whose digit is the same for every
+// entry is skipped. A pass takes tiles of SP_SORT_TILE entries: each wave
+// ranks its 256 entries by digit (64 at a time, in index order), the tile is
+// laid out digit by digit in LDS, and then written out in runs, so
+// consecutive lanes store to consecutive addresses of a digit's range.
+constexpr int SP_SORT_TILE = 4096;
+struct SpSortLds {
+  uint64_t key[SP_SORT_TILE];
+  uint32_t id[SP_SORT_TILE];
+  unsigned wcnt[16][256];   // per wave: running count, then start within its digit
+  unsigned gb[8][256];      // per pass: count, then next output index of each digit
+  unsigned tb[256];         // tile: first LDS index of each digit
+  unsigned tc[256];         // tile: entries of each digit
+  int nrun;                 // passes that move entries
+  int run[8];
+  u128 wt[16];             // wave totals of a tile's changes
+  u128 wp[16];             // their exclusive prefix
+  u128 tt;                 // tile total
+};
+constexpr size_t SP_SORT_LDS = sizeof(SpSortLds);
+
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_sp_sort(int m, const long long *__restrict__ offsets, const double *__restrict__ elam, uint64_t *__restrict__ keyA,
           uint32_t *__restrict__ idA, uint64_t *__restrict__ keyB, uint32_t *__restrict__ idB,
           const u128 *__restrict__ dE, const u128 *__restrict__ dP, const PathScale *__restrict__ sc,
           u128 *__restrict__ stE, u128 *__restrict__ stP) {
-  __shared__ unsigned hist[256], base[256];
-  __shared__ unsigned wcnt[16][256];
-  __shared__ int skip;
-  __shared__ u128 wtE[16], wtP[16];
+  extern __shared__ __attribute__((aligned(16))) unsigned char sp_smem[];
+  SpSortLds &L = *reinterpret_cast<SpSortLds *>(sp_smem);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int j = blockIdx.x;
   const long long a = offsets[(long long)j * m], N = offsets[(long long)j * m + m] - a;
+  for (int q = tid; q < 8 * 256; q += 1024) L.gb[q >> 8][q & 255] = 0;
+  __syncthreads();
   for (long long s = tid; s < N; s += 1024) {
-    keyA[a + s] = dbits(elam[a + s]);
-    idA[a + s] = (uint32_t)(a + s);
-  }
-  uint64_t *kin = keyA, *kout = keyB;
-  uint32_t *iin = idA, *iout = idB;
-  for (int pass = 0; pass < 8; ++pass) {
-    const int sh = 8 * pass;
-    __syncthreads();
-    if (tid < 256) hist[tid] = 0;
-    for (int q = tid; q < 16 * 256; q += 1024) wcnt[q >> 8][q & 255] = 0;
-    if (tid == 0) skip = 0;
-    __syncthreads();
-    for (long long s = tid; s < N; s += 1024) atomicAdd(&hist[(kin[a + s] >> sh) & 255], 1u);
-    __syncthreads();
-    if (tid < 256 && (long long)hist[tid] == N) skip = 1;
-    if (tid < 64) {
-      unsigned c[4], t = 0;
-      for (int r = 0; r < 4; ++r) {
-        c[r] = hist[4 * tid + r];
-        t += c[r];
-      }
-      unsigned run = (unsigned)wave_excl_scan_int((int)t, lane);
-      for (int r = 0; r < 4; ++r) {
-        base[4 * tid + r] = run;
-        run += c[r];
-      }
-    }
-    __syncthreads();
-    if (skip) continue;
-    for (long long t0 = 0; t0 < N; t0 += 1024) {
-      const long long s = t0 + tid;
-      const bool valid = s < N;
-      const uint64_t key = valid ? kin[a + s] : 0;
-      const uint32_t id = valid ? iin[a + s] : 0;
-      const int d = valid ? (int)((key >> sh) & 255) : 0;
-      uint64_t peers = __ballot(valid);
+    const uint64_t key = dbits(elam[a + s]);
 #pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
-        const uint64_t bb = __ballot((d >> bit) & 1);
-        peers &= ((d >> bit) & 1) ? bb : ~bb;
+    for (int p = 0; p < 8; ++p) atomicAdd(&L.gb[p][(key >> (8 * p)) & 255], 1u);
+  }
+  __syncthreads();
+  if (tid < 512) {
+    // wave p turns pass p's counts into first output indices
+    const int p = w;
+    unsigned c[4], t = 0;
+    bool one = false;
+    for (int r = 0; r < 4; ++r) {
+      c[r] = L.gb[p][4 * lane + r];
+      t += c[r];
+      one |= (long long)c[r] == N;
+    }
+    unsigned run = (unsigned)wave_excl_scan_int((int)t, lane);
+    for (int r = 0; r < 4; ++r) {
+      L.gb[p][4 * lane + r] = run;
+      run += c[r];
+    }
+    const bool skip = __ballot(one) != 0ull;
+    if (lane == 0) L.run[p] = skip ? 0 : 1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int c = 0;
+    for (int p = 0; p < 8; ++p)
+      if (L.run[p]) L.run[c++] = p;
+    L.nrun = c;
+  }
+  __syncthreads();
+  const int nrun = L.nrun;
+  if (nrun == 0) {
+    // every key the same: the index order is the sorted order
+    for (long long s = tid; s < N; s += 1024) {
+      keyA[a + s] = dbits(elam[a + s]);
+      idA[a + s] = (uint32_t)(a + s);
+    }
+  }
+  // the last moving pass writes keyA/idA
+  uint64_t *kout = (nrun & 1) ? keyA : keyB;
+  uint32_t *iout = (nrun & 1) ? idA : idB;
+  const uint64_t *kin = nullptr;
+  const uint32_t *iin = nullptr;
+  for (int ip = 0; ip < nrun; ++ip) {
+    const int p = L.run[ip], sh = 8 * p;
+    for (long long t0 = 0; t0 < N; t0 += SP_SORT_TILE) {
+      for (int r = 0; r < 4; ++r) L.wcnt[w][4 * lane + r] = 0;
+      const int tn = (int)min((long long)SP_SORT_TILE, N - t0);
+      uint64_t key[4];
+      uint32_t id[4];
+      if (ip == 0) {
+        const double *__restrict__ lb = elam + a + t0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = w * 256 + r * 64 + lane;
+          key[r] = e < tn ? dbits(lb[e]) : 0ull;
+          id[r] = (uint32_t)(a + t0) + (uint32_t)e;
+        }
+      } else {
+        const uint64_t *__restrict__ kb = kin + a + t0;
+        const uint32_t *__restrict__ ib = iin + a + t0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = w * 256 + r * 64 + lane;
+          key[r] = e < tn ? kb[e] : 0ull;
+          id[r] = e < tn ? ib[e] : 0u;
+        }
       }
-      const int rank = __builtin_popcountll(peers & ((1ull << lane) - 1ull));
-      if (valid && rank == 0) wcnt[w][d] = (unsigned)__builtin_popcountll(peers);
-      __syncthreads();
-      if (valid) {
-        unsigned off = base[d];
-        for (int q = 0; q < w; ++q) off += wcnt[q][d];
-        kout[a + off + rank] = key;
-        iout[a + off + rank] = id;
+      // (digit << 16) | rank within the wave's digit, all ones past the end
+      unsigned pk[4];
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool valid = w * 256 + r * 64 + lane < tn;
+        const int d = (int)((key[r] >> sh) & 255);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+          const uint64_t bb = __ballot((d >> bit) & 1);
+          peers &= ((d >> bit) & 1) ? bb : ~bb;
+        }
+        const int rank = lanes_below(peers);
+        const unsigned off = L.wcnt[w][d];
+        pk[r] = valid ? ((unsigned)d << 16) | (off + (unsigned)rank) : ~0u;
+        wave_lds_sync();
+        if (valid && rank == 0) L.wcnt[w][d] = off + (unsigned)__builtin_popcountll(peers);
+        wave_lds_sync();
       }
       __syncthreads();
       if (tid < 256) {
-        unsigned add = 0;
+        unsigned run = 0;
         for (int q = 0; q < 16; ++q) {
-          add += wcnt[q][tid];
-          wcnt[q][tid] = 0;
+          const unsigned c = L.wcnt[q][tid];
+          L.wcnt[q][tid] = run;
+          run += c;
         }
-        base[tid] += add;
+        L.tc[tid] = run;
       }
       __syncthreads();
+      if (tid < 64) {
+        unsigned c[4], t = 0;
+        for (int r = 0; r < 4; ++r) {
+          c[r] = L.tc[4 * lane + r];
+          t += c[r];
+        }
+        unsigned run = (unsigned)wave_excl_scan_int((int)t, lane);
+        for (int r = 0; r < 4; ++r) {
+          L.tb[4 * lane + r] = run;
+          run += c[r];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (pk[r] != ~0u) {
+          const int d = (int)(pk[r] >> 16);
+          const unsigned pos = L.tb[d] + L.wcnt[w][d] + (pk[r] & 0xffffu);
+          L.key[pos] = key[r];
+          L.id[pos] = id[r];
+        }
+      }
+      __syncthreads();
+      uint64_t *__restrict__ ko = kout + a;
+      uint32_t *__restrict__ io = iout + a;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = r * 1024 + tid;
+        if (q < tn) {
+          const uint64_t k = L.key[q];
+          const int d = (int)((k >> sh) & 255);
+          const unsigned dst = L.gb[p][d] + (unsigned)q - L.tb[d];
+          ko[dst] = k;
+          io[dst] = L.id[q];
+        }
+      }
+      __syncthreads();
+      if (tid < 256) L.gb[p][tid] += L.tc[tid];
     }
-    uint64_t *tk = kin;
+    // this pass's output is the next one's input; the buffers alternate
+    // so that the last pass ends in keyA/idA
+    __syncthreads();
     kin = kout;
-    kout = tk;
-    uint32_t *ti = iin;
     iin = iout;
-    iout = ti;
+    kout = (kout == keyA) ? keyB : keyA;
+    iout = (iout == idA) ? idB : idA;
   }
   __syncthreads();
-  if (kin != keyA) {
-    for (long long s = tid; s < N; s += 1024) {
-      keyA[a + s] = kin[a + s];
-      idA[a + s] = iin[a + s];
-    }
-    __syncthreads();
-  }
-  // exact lines in sorted order
-  u128 cE = 0, cP = fixed_of(1.0, sc->sP);
-  for (long long t0 = 0; t0 < N; t0 += 1024) {
-    const long long s = t0 + tid;
-    const bool valid = s < N;
-    const uint32_t id = valid ? idA[a + s] : 0;
-    u128 x = valid ? dE[id] : (u128)0, y = valid ? dP[id] : (u128)0;
-    x = wave_incl_scan_u128(x, lane);
-    y = wave_incl_scan_u128(y, lane);
-    if (lane == 63) {
-      wtE[w] = x;
-      wtP[w] = y;
-    }
-    __syncthreads();
-    u128 px = 0, py = 0, tx = 0, ty = 0;
-    for (int q = 0; q < 16; ++q) {
-      if (q < w) {
-        px += wtE[q];
-        py += wtP[q];
+  // exact lines in sorted order: 4 consecutive entries per lane, then the
+  // lanes, then the 16 waves of a tile; the value E and the slope P one
+  // after the other
+  for (int part = 0; part < 2; ++part) {
+    const u128 *__restrict__ dz = part ? dP : dE;
+    u128 *__restrict__ st = part ? stP : stE;
+    u128 c = part ? fixed_of(1.0, sc->sP) : (u128)0;
+    for (long long t0 = 0; t0 < N; t0 += SP_SORT_TILE) {
+      const long long s0 = t0 + 4 * tid;
+      u128 x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool valid = s0 + r < N;
+        const uint32_t id = valid ? idA[a + s0 + r] : 0u;
+        x[r] = valid ? dz[id] : (u128)0;
       }
-      tx += wtE[q];
-      ty += wtP[q];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) x[r] += x[r - 1];
+      const u128 ix = wave_incl_scan_u128(x[3], lane);
+      if (lane == 63) L.wt[w] = ix;
+      __syncthreads();
+      if (tid < 64) {
+        const u128 o = lane < 16 ? L.wt[lane] : (u128)0;
+        const u128 sx = wave_incl_scan_u128(o, lane);
+        if (lane < 16) L.wp[lane] = sx - o;
+        if (lane == 15) L.tt = sx;
+      }
+      __syncthreads();
+      const u128 b = c + L.wp[w] + (ix - x[3]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (s0 + r < N) st[a + s0 + r] = b + x[r];
+      c += L.tt;
     }
-    if (valid) {
-      stE[a + s] = cE + px + x;
-      stP[a + s] = cP + py + y;
-    }
-    cE += tx;
-    cP += ty;
-    __syncthreads();
   }
 }
 
