@@ -15,7 +15,8 @@
 //
 // Pipeline (one GPU, everything on the device):
 //   1. Algorithm 2's entries (bp_kernels.h).
-//   2. k_sp_resid: e for every entry, up to 16 entries per pass over the rows; the
+//   2. k_sp_resid: e for every entry, up to 16 entries per pass over the rows
+//      (columns through buffer loads, the 16 R64 trees folded together); the
 //      global maxima that fix the scales.
 //   3. k_sp_delta: each entry's change of (E, P) in fixed point.
 //   4. k_sp_sort: one workgroup per j sorts j's entries by breakpoint (stable
@@ -42,6 +43,9 @@
 
 constexpr int SP_TMAX = 4096;      // lambda tiles
 constexpr int SP_SAMPLES = 4096;   // breakpoints sampled to place them
+// word 3 of a raw buffer descriptor (32-bit data format, no swizzle): loads
+// past num_records return 0
+constexpr int SP_RSRC_WORD3 = 0x00020000;
 constexpr int SP_RG = 16;          // entries scored per pass over the rows
 
 struct PathScale {
@@ -232,8 +236,55 @@ __device__ __forceinline__ double dofbits(uint64_t b) { return __longlong_as_dou
 // G entries of one segment scored in one pass over the rows: lane l sums
 // rows l, l + 64, ... in increasing order (the R64 partials), the rows of the
 // next slot loaded while this slot is scored; then the R64 tree per entry.
+// One level of the R64 tree for K entries at once: the lanes below stride d
+// keep the first half of the entries, the others the second half, and each
+// adds its partner's value for the kept entry (lane l with lane l + d, the
+// pair the tree adds).  Half the shuffles of K separate trees.
+template <int K>
+__device__ __forceinline__ void sp_fold(double *v, int lane, int d) {
+  const bool up = (lane & d) != 0;
+#pragma unroll
+  for (int i = 0; i < K / 2; ++i) {
+    const double lo = v[i], hi = v[K / 2 + i];
+    const double keep = up ? hi : lo, send = up ? lo : hi;
+    const double recv = __shfl_xor(send, d);
+    v[i] = up ? recv + keep : keep + recv;
+  }
+}
+
+// R64 sums of G lane-partials at once: returns entry (lane >> (6 - log2 G))
+// mod G's sum in the lanes whose low 6 - log2 G bits are zero.
 template <int G>
-__device__ __forceinline__ void sp_score(const double *__restrict__ xj, const double *__restrict__ xk, int n, int lane,
+__device__ __forceinline__ double sp_tree(double (&p)[G], int lane) {
+  static_assert(G == 4 || G == 8 || G == 16, "group size");
+  constexpr int LG = G == 16 ? 4 : G == 8 ? 3 : 2;
+  sp_fold<G>(p, lane, 32);
+  sp_fold<G / 2>(p, lane, 16);
+  if constexpr (LG >= 3) sp_fold<G / 4>(p, lane, 8);
+  if constexpr (LG >= 4) sp_fold<G / 8>(p, lane, 4);
+  double x = p[0];
+#pragma unroll
+  for (int d = 32 >> LG; d >= 1; d >>= 1) {
+    const double o = __shfl_xor(x, d);
+    x = (lane & d) ? o + x : x + o;
+  }
+  return x;
+}
+
+// x[row] of a column through a buffer descriptor: rows past the column's
+// end read 0.
+__device__ __forceinline__ double sp_ld(__amdgpu_buffer_rsrc_t r, int off) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  double d;
+  __builtin_memcpy(&d, &u, sizeof d);
+  return d;
+}
+
+// Rows lane + 64 s for s < steps; a row past n reads 0 and adds
+// |0 - v 0| = +0, which leaves the lane's partial as it is.  The next row
+// step is loaded before the current one is used.
+template <int G>
+__device__ __forceinline__ void sp_score(__amdgpu_buffer_rsrc_t rj, __amdgpu_buffer_rsrc_t rk, int steps, int lane,
                                          const double *__restrict__ ev, long long t0, long long b,
                                          double *__restrict__ ee, double &emax, double &vmax) {
   double v[G], p[G];
@@ -242,28 +293,44 @@ __device__ __forceinline__ void sp_score(const double *__restrict__ xj, const do
     v[r] = t0 + r < b ? ev[t0 + r] : 0.0;
     p[r] = 0.0;
   }
-  double xn = lane < n ? gld(xj + lane) : 0.0, yn = lane < n ? gld(xk + lane) : 0.0;
-  for (int i = lane; i < n; i += 64) {
-    const double x = xn, y = yn;
-    if (i + 64 < n) {
-      xn = gld(xj + i + 64);
-      yn = gld(xk + i + 64);
-    }
+  int off = lane * 8;
+  double xa = sp_ld(rj, off), ya = sp_ld(rk, off);
+  int s = 0;
+  for (; s + 2 <= steps; s += 2) {
+    const double xb = sp_ld(rj, off + 512), yb = sp_ld(rk, off + 512);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
-      const double prod = v[r] * x;
-      const double d = y - prod;
+      const double prod = v[r] * xa;
+      const double d = ya - prod;
+      p[r] = p[r] + fabs(d);
+    }
+    off += 1024;
+    xa = sp_ld(rj, off);
+    ya = sp_ld(rk, off);
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const double prod = v[r] * xb;
+      const double d = yb - prod;
+      p[r] = p[r] + fabs(d);
+    }
+  }
+  if (s < steps) {
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const double prod = v[r] * xa;
+      const double d = ya - prod;
       p[r] = p[r] + fabs(d);
     }
   }
 #pragma unroll
-  for (int r = 0; r < G; ++r) {
-    const double e = __shfl(wave_r64_tree(p[r]), 0);
-    if (t0 + r < b) {
-      if (lane == 0) ee[t0 + r] = e;
-      emax = fmax(emax, e);
-      vmax = fmax(vmax, fabs(v[r]));
-    }
+  for (int r = 0; r < G; ++r)
+    if (t0 + r < b) vmax = fmax(vmax, fabs(v[r]));
+  constexpr int SH = G == 16 ? 2 : G == 8 ? 3 : 4;
+  const double e = sp_tree<G>(p, lane);
+  const int r = (lane >> SH) & (G - 1);
+  if ((lane & ((1 << SH) - 1)) == 0 && t0 + r < b) {
+    ee[t0 + r] = e;
+    emax = fmax(emax, e);
   }
 }
 
@@ -273,7 +340,7 @@ __device__ __forceinline__ void sp_score(const double *__restrict__ xj, const do
 // breakpoints (nonnegative doubles order as their bit patterns).  Entries in
 // groups of 16, the last group of 8 or 4 when that covers the rest; segments
 // in XCD tiles (at least 8 workgroups).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long long *__restrict__ offsets,
            const double *__restrict__ elam, const double *__restrict__ ev, double *__restrict__ ee,
            double *__restrict__ segv, unsigned long long *__restrict__ gmax) {
@@ -284,24 +351,34 @@ k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long 
     long long g;
     if (!tl.at(f, g)) break;
     if (g < 0) continue;
-    const int j = (int)(g / m), k = (int)(g % m);
+    // the segment is the same for the whole wave: its values go to scalar
+    // registers
+    const int j = __builtin_amdgcn_readfirstlane((int)(g / m)), k = __builtin_amdgcn_readfirstlane((int)(g % m));
+    g = (long long)j * m + k;
     const long long a = offsets[g], b = offsets[g + 1];
     if (j == k || a == b) {
       if (lane == 0) segv[g] = 0.0;
       continue;
     }
-    const double *__restrict__ xj = X + (long long)j * ld;
-    const double *__restrict__ xk = X + (long long)k * ld;
+    // n <= 16384 rows: n 8 bytes fits the descriptor's size field
+    const __amdgpu_buffer_rsrc_t rj = __builtin_amdgcn_make_buffer_rsrc((void *)(X + (long long)j * ld), (short)0,
+                                                                        n * 8, SP_RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc((void *)(X + (long long)k * ld), (short)0,
+                                                                        n * 8, SP_RSRC_WORD3);
+    const int steps = (n + 63) >> 6;
     double emax = 0.0, vmax = 0.0;
     long long t0 = a;
-    for (; b - t0 > 8; t0 += SP_RG) sp_score<SP_RG>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
-    if (b - t0 > 4) sp_score<8>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
-    else if (b - t0 > 0) sp_score<4>(xj, xk, n, lane, ev, t0, b, ee, emax, vmax);
+    for (; b - t0 > 8; t0 += SP_RG) sp_score<SP_RG>(rj, rk, steps, lane, ev, t0, b, ee, emax, vmax);
+    if (b - t0 > 4) sp_score<8>(rj, rk, steps, lane, ev, t0, b, ee, emax, vmax);
+    else if (b - t0 > 0) sp_score<4>(rj, rk, steps, lane, ev, t0, b, ee, emax, vmax);
     if (lane == 0) segv[g] = vmax;
     we = fmax(we, emax);
     wv = fmax(wv, vmax);
     wl = fmax(wl, elam[b - 1]);
   }
+  // e's maximum sits in the lanes that held the sums
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) we = fmax(we, __shfl_xor(we, d));
   if (lane == 0) {
     atomicMax(gmax + 0, (unsigned long long)dbits(we));
     atomicMax(gmax + 1, (unsigned long long)dbits(wv));
