@@ -80,6 +80,21 @@ __host__ __device__ constexpr int xcd_tile(int n) {
   return (1 << 20) / (8 * n) > 64 ? 64 : ((1 << 20) / (8 * n) < 4 ? 4 : (1 << 20) / (8 * n));
 }
 
+// A column through a raw buffer descriptor (word 3: 32-bit data format, no
+// swizzle); n <= 16384 rows, so n 8 bytes fits the size field.  Loads past
+// the column's end return 0, so a wave can run a uniform loop over row
+// steps with no bounds branch.
+constexpr int COL_RSRC_WORD3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const double *p, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, n * 8, COL_RSRC_WORD3);
+}
+__device__ __forceinline__ double col_ld(__amdgpu_buffer_rsrc_t r, int off) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  double d;
+  __builtin_memcpy(&d, &u, sizeof d);
+  return d;
+}
+
 // Is element (key, row) at or above the pair (lk, lr) in sorted order?
 __device__ __forceinline__ bool pair_ge(uint64_t key, int row, uint64_t lk, int lr) {
   return key > lk || (key == lk && row >= lr);
@@ -105,7 +120,9 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
     long long g;
     if (!tl.at(f, g)) break;
     if (g < 0) continue;
-    const int j = (int)(g / m), k = (int)(g % m);
+    // the segment is the same for the whole wave (scalar registers)
+    const int j = __builtin_amdgcn_readfirstlane((int)(g / m)), k = __builtin_amdgcn_readfirstlane((int)(g % m));
+    g = (long long)j * m + k;
     const ColInfo cj = ci[j];
     if (j == k || cj.flags) {
       if (lane == 0) {
@@ -123,16 +140,15 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
     // the columns are read one slot ahead
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
     int cnt = 0;
-    const int l0 = lane < n ? lane : 0;
-    double an = gld(s.sxj + l0), bn = gld(s.xk + l0);
+    const __amdgpu_buffer_rsrc_t rj = col_rsrc(s.sxj, n), rk = col_rsrc(s.xk, n);
+    int off = lane * 8;
+    double an = col_ld(rj, off), bn = col_ld(rk, off);
     for (int t = 0; t < T; ++t) {
       const int i = lane + 64 * t;
       const double a = an, b = bn;
-      if (t + 1 < T) {
-        const int i2 = i + 64 < n ? i + 64 : 0;
-        an = gld(s.sxj + i2);
-        bn = gld(s.xk + i2);
-      }
+      off += 512;
+      an = col_ld(rj, off);
+      bn = col_ld(rk, off);
       const uint64_t key = key_of_pair(i < n, a, b);
       const bool valid = key != KEY_NONE;
       const bool ng = key < KEY_ZERO, zr = key == KEY_ZERO;
@@ -269,9 +285,11 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
     long long g;
     if (!tl.at(f, g)) break;
     if (g < 0) continue;
+    // the segment is the same for the whole wave (scalar registers)
+    const int j = __builtin_amdgcn_readfirstlane((int)(g / m)), k = __builtin_amdgcn_readfirstlane((int)(g % m));
+    g = (long long)j * m + k;
     const long long base = offsets[g], cnt = offsets[g + 1] - base;
     if (cnt == 0) continue;
-    const int j = (int)(g / m), k = (int)(g % m);
     const ColInfo cj = ci[j];
     const int r0 = R0[g];
     if (r0 >= 0) {
@@ -307,16 +325,15 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
         // columns read one slot ahead)
         double b0 = 0.0, b1 = 0.0, b2 = 0.0;
         int nwin = 0;
-        const int l0 = lane < n ? lane : 0;
-        double an = gld(s.sxj + l0), bn = gld(s.xk + l0);
+        const __amdgpu_buffer_rsrc_t rj = col_rsrc(s.sxj, n), rk = col_rsrc(s.xk, n);
+        int off = lane * 8;
+        double an = col_ld(rj, off), bn = col_ld(rk, off);
         for (int t = 0; t < T; ++t) {
           const int i = lane + 64 * t;
           const double a = an, b = bn;
-          if (t + 1 < T) {
-            const int i2 = i + 64 < n ? i + 64 : 0;
-            an = gld(s.sxj + i2);
-            bn = gld(s.xk + i2);
-          }
+          off += 512;
+          an = col_ld(rj, off);
+          bn = col_ld(rk, off);
           const uint64_t key = key_of_pair(i < n, a, b);
           const bool valid = key != KEY_NONE;
           const bool lt = valid && !pair_ge(key, i, wk_lo, wr_lo);

@@ -43,9 +43,6 @@
 
 constexpr int SP_TMAX = 4096;      // lambda tiles
 constexpr int SP_SAMPLES = 4096;   // breakpoints sampled to place them
-// word 3 of a raw buffer descriptor (32-bit data format, no swizzle): loads
-// past num_records return 0
-constexpr int SP_RSRC_WORD3 = 0x00020000;
 constexpr int SP_RG = 16;          // entries scored per pass over the rows
 
 struct PathScale {
@@ -271,15 +268,6 @@ __device__ __forceinline__ double sp_tree(double (&p)[G], int lane) {
   return x;
 }
 
-// x[row] of a column through a buffer descriptor: rows past the column's
-// end read 0.
-__device__ __forceinline__ double sp_ld(__amdgpu_buffer_rsrc_t r, int off) {
-  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-  double d;
-  __builtin_memcpy(&d, &u, sizeof d);
-  return d;
-}
-
 // Rows lane + 64 s for s < steps; a row past n reads 0 and adds
 // |0 - v 0| = +0, which leaves the lane's partial as it is.  The next row
 // step is loaded before the current one is used.
@@ -294,10 +282,10 @@ __device__ __forceinline__ void sp_score(__amdgpu_buffer_rsrc_t rj, __amdgpu_buf
     p[r] = 0.0;
   }
   int off = lane * 8;
-  double xa = sp_ld(rj, off), ya = sp_ld(rk, off);
+  double xa = col_ld(rj, off), ya = col_ld(rk, off);
   int s = 0;
   for (; s + 2 <= steps; s += 2) {
-    const double xb = sp_ld(rj, off + 512), yb = sp_ld(rk, off + 512);
+    const double xb = col_ld(rj, off + 512), yb = col_ld(rk, off + 512);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const double prod = v[r] * xa;
@@ -305,8 +293,8 @@ __device__ __forceinline__ void sp_score(__amdgpu_buffer_rsrc_t rj, __amdgpu_buf
       p[r] = p[r] + fabs(d);
     }
     off += 1024;
-    xa = sp_ld(rj, off);
-    ya = sp_ld(rk, off);
+    xa = col_ld(rj, off);
+    ya = col_ld(rk, off);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const double prod = v[r] * xb;
@@ -360,11 +348,7 @@ k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long 
       if (lane == 0) segv[g] = 0.0;
       continue;
     }
-    // n <= 16384 rows: n 8 bytes fits the descriptor's size field
-    const __amdgpu_buffer_rsrc_t rj = __builtin_amdgcn_make_buffer_rsrc((void *)(X + (long long)j * ld), (short)0,
-                                                                        n * 8, SP_RSRC_WORD3);
-    const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc((void *)(X + (long long)k * ld), (short)0,
-                                                                        n * 8, SP_RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rj = col_rsrc(X + (long long)j * ld, n), rk = col_rsrc(X + (long long)k * ld, n);
     const int steps = (n + 63) >> 6;
     double emax = 0.0, vmax = 0.0;
     long long t0 = a;
