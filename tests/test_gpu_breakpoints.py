@@ -67,7 +67,7 @@ def test_random(ctx, n, m, integer, seed):
     _eq(_gpu(ctx, X), O.breakpoints(X), f"{n}x{m}")
 
 
-@pytest.mark.parametrize("n", [1500, 4000, 9000])
+@pytest.mark.parametrize("n", [1500, 4000, 9000, 16384])
 def test_many_breakpoints_per_segment(ctx, n):
     # strongly correlated columns: most points lie between the lambda = 0
     # minimiser and 0, more than one window list holds

@@ -2,7 +2,7 @@
 exact path: every record (lambda, j, k, v, row, E, P) bit for bit on small
 and mid-size inputs (the worked example, random and integer matrices with
 ties, duplicate and zero columns, 70 equal columns (more than a wave of
-tied lines in a tile), one column, long columns, a 400 x 40
+tied lines in a tile), one column, long columns, the largest n (16384), a 400 x 40
 workload whose breakpoints fill all 4096 lambda tiles), and on the
 2000 x 2000 workload the records checked where the oracle can score them one
 preserved coordinate at a time."""
@@ -85,6 +85,14 @@ def test_all_tiles_400x40(ctx):
     X = wl.rank_one_matrix(400, 40, 8, 40, 20.0, 0.01, (51, 0), laplace_b=0.1)
     bp = ctx.breakpoints(_dev(X))
     assert bp["lam"].numel() > 8 * 4096       # several entries per lambda tile
+    _same(_gpu_records(ctx, X), O.solution_path(X))
+
+
+def test_max_rows_16384x4(ctx):
+    """The largest n the library takes (every row step past n reads 0
+    through the range-checked column loads); about 7500 entries per
+    segment."""
+    X = wl.rank_one_matrix(16384, 4, 4, 0, 20.0, 0.0, (33, 16384), laplace_b=0.02)
     _same(_gpu_records(ctx, X), O.solution_path(X))
 
 
