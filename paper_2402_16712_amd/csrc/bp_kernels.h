@@ -80,21 +80,6 @@ __host__ __device__ constexpr int xcd_tile(int n) {
   return (1 << 20) / (8 * n) > 64 ? 64 : ((1 << 20) / (8 * n) < 4 ? 4 : (1 << 20) / (8 * n));
 }
 
-// A column through a raw buffer descriptor (word 3: 32-bit data format, no
-// swizzle); n <= 16384 rows, so n 8 bytes fits the size field.  Loads past
-// the column's end return 0, so a wave can run a uniform loop over row
-// steps with no bounds branch.
-constexpr int COL_RSRC_WORD3 = 0x00020000;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const double *p, int n) {
-  return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, n * 8, COL_RSRC_WORD3);
-}
-__device__ __forceinline__ double col_ld(__amdgpu_buffer_rsrc_t r, int off) {
-  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-  double d;
-  __builtin_memcpy(&d, &u, sizeof d);
-  return d;
-}
-
 // Is element (key, row) at or above the pair (lk, lr) in sorted order?
 __device__ __forceinline__ bool pair_ge(uint64_t key, int row, uint64_t lk, int lr) {
   return key > lk || (key == lk && row >= lr);

@@ -103,6 +103,21 @@ __device__ __forceinline__ void weight_chunks(double a, int e0, double &c0, doub
   c0 = fma(-c1, 0x1p37, r);
 }
 
+// A column through a raw buffer descriptor (word 3: 32-bit data format, no
+// swizzle); n <= 16384 rows, so n 8 bytes fits the size field.  Loads past
+// the column's end return 0, so a wave can run a uniform loop over row
+// steps with no bounds branch.
+constexpr int COL_RSRC_WORD3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const double *p, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, n * 8, COL_RSRC_WORD3);
+}
+__device__ __forceinline__ double col_ld(__amdgpu_buffer_rsrc_t r, int off) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  double d;
+  __builtin_memcpy(&d, &u, sizeof d);
+  return d;
+}
+
 // an exact whole double below 2^64 as an integer
 __device__ __forceinline__ uint64_t u64_of_whole(double v) {
   const double hi = floor(v * 0x1p-32);

@@ -160,6 +160,12 @@ __device__ __forceinline__ double sxj_at(const SegIO &s, int i) {
   return s.lds ? s.sxj[i] : gld(s.sxj + i);
 }
 
+// x_ij of row i < 64 T, 0 past row n: the zero-padded LDS copy, or the
+// column in device memory through its range-checked descriptor rj
+__device__ __forceinline__ double sxj_pad(const SegIO &s, __amdgpu_buffer_rsrc_t rj, int i) {
+  return s.lds ? s.sxj[i] : col_ld(rj, i * 8);
+}
+
 // key of fl(x_ik / x_ij) + 0.0; KEY_NONE outside the matrix or where x_ij = 0
 __device__ __forceinline__ uint64_t seg_key(const SegIO &s, int i) {
   const bool in = i < s.n;
@@ -500,12 +506,40 @@ __device__ __forceinline__ void wave_resolve(const SegIO &s, const uint64_t *lk,
   }
 }
 
-// e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0)
+// e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0).  kPad: rows
+// past n are read as 0 instead of masked (the single-penalty kernels; the
+// several-penalty ones keep the masked loop, which spills less there)
+template <bool kPad>
 __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
   // column k in batches of RB loads issued back to back (the sum is still
   // taken slot by slot in increasing order)
   constexpr int RB = 8;
   double p = 0.0;
+  if (kPad && __builtin_isfinite(v)) {
+    // rows past n read 0 from both columns and add |0 - v 0| = +0, which
+    // leaves the lane's partial as it is: no per-row masks or clamps
+    const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, s.n), rj = col_rsrc(s.lds ? s.xk : s.sxj, s.n);
+    int t0 = 0;
+    for (; t0 + RB <= s.T; t0 += RB) {
+      double xk[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) xk[r] = col_ld(rk, (s.lane + 64 * (t0 + r)) * 8);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const double prod = v * sxj_pad(s, rj, s.lane + 64 * (t0 + r));
+        const double d = xk[r] - prod;
+        p = p + fabs(d);
+      }
+    }
+    for (; t0 < s.T; ++t0) {
+      const int i = s.lane + 64 * t0;
+      const double prod = v * sxj_pad(s, rj, i);
+      const double d = col_ld(rk, i * 8) - prod;
+      p = p + fabs(d);
+    }
+    return wave_r64_tree(p);
+  }
+  // (an infinite ratio: v 0 is NaN, so the rows past n are masked)
   for (int t0 = 0; t0 < s.T; t0 += RB) {
     double xk[RB];
 #pragma unroll
@@ -1051,14 +1085,18 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         int nwin = 0;
         // columns j and k are read one slot ahead so the loads overlap the
         // divide; the weight reuses x_ij
-        double anext = sxj_at(s, lane < n ? lane : 0), bnext = gld(s.xk + (lane < n ? lane : 0));
+        // (one penalty: rows past n read 0, key NONE and no weight; several:
+        // clamped to row 0, which spills less there)
+        const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, n), rj = col_rsrc(s.lds ? s.xk : s.sxj, n);
+        auto ldj = [&](int i) { return kMulti ? sxj_at(s, i < n ? i : 0) : sxj_pad(s, rj, i); };
+        auto ldk = [&](int i) { return kMulti ? gld(s.xk + (i < n ? i : 0)) : col_ld(rk, i * 8); };
+        double anext = ldj(lane), bnext = ldk(lane);
         for (int tt = 0; tt < T; ++tt) {
           const int i = lane + 64 * tt;
           const double a = anext, b = bnext;
-          const int i2 = i + 64 < n ? i + 64 : 0;
           if (tt + 1 < T) {
-            anext = sxj_at(s, i2);
-            bnext = gld(s.xk + i2);
+            anext = ldj(i + 64);
+            bnext = ldk(i + 64);
           }
           const uint64_t key = key_of_pair(i < n, a, b);
           const bool valid = key != KEY_NONE;
@@ -1199,7 +1237,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       double e_l = 0.0;
       if (__builtin_popcountll(needm) == 1) {
         const int jl = __builtin_ctzll(needm);
-        const double e1 = __shfl(wave_residual(s, __shfl(v_l, jl)), 0);
+        const double e1 = __shfl(wave_residual<!kMulti>(s, __shfl(v_l, jl)), 0);
         if (lane == jl) e_l = e1;
       } else {
         constexpr int RJ = 4;
