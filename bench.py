@@ -29,9 +29,10 @@ sys.path.insert(0, ROOT)
 # VALU lane-op issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (= the 78.6 TFLOP/s FP64 vector peak with an FMA counted as 2 flops).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU operations per ratio element of the segment kernel (see
-# DESIGN.md, "Roofline"): IEEE FP64 divide (10), key + sign classification
-# (4), exact 128-bit weight accumulation (4), residual mul/sub/add (3).
+# Algorithmic VALU operations per ratio element of the segment kernel: the
+# correctly rounded IEEE FP64 divide (10: 2 div_scale, rcp, 5 fma, div_fmas,
+# div_fixup), key + sign classification (4), exact 128-bit weight
+# accumulation (4), residual mul/sub/add (3).
 OPS_PER_ELEMENT = 21
 
 
