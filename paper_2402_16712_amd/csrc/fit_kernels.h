@@ -566,6 +566,31 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
   double p[G];
 #pragma unroll
   for (int r = 0; r < G; ++r) p[r] = 0.0;
+  bool fin = true;
+#pragma unroll
+  for (int r = 0; r < G; ++r) fin = fin && __builtin_isfinite(v[r]);
+  if (fin) {
+    // rows past n read 0 from both columns and add |0 - v 0| = +0
+    const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, s.n), rj = col_rsrc(s.lds ? s.xk : s.sxj, s.n);
+    double an = sxj_pad(s, rj, s.lane), bn = col_ld(rk, s.lane * 8);
+    for (int t = 0; t < s.T; ++t) {
+      const int i = s.lane + 64 * t;
+      const double a = an, b = bn;
+      if (t + 1 < s.T) {
+        an = sxj_pad(s, rj, i + 64);
+        bn = col_ld(rk, (i + 64) * 8);
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const double prod = v[r] * a;
+        const double d = b - prod;
+        p[r] = p[r] + fabs(d);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree(p[r]), 0);
+    return;
+  }
   const int l0 = s.lane < s.n ? s.lane : 0;
   double an = sxj_at(s, l0), bn = gld(s.xk + l0);
   for (int t = 0; t < s.T; ++t) {
@@ -1239,7 +1264,8 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         const int jl = __builtin_ctzll(needm);
         const double e1 = __shfl(wave_residual<!kMulti>(s, __shfl(v_l, jl)), 0);
         if (lane == jl) e_l = e1;
-      } else {
+      } else if constexpr (kMulti) {
+        // (one penalty: at most one job)
         constexpr int RJ = 4;
         uint64_t jm = needm;
         while (jm) {
