@@ -60,6 +60,9 @@ struct l1line_ctx_s {
   float *rk_w;              // ranker: FP32 weights, Adam moments m1, m2 (device, 3 x L1LINE_MLP_PARAMS)
   bool rk_have_w, rk_have_state;
   int64_t rk_step;          // Adam steps taken (checkpoint state)
+  // the dynamic-LDS limits raised on this context's device for the kernels
+  // that take more than 64 KB (segment kernels, path sort, MLP backward)
+  bool attr_seg, attr_sort, attr_bwd;
   uint64_t rk_seed, rk_cursor;  // training-set seed and next example (checkpoint state)
 };
 
@@ -247,8 +250,6 @@ static uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
   return h;
 }
 
-static bool lds_attr_set = false;
-static bool sp_sort_attr_set = false;
 
 // Optional restrictions of a one-problem run (device pointers): cand / ncand
 // restrict the preserved columns to a list, jmask marks them for the
@@ -454,7 +455,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   const int sxj_rows = Ly.nmax <= SXJ_LDS_MAX ? Ly.nmax : 0;
   const int lcap = (Ly.Lmax > 1 && seg_lds_bytes(sxj_rows, Ly.Lmax, PATH_CAP) <= lds_max) ? PATH_CAP : WIN_CAP;
   const size_t lds = seg_lds_bytes(sxj_rows, Ly.Lmax, lcap);
-  if (!lds_attr_set) {
+  if (!ctx->attr_seg) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_max));
     HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<false, false>,
@@ -463,7 +464,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
                                 (int)lds_max));
     HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_max));
-    lds_attr_set = true;
+    ctx->attr_seg = true;
   }
   const long long all_items = Ly.ksplit ? (long long)Ly.nitems * SEG_XCDS : (long long)Ly.nitems;
   const int grid_seg = (int)std::max(1ll, std::min(all_items, (long long)tp.blocks_per_cu * ctx->num_cu));
@@ -851,7 +852,6 @@ int l1line_tune_get(l1line_ctx ctx, int32_t *params) {
 }
 
 // ------------------------------------------------------------------ ranker
-static bool bwd_attr_set = false;
 
 static int mlp_forward(l1line_ctx ctx, const float *P, const float *F, int64_t N, float *out, float *H1, float *H2,
                        hipStream_t s) {
@@ -889,9 +889,9 @@ static int mlp_grad_impl(l1line_ctx ctx, const float *params, const float *F, co
   float *gpart = (float *)(b + o_g), *lpart = (float *)(b + o_l);
   st = mlp_forward(ctx, params, F, N, out, H1, H2, s);
   if (st) return st;
-  if (!bwd_attr_set) {
+  if (!ctx->attr_bwd) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_mlp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BWD_LDS));
-    bwd_attr_set = true;
+    ctx->attr_bwd = true;
   }
   {
     ProfScope ps(ctx, s, "mlp_bwd");
@@ -1460,10 +1460,10 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   }
   {
     ProfScope ps(ctx, s, "sp_sort");
-    if (!sp_sort_attr_set) {
+    if (!ctx->attr_sort) {
       HIP_TRY(hipFuncSetAttribute((const void *)k_sp_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)SP_SORT_LDS));
-      sp_sort_attr_set = true;
+      ctx->attr_sort = true;
     }
     hipLaunchKernelGGL(k_sp_sort, dim3((unsigned)m), dim3(1024), SP_SORT_LDS, s, (int)m, (const long long *)offsets,
                        (const double *)elam, keyA, idA, keyB, idB, (const u128 *)dE, (const u128 *)dP,
