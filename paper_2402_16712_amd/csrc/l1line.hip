@@ -1425,8 +1425,8 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   // per-entry arrays, then per (tile, column) arrays
   const size_t e8 = align_up(sizeof(double) * NE, 256), e4 = align_up(sizeof(int) * NE, 256),
                e16 = align_up(sizeof(u128) * NE, 256), tm = (size_t)SP_TMAX * m;
-  const size_t q_lam = 0, q_v = q_lam + e8, q_row = q_v + e8, q_e = q_row + e4, q_dE = q_e + e8, q_dP = q_dE + e16,
-               q_kA = q_dP + e16, q_kB = q_kA + e8, q_iA = q_kB + e8, q_iB = q_iA + e4, q_sE = q_iB + e4,
+  const size_t q_lam = 0, q_v = q_lam + e8, q_row = q_v + e8, q_e = q_row + e4, q_dz = q_e + e8,
+               q_kA = q_dz + 2 * e16, q_kB = q_kA + e8, q_iA = q_kB + e8, q_iB = q_iA + e4, q_sE = q_iB + e4,
                q_sP = q_sE + e16, q_LB = q_sP + e16, q_list = q_LB + align_up(sizeof(double) * tm, 256),
                q_pos = q_list + align_up(sizeof(int) * tm, 256), q_pb = q_pos + align_up(sizeof(long long) * tm, 256),
                big = q_pb + align_up(sizeof(long long) * tm, 256);
@@ -1436,7 +1436,8 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   double *elam = (double *)(c + q_lam), *ev = (double *)(c + q_v), *ee = (double *)(c + q_e),
          *LB = (double *)(c + q_LB);
   int *erow = (int *)(c + q_row), *list = (int *)(c + q_list);
-  u128 *dE = (u128 *)(c + q_dE), *dP = (u128 *)(c + q_dP), *stE = (u128 *)(c + q_sE), *stP = (u128 *)(c + q_sP);
+  SpDelta *dz = (SpDelta *)(c + q_dz);
+  u128 *stE = (u128 *)(c + q_sE), *stP = (u128 *)(c + q_sP);
   uint64_t *keyA = (uint64_t *)(c + q_kA), *keyB = (uint64_t *)(c + q_kB);
   uint32_t *idA = (uint32_t *)(c + q_iA), *idB = (uint32_t *)(c + q_iB);
   long long *spos = (long long *)(c + q_pos), *spb = (long long *)(c + q_pb);
@@ -1456,7 +1457,7 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   {
     ProfScope ps(ctx, s, "sp_delta");
     hipLaunchKernelGGL(k_sp_delta, dim3(grid), dim3(256), 0, s, (int)m, (const long long *)offsets,
-                       (const double *)ev, (const double *)ee, sc, dE, dP);
+                       (const double *)ev, (const double *)ee, sc, dz);
   }
   {
     ProfScope ps(ctx, s, "sp_sort");
@@ -1466,7 +1467,7 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
       ctx->attr_sort = true;
     }
     hipLaunchKernelGGL(k_sp_sort, dim3((unsigned)m), dim3(1024), SP_SORT_LDS, s, (int)m, (const long long *)offsets,
-                       (const double *)elam, keyA, idA, keyB, idB, (const u128 *)dE, (const u128 *)dP,
+                       (const double *)elam, keyA, idA, keyB, idB, (const SpDelta *)dz,
                        (const PathScale *)sc, stE, stP);
   }
   {

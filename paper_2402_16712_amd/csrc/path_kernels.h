@@ -387,10 +387,15 @@ __global__ void k_sp_scale(const unsigned long long *__restrict__ gmax, PathScal
 // --------------------------------------------------------------------- deltas
 // The change of (E, P) at each entry: entry t replaces entry t - 1 of its
 // segment (entry 0 replaces nothing).  Two's complement in 128 bits.
+// An entry's change of the line: value E and slope P, one 32-byte record so
+// that the sort's gather of both touches one cache line.
+struct alignas(32) SpDelta {
+  u128 E, P;
+};
+
 __global__ void __launch_bounds__(256)
 k_sp_delta(int m, const long long *__restrict__ offsets, const double *__restrict__ ev,
-           const double *__restrict__ ee, PathScale *__restrict__ sc, u128 *__restrict__ dE,
-           u128 *__restrict__ dP) {
+           const double *__restrict__ ee, PathScale *__restrict__ sc, SpDelta *__restrict__ dz) {
   const int lane = threadIdx.x & 63;
   const long long nseg = (long long)m * m;
   const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
@@ -402,8 +407,10 @@ k_sp_delta(int m, const long long *__restrict__ offsets, const double *__restric
       const double e = ee[t], v = fabs(ev[t]);
       const double pe = t > a ? ee[t - 1] : 0.0, pv = t > a ? fabs(ev[t - 1]) : 0.0;
       if ((e != 0.0 && lowest_bit_exp(e) < sE) || (v != 0.0 && lowest_bit_exp(v) < sP)) bad = 1;
-      dE[t] = fixed_of(e, sE) - fixed_of(pe, sE);
-      dP[t] = fixed_of(v, sP) - fixed_of(pv, sP);
+      SpDelta dl;
+      dl.E = fixed_of(e, sE) - fixed_of(pe, sE);
+      dl.P = fixed_of(v, sP) - fixed_of(pv, sP);
+      dz[t] = dl;
     }
   }
   if (bad) atomicOr(&sc->bad, 1);
@@ -432,16 +439,16 @@ struct SpSortLds {
   unsigned tc[256];         // tile: entries of each digit
   int nrun;                 // passes that move entries
   int run[8];
-  u128 wt[16];             // wave totals of a tile's changes
-  u128 wp[16];             // their exclusive prefix
-  u128 tt;                 // tile total
+  u128 wt[16], wtp[16];    // wave totals of a tile's changes of E and P
+  u128 wp[16], wpp[16];    // their exclusive prefix
+  u128 tt, ttp;            // tile totals
 };
 constexpr size_t SP_SORT_LDS = sizeof(SpSortLds);
 
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_sp_sort(int m, const long long *__restrict__ offsets, const double *__restrict__ elam, uint64_t *__restrict__ keyA,
           uint32_t *__restrict__ idA, uint64_t *__restrict__ keyB, uint32_t *__restrict__ idB,
-          const u128 *__restrict__ dE, const u128 *__restrict__ dP, const PathScale *__restrict__ sc,
+          const SpDelta *__restrict__ dz, const PathScale *__restrict__ sc,
           u128 *__restrict__ stE, u128 *__restrict__ stP) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sp_smem[];
   SpSortLds &L = *reinterpret_cast<SpSortLds *>(sp_smem);
@@ -599,40 +606,42 @@ k_sp_sort(int m, const long long *__restrict__ offsets, const double *__restrict
     iout = (iout == idA) ? idB : idA;
   }
   __syncthreads();
-  // exact lines in sorted order: 4 consecutive entries per lane, then the
-  // lanes, then the 16 waves of a tile; the value E and the slope P one
-  // after the other
-  for (int part = 0; part < 2; ++part) {
-    const u128 *__restrict__ dz = part ? dP : dE;
-    u128 *__restrict__ st = part ? stP : stE;
-    u128 c = part ? fixed_of(1.0, sc->sP) : (u128)0;
-    for (long long t0 = 0; t0 < N; t0 += SP_SORT_TILE) {
-      const long long s0 = t0 + 4 * tid;
-      u128 x[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const bool valid = s0 + r < N;
-        const uint32_t id = valid ? idA[a + s0 + r] : 0u;
-        x[r] = valid ? dz[id] : (u128)0;
-      }
-#pragma unroll
-      for (int r = 1; r < 4; ++r) x[r] += x[r - 1];
-      const u128 ix = wave_incl_scan_u128(x[3], lane);
-      if (lane == 63) L.wt[w] = ix;
-      __syncthreads();
-      if (tid < 64) {
-        const u128 o = lane < 16 ? L.wt[lane] : (u128)0;
-        const u128 sx = wave_incl_scan_u128(o, lane);
-        if (lane < 16) L.wp[lane] = sx - o;
-        if (lane == 15) L.tt = sx;
-      }
-      __syncthreads();
-      const u128 b = c + L.wp[w] + (ix - x[3]);
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (s0 + r < N) st[a + s0 + r] = b + x[r];
-      c += L.tt;
+  // exact lines in sorted order: one entry per lane (its value and slope
+  // change read together), then the lanes, then the 16 waves
+  u128 cE = 0, cP = fixed_of(1.0, sc->sP);
+  for (long long t0 = 0; t0 < N; t0 += 1024) {
+    const long long s0 = t0 + tid;
+    u128 x = 0, y = 0;
+    if (s0 < N) {
+      const SpDelta d0 = dz[idA[a + s0]];
+      x = d0.E;
+      y = d0.P;
     }
+    const u128 ix = wave_incl_scan_u128(x, lane), iy = wave_incl_scan_u128(y, lane);
+    if (lane == 63) {
+      L.wt[w] = ix;
+      L.wtp[w] = iy;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const u128 ox = lane < 16 ? L.wt[lane] : (u128)0, oy = lane < 16 ? L.wtp[lane] : (u128)0;
+      const u128 sx = wave_incl_scan_u128(ox, lane), sy = wave_incl_scan_u128(oy, lane);
+      if (lane < 16) {
+        L.wp[lane] = sx - ox;
+        L.wpp[lane] = sy - oy;
+      }
+      if (lane == 15) {
+        L.tt = sx;
+        L.ttp = sy;
+      }
+    }
+    __syncthreads();
+    if (s0 < N) {
+      stE[a + s0] = cE + L.wp[w] + ix;
+      stP[a + s0] = cP + L.wpp[w] + iy;
+    }
+    cE += L.tt;
+    cP += L.ttp;
   }
 }
 
