@@ -139,12 +139,15 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
       const bool ng = key < KEY_ZERO, zr = key == KEY_ZERO;
       double c0, c1, c2;
       weight_chunks(a, s.e0, c0, c1, c2);
-      a0 = a0 + (ng ? c0 : 0.0);
-      a1 = a1 + (ng ? c1 : 0.0);
-      a2 = a2 + (ng ? c2 : 0.0);
-      z0 = z0 + (zr ? c0 : 0.0);
-      z1 = z1 + (zr ? c1 : 0.0);
-      z2 = z2 + (zr ? c2 : 0.0);
+      // masked adds as fma with a 0/1 factor: the same exact sums (whole
+      // numbers below 2^53; c 0 adds +0) in one op instead of select + add
+      const double fn = ng ? 1.0 : 0.0, fz = zr ? 1.0 : 0.0;
+      a0 = fma(c0, fn, a0);
+      a1 = fma(c1, fn, a1);
+      a2 = fma(c2, fn, a2);
+      z0 = fma(c0, fz, z0);
+      z1 = fma(c1, fz, z1);
+      z2 = fma(c2, fz, z2);
       if (r0 >= 0 && valid) {
         const bool in = neg ? (key < KEY_ZERO && pair_ge(key, i, mkey, r0))
                             : (key > KEY_ZERO && pair_le(key, i, mkey, r0));
@@ -325,9 +328,10 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
           const bool in = valid && !lt && pair_le(key, i, wk_hi, wr_hi);
           double c0, c1, c2;
           weight_chunks(a, s.e0, c0, c1, c2);
-          b0 = b0 + (lt ? c0 : 0.0);
-          b1 = b1 + (lt ? c1 : 0.0);
-          b2 = b2 + (lt ? c2 : 0.0);
+          const double fl = lt ? 1.0 : 0.0;   // masked adds as fma (exact, as above)
+          b0 = fma(c0, fl, b0);
+          b1 = fma(c1, fl, b1);
+          b2 = fma(c2, fl, b2);
           const uint64_t wm = __ballot(in);
           const int pos = nwin + lanes_below(wm);
           nwin += __builtin_popcountll(wm);

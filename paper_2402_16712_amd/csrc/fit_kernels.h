@@ -1130,9 +1130,12 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           {
             double c0, c1, c2;
             weight_chunks(a, s.e0, c0, c1, c2);
-            c0s = c0s + (le_lo ? c0 : 0.0);
-            c1s = c1s + (le_lo ? c1 : 0.0);
-            c2s = c2s + (le_lo ? c2 : 0.0);
+            // masked adds as fma with a 0/1 factor: the same exact sums
+            // (whole numbers below 2^53; c 0 adds +0), one op each
+            const double fl = le_lo ? 1.0 : 0.0;
+            c0s = fma(c0, fl, c0s);
+            c1s = fma(c1, fl, c1s);
+            c2s = fma(c2, fl, c2s);
           }
           const uint64_t wm = __ballot(inwin);
           const int pos = nwin + lanes_below(wm);
