@@ -96,6 +96,16 @@ def test_max_rows_16384x4(ctx):
     _same(_gpu_records(ctx, X), O.solution_path(X))
 
 
+def test_tied_breakpoints_across_sort_tiles(ctx):
+    """Integer data: about 17000 entries per preserved coordinate (several
+    4096-entry tiles of the radix sort) and thousands of groups of entries at
+    the same nonzero lambda, which must keep their (k, t) order across
+    tiles."""
+    X = wl.rank_one_matrix(12000, 4, 4, 0, 20.0, 0.0, (62, 12000), laplace_b=0.02)
+    X = np.asfortranarray(np.round(X * 32.0))
+    _same(_gpu_records(ctx, X), O.solution_path(X))
+
+
 def test_capacity_and_count(ctx):
     X = _cases()["random_60x30"]
     Xd = _dev(X)
