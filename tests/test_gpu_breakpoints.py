@@ -76,6 +76,15 @@ def test_many_breakpoints_per_segment(ctx, n):
     _eq(_gpu(ctx, X), O.breakpoints(X), f"corr{n}")
 
 
+def test_integer_ties_long_columns(ctx):
+    # integer data, 12000 rows: thousands of equal breakpoints across the
+    # segments, several window passes per segment
+    X = wl.rank_one_matrix(12000, 4, 4, 0, 20.0, 0.0, (62, 12000), laplace_b=0.02)
+    X = np.asfortranarray(np.round(X * 32.0))
+    _say("case bp integer ties 12000x4")
+    _eq(_gpu(ctx, X), O.breakpoints(X), "int12000")
+
+
 def test_one_key_with_many_rows(ctx):
     # 1500 identical ratios in one segment: streamed in row order
     rng = np.random.default_rng(4)
