@@ -91,11 +91,24 @@ __device__ __forceinline__ bool pair_le(uint64_t key, int row, uint64_t hk, int 
 // ------------------------------------------------------------------ counts
 // counts[g] (int64, written to offsets + 1 + g) and lambda_max[g] of segment
 // g = j m + k; V0, R0: v_k and its row at lambda = 0 (m x m, row -1 for 0).
+// kList: also list each segment's entries (key, row), when there are at most
+// wcap (<= BP_LIST_MAX) of them, in row order at wkeys/wrows[g wcap ..]
+// (staged in LDS, stored once per segment), and in wsb[g] the exact weight
+// of the negative ratios (negative minimiser) or of the negative and zero
+// ones (positive): the emit pass then takes its first window from there
+// instead of scanning the rows again.
+constexpr int BP_LIST_MAX = 128;
+template <bool kList>
 __global__ void __launch_bounds__(256)
 k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColInfo *__restrict__ ci,
            const double *__restrict__ V0, const int *__restrict__ R0, long long *__restrict__ counts,
-           double *__restrict__ lmax) {
+           double *__restrict__ lmax, uint64_t *__restrict__ wkeys, unsigned short *__restrict__ wrows,
+           u128 *__restrict__ wsb, int wcap) {
   const int lane = threadIdx.x & 63;
+  __shared__ uint64_t skeys[4][BP_LIST_MAX];
+  __shared__ unsigned short srows[4][BP_LIST_MAX];
+  uint64_t *lk = skeys[(threadIdx.x >> 6) & 3];
+  unsigned short *lr = srows[(threadIdx.x >> 6) & 3];
   const int ts = xcd_tile(n);
   const int T = (n + 63) >> 6;
   int Tp = 1;
@@ -124,7 +137,7 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
     // weights as FP64 sums of 37-bit chunks (exact, see weight_chunks);
     // the columns are read one slot ahead
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
-    int cnt = 0;
+    int cnt = 0, nin = 0;
     const __amdgpu_buffer_rsrc_t rj = col_rsrc(s.sxj, n), rk = col_rsrc(s.xk, n);
     int off = lane * 8;
     double an = col_ld(rj, off), bn = col_ld(rk, off);
@@ -153,10 +166,34 @@ k_bp_count(const double *__restrict__ X, int n, int m, long long ld, const ColIn
                             : (key > KEY_ZERO && pair_le(key, i, mkey, r0));
         cnt += in ? 1 : 0;
       }
+      if constexpr (kList) {
+        // the emit pass's first window: the same elements, in row order
+        const bool inl = r0 >= 0 && valid &&
+                         (neg ? (key < KEY_ZERO && pair_ge(key, i, mkey, r0))
+                              : (key > KEY_ZERO && pair_le(key, i, mkey, r0)));
+        const uint64_t im = __ballot(inl);
+        const int pos = nin + lanes_below(im);
+        nin += __builtin_popcountll(im);
+        if (inl && pos < wcap) {
+          lk[pos] = key;
+          lr[pos] = (unsigned short)i;
+        }
+      }
     }
     const u128 A = chunks_to_u128(wave_sum_dbl(a0), wave_sum_dbl(a1), wave_sum_dbl(a2)),
                B = A + chunks_to_u128(wave_sum_dbl(z0), wave_sum_dbl(z1), wave_sum_dbl(z2)), W = cj.wfix;
     cnt = wave_sum_int(cnt);
+    if constexpr (kList) {
+      if (nin <= wcap) {
+        wave_lds_sync();
+        for (int e = lane; e < nin; e += 64) {
+          wkeys[g * wcap + e] = lk[e];
+          wrows[g * wcap + e] = lr[e];
+        }
+        wave_lds_sync();
+      }
+      if (lane == 0) wsb[g] = neg ? A : B;
+    }
     u128 lm = 0;
     if ((A << 1) > W) lm = (A << 1) - W;
     else if (W > (B << 1)) lm = W - (B << 1);
@@ -250,7 +287,9 @@ __global__ void __launch_bounds__(256)
 k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInfo *__restrict__ ci,
           const double *__restrict__ V0, const int *__restrict__ R0, const long long *__restrict__ offsets,
           const double *__restrict__ lmax, long long capacity, double *__restrict__ lam, double *__restrict__ v,
-          int *__restrict__ row, int *__restrict__ status, int *__restrict__ sticky) {
+          int *__restrict__ row, int *__restrict__ status, int *__restrict__ sticky,
+          const uint64_t *__restrict__ wkeys, const unsigned short *__restrict__ wrows,
+          const u128 *__restrict__ wsb, int wcap) {
   __shared__ uint64_t skeys[BP_WAVES][BP_CAP];
   __shared__ unsigned short srows[BP_WAVES][BP_CAP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -311,8 +350,26 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
         const int wr_hi = neg ? (w_hi == hi_k ? hi_r : 0xFFFF) : hi_r;
         // (weights as FP64 sums of 37-bit chunks, see weight_chunks; the
         // columns read one slot ahead)
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+        u128 Sb;
         int nwin = 0;
+        bool listed = false;
+        if (rounds == 1 && cnt - 1 <= wcap) {
+          // the count pass listed this first window (every entry of the
+          // segment); the weight below it is the count pass's weight of
+          // the negative and zero ratios (positive minimiser), or of the
+          // negative ones less the list's own (negative: the list is the
+          // negative ratios from the minimiser on), taken after the sort
+          listed = true;
+          nwin = (int)(cnt - 1);
+          const uint64_t *__restrict__ gk = wkeys + g * wcap;
+          const unsigned short *__restrict__ gr = wrows + g * wcap;
+          for (int e = lane; e < nwin; e += 64) {
+            lk[e] = gk[e];
+            lr[e] = gr[e];
+          }
+          Sb = wsb[g];
+        } else {
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
         const __amdgpu_buffer_rsrc_t rj = col_rsrc(s.sxj, n), rk = col_rsrc(s.xk, n);
         int off = lane * 8;
         double an = col_ld(rj, off), bn = col_ld(rk, off);
@@ -340,8 +397,9 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
             lr[pos] = (unsigned short)i;
           }
         }
-        const u128 Sb = chunks_to_u128(wave_sum_dbl(b0), wave_sum_dbl(b1), wave_sum_dbl(b2));
+        Sb = chunks_to_u128(wave_sum_dbl(b0), wave_sum_dbl(b1), wave_sum_dbl(b2));
         nwin = uni_int(nwin);
+        }
         wave_lds_sync();
         if (nwin > BP_CAP) {
           if (wk_lo == wk_hi) {
@@ -388,6 +446,7 @@ k_bp_emit(const double *__restrict__ X, int n, int m, long long ld, const ColInf
           const int E = N >> 6;
           u128 tot, incl;
           wave_list_sums(s, lk, lr, E, tot, incl);
+          if (listed && neg) Sb -= shfl_u128(incl, 63);
           u128 run = Sb + incl - tot;                 // weight before this lane's entries
           for (int q = 0; q < E; ++q) {
             const int e = E * lane + q;

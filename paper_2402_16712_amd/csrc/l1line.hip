@@ -54,6 +54,8 @@ struct l1line_ctx_s {
   size_t rk_bytes;
   void *sp;                 // solution-path scratch (per breakpoint entry, per tile and column)
   size_t sp_bytes;
+  void *bl;                 // Algorithm 2: each segment's entries listed by the count pass
+  size_t bl_bytes;
   int *sticky;              // device: first data-dependent error of any call on the context
   int host_err;             // first argument / runtime error an entry point returned
   std::string tune_path;    // launch-parameter cache file ("" = none)
@@ -137,6 +139,52 @@ static int ensure_rk(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
     return L1LINE_ENOMEM;
   }
   ctx->rk_bytes = want;
+  return L1LINE_OK;
+}
+
+static int ensure_bl(l1line_ctx ctx, size_t bytes, hipStream_t stream) {
+  if (bytes <= ctx->bl_bytes) return L1LINE_OK;
+  if (ctx->bl) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipFree(ctx->bl));
+    ctx->bl = nullptr;
+    ctx->bl_bytes = 0;
+  }
+  const size_t want = align_up(bytes, 1 << 20);
+  if (hipMalloc(&ctx->bl, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return L1LINE_ENOMEM;
+  }
+  ctx->bl_bytes = want;
+  return L1LINE_OK;
+}
+
+// Algorithm 2's entry lists: the count pass keeps the entries (key, row) of
+// each segment that has at most BP_LIST of them, and the weight below them,
+// so that the entry pass skips its scan of the rows for those segments.  Within a budget of
+// BP_LIST_BUDGET bytes, else not used (capacity 0).
+constexpr int BP_LIST = BP_LIST_MAX;
+constexpr size_t BP_LIST_BUDGET = (size_t)6 << 30;
+struct BpList {
+  uint64_t *keys = nullptr;
+  unsigned short *rows = nullptr;
+  u128 *sb = nullptr;
+  int cap = 0;
+};
+static int bp_list(l1line_ctx ctx, long long nseg, hipStream_t s, BpList *L) {
+  const size_t kb = align_up(sizeof(uint64_t) * BP_LIST * (size_t)nseg, 256),
+               rb = align_up(sizeof(unsigned short) * BP_LIST * (size_t)nseg, 256),
+               sb = align_up(sizeof(u128) * (size_t)nseg, 256);
+  *L = BpList();
+  if (kb + rb + sb > BP_LIST_BUDGET) return L1LINE_OK;
+  const int st = ensure_bl(ctx, kb + rb + sb, s);
+  if (st == L1LINE_ENOMEM) return L1LINE_OK;   // run without the lists
+  if (st) return st;
+  char *b = (char *)ctx->bl;
+  L->keys = (uint64_t *)b;
+  L->rows = (unsigned short *)(b + kb);
+  L->sb = (u128 *)(b + kb + rb);
+  L->cap = BP_LIST;
   return L1LINE_OK;
 }
 
@@ -612,6 +660,8 @@ int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path) {
   c->rk = nullptr;
   c->rk_bytes = 0;
   c->sp = nullptr;
+  c->bl = nullptr;
+  c->bl_bytes = 0;
   c->sp_bytes = 0;
   c->sticky = nullptr;
   c->host_err = L1LINE_OK;
@@ -667,6 +717,7 @@ int l1line_destroy(l1line_ctx ctx) {
   if (ctx->stage && hipHostFree(ctx->stage) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->rk && hipFree(ctx->rk) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->sp && hipFree(ctx->sp) != hipSuccess) st = L1LINE_EHIP;
+  if (ctx->bl && hipFree(ctx->bl) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->sticky && hipFree(ctx->sticky) != hipSuccess) st = L1LINE_EHIP;
   if (ctx->rk_w && hipFree(ctx->rk_w) != hipSuccess) st = L1LINE_EHIP;
   (void)hipEventDestroy(ctx->stage_done);
@@ -1293,17 +1344,29 @@ static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   if (st) return st;
   const long long nseg = (long long)m * m;
   const unsigned grid = (unsigned)std::max(8ll, std::min((nseg + 3) / 4, (long long)ctx->num_cu * 8));
+  BpList bl;
+  if (capacity > 0) {
+    st = bp_list(ctx, nseg, s, &bl);
+    if (st) return st;
+  }
   {
     ProfScope ps(ctx, s, "bp_count");
-    hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
-                       (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (long long *)offsets + 1, lm);
+    if (bl.cap > 0)
+      hipLaunchKernelGGL(k_bp_count<true>, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                         (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (long long *)offsets + 1,
+                         lm, bl.keys, bl.rows, bl.sb, bl.cap);
+    else
+      hipLaunchKernelGGL(k_bp_count<false>, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                         (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (long long *)offsets + 1,
+                         lm, (uint64_t *)nullptr, (unsigned short *)nullptr, (u128 *)nullptr, 0);
     scan_offsets(s, (long long *)offsets, nseg, (long long *)(b + o_part));
   }
   if (capacity > 0) {
     ProfScope ps(ctx, s, "bp_emit");
     hipLaunchKernelGGL(k_bp_emit, dim3(grid), dim3(64 * BP_WAVES), 0, s, X, (int)n, (int)m, (long long)ld,
                        (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (const long long *)offsets,
-                       (const double *)lm, (long long)capacity, lam, v, (int *)row, (int *)status, ctx->sticky);
+                       (const double *)lm, (long long)capacity, lam, v, (int *)row, (int *)status, ctx->sticky,
+                       (const uint64_t *)bl.keys, (const unsigned short *)bl.rows, (const u128 *)bl.sb, bl.cap);
   }
   HIP_TRY(hipGetLastError());
   return L1LINE_OK;
@@ -1409,10 +1472,19 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   st = run_batch(ctx, &p0, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
   if (st) return st;
   const unsigned grid = (unsigned)std::max(8ll, std::min((mm + 3) / 4, (long long)ctx->num_cu * 8));
+  BpList bl;
+  st = bp_list(ctx, mm, s, &bl);
+  if (st) return st;
   {
     ProfScope ps(ctx, s, "bp_count");
-    hipLaunchKernelGGL(k_bp_count, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
-                       (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, offsets + 1, lm);
+    if (bl.cap > 0)
+      hipLaunchKernelGGL(k_bp_count<true>, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                         (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, offsets + 1, lm, bl.keys,
+                         bl.rows, bl.sb, bl.cap);
+    else
+      hipLaunchKernelGGL(k_bp_count<false>, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
+                         (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, offsets + 1, lm,
+                         (uint64_t *)nullptr, (unsigned short *)nullptr, (u128 *)nullptr, 0);
     scan_offsets(s, offsets, mm, (long long *)(b + o_part));
   }
   long long NE = 0;
@@ -1445,7 +1517,8 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
     ProfScope ps(ctx, s, "bp_emit");
     hipLaunchKernelGGL(k_bp_emit, dim3(grid), dim3(64 * BP_WAVES), 0, s, X, (int)n, (int)m, (long long)ld,
                        (const ColInfo *)bp.ci, (const double *)bp.V, (const int *)bp.R, (const long long *)offsets,
-                       (const double *)lm, (long long)NE, elam, ev, erow, fst, ctx->sticky);
+                       (const double *)lm, (long long)NE, elam, ev, erow, fst, ctx->sticky,
+                       (const uint64_t *)bl.keys, (const unsigned short *)bl.rows, (const u128 *)bl.sb, bl.cap);
   }
   HIP_TRY(hipMemsetAsync(gmax, 0, 4 * sizeof(unsigned long long), s));
   {
