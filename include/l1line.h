@@ -305,8 +305,11 @@ int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps,
  *   status      as l1line_fit, and ESIZE (nothing written to lam, v, row)
  *               when the total exceeds capacity
  * Usage: a call with capacity 0 fills offsets; read offsets[m*m], size the
- * arrays, call again.  Host errors: as l1line_fit; ESIZE for m >
- * L1LINE_BP_MAX_M. */
+ * arrays, call again.  A call with capacity > 0 also keeps in the context
+ * up to 1296 bytes per segment (each segment's entries of at most 128, so
+ * that they are not searched for twice) when m*m*1296 bytes stay within
+ * 6 GiB; where that cannot be allocated the call runs without it.  Host
+ * errors: as l1line_fit; ESIZE for m > L1LINE_BP_MAX_M. */
 #define L1LINE_BP_MAX_M 8192
 int l1line_breakpoints(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                        int64_t ld, int64_t *offsets, double *lambda_max,
@@ -375,7 +378,8 @@ int l1line_components(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
  * ENONFINITE / EWIDE as l1line_fit, EWIDE also when some residual or |v| has
  * bits more than 110 places below the largest (the exact lines would not fit
  * 128 bits), ENOMEM for the workspace: about 120 bytes per breakpoint entry
- * plus 28 bytes per (tile, column) for 4096 tiles. */
+ * plus 28 bytes per (tile, column) for 4096 tiles (and, when it can be had,
+ * the per-segment entry lists of l1line_breakpoints). */
 int l1line_solution_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                          int64_t ld, int64_t capacity, int64_t *count,
                          double *lam, int64_t *j, int32_t *k, double *v,
