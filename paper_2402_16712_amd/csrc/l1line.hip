@@ -1520,11 +1520,13 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
                        (const double *)lm, (long long)NE, elam, ev, erow, fst, ctx->sticky,
                        (const uint64_t *)bl.keys, (const unsigned short *)bl.rows, (const u128 *)bl.sb, bl.cap);
   }
-  HIP_TRY(hipMemsetAsync(gmax, 0, 4 * sizeof(unsigned long long), s));
+  // the maxima (4 x 8 bytes) and the residual kernel's slot counters (8 ints)
+  HIP_TRY(hipMemsetAsync(gmax, 0, 4 * sizeof(unsigned long long) + 8 * sizeof(int), s));
   {
     ProfScope ps(ctx, s, "sp_resid");
     hipLaunchKernelGGL(k_sp_resid, dim3(grid), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld,
-                       (const long long *)offsets, (const double *)elam, (const double *)ev, ee, segv, gmax);
+                       (const long long *)offsets, (const double *)elam, (const double *)ev, ee, segv, gmax,
+                       (int *)(gmax + 4));
   }
   hipLaunchKernelGGL(k_sp_scale, dim3(1), dim3(1), 0, s, (const unsigned long long *)gmax, sc);
   {

@@ -331,11 +331,17 @@ __device__ __forceinline__ void sp_score(__amdgpu_buffer_rsrc_t rj, __amdgpu_buf
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_sp_resid(const double *__restrict__ X, int n, int m, long long ld, const long long *__restrict__ offsets,
            const double *__restrict__ elam, const double *__restrict__ ev, double *__restrict__ ee,
-           double *__restrict__ segv, unsigned long long *__restrict__ gmax) {
+           double *__restrict__ segv, unsigned long long *__restrict__ gmax, int *__restrict__ next) {
   const int lane = threadIdx.x & 63;
   const XcdTiles tl(m, xcd_tile(n), blockDim.x >> 6);
   double we = 0.0, wv = 0.0, wl = 0.0;   // the wave's maxima, one atomic each at the end
-  for (long long f = tl.wx;; f += tl.nwx) {
+  for (;;) {
+    // the XCD's next tile slot from its own counter (next[x], zero at
+    // launch): the waves of an XCD stay on neighbouring slots, whose
+    // columns share its L2, however long their segments
+    int fi = 0;
+    if (lane == 0) fi = atomicAdd(next + tl.x, 1);
+    const long long f = __builtin_amdgcn_readfirstlane(__shfl(fi, 0));
     long long g;
     if (!tl.at(f, g)) break;
     if (g < 0) continue;
