@@ -70,7 +70,7 @@ extern "C" {
 #define L1LINE_EIO (-9)        /* a file could not be read or written, or is malformed */
 #define L1LINE_ENOMODEL (-10)  /* the context holds no ranker weights                */
 
-#define L1LINE_MAX_N 16384         /* rows per matrix (column j is held in LDS)   */
+#define L1LINE_MAX_N 16384         /* rows per matrix (row ids are 16-bit in the segment lists) */
 #define L1LINE_MAX_LAMBDAS 128     /* penalties per call (passed by value)        */
 
 typedef struct l1line_ctx_s *l1line_ctx;

@@ -408,7 +408,9 @@ __global__ void k_topk(const float *__restrict__ score, int m, int K, float thre
   if (tid == 0) {
     const float mg = (K < m) ? next - best0 : 0.f;
     *margin_out = mg;
-    *fallback = (K >= m || mg < threshold) ? 1 : 0;
+    // a NaN margin (every score non-finite: inf - inf) or a non-finite best
+    // score separates nothing: the exhaustive search decides
+    *fallback = (K >= m || !(mg >= threshold) || !isfinite(best0)) ? 1 : 0;
   }
 }
 
