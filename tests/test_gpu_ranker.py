@@ -85,6 +85,53 @@ def test_mlp_grad(ctx, N):
         _close(g[lo:hi], want[lo:hi], 1e-2, name)
 
 
+@pytest.mark.parametrize("N", [1, 17, 333, 4096 + 5])
+def test_mlp_forward_elementwise_bound(ctx, N):
+    # every row inside the interval any FP32-accumulating evaluation with
+    # the reference's BF16 rounding points must reach (oracle.mlp_oracle:
+    # forward_interval)
+    _say(f"mlp_forward interval N={N}")
+    P = _params(1)
+    F = np.random.default_rng(N + 50).standard_normal((N, M.IN)).astype(np.float32)
+    out = ctx.mlp_forward(_dev(P), _dev(F)).cpu().numpy().astype(np.float64)
+    lo, hi, _ = M.forward_interval(P, F)
+    bad = np.nonzero((out < lo) | (out > hi))[0]
+    assert bad.size == 0, (bad[:5], out[bad[:5]], lo[bad[:5]], hi[bad[:5]])
+
+
+@pytest.mark.parametrize("N", [1, 31, 33, 500, 2048 + 7])
+def test_mlp_grad_elementwise_bound(ctx, N):
+    _say(f"mlp_grad interval N={N}")
+    P = _params(2)
+    rng = np.random.default_rng(N + 70)
+    F = rng.standard_normal((N, M.IN)).astype(np.float32)
+    y = rng.standard_normal(N).astype(np.float32)
+    g, loss = ctx.mlp_grad(_dev(P), _dev(F), _dev(y))
+    g = g.cpu().numpy().astype(np.float64)
+    lo, hi, (llo, lhi) = M.grad_interval(P, F, y)
+    bad = np.nonzero((g < lo) | (g > hi))[0]
+    assert bad.size == 0, (bad[:5], g[bad[:5]], lo[bad[:5]], hi[bad[:5]])
+    assert llo <= float(loss.item()) <= lhi
+
+
+@pytest.mark.parametrize("N,seed", [(48, 0), (64, 1), (7, 2), (130, 3), (96, 4)])
+def test_mlp_exact_inputs_bitwise(ctx, N, seed):
+    # inputs on which every product, FP32 sum and BF16 rounding is exact: the
+    # kernels must return the reference's values bit for bit, every entry
+    from tests.mlp_cases import exact_case
+    _say(f"mlp exact inputs N={N}")
+    P, F, y = exact_case(N, seed)
+    out = ctx.mlp_forward(_dev(P), _dev(F)).cpu().numpy()
+    want, _ = M.forward(P, F, bf=True)
+    assert out.tobytes() == want.astype(np.float32).tobytes()
+    g, loss = ctx.mlp_grad(_dev(P), _dev(F), _dev(y))
+    wl_, wg = M.loss_and_grad(P, F, y, bf=True)
+    g = g.cpu().numpy()
+    bad = np.nonzero(g != wg.astype(np.float32))[0]
+    assert bad.size == 0, (bad[:8], g[bad[:8]], wg[bad[:8]])
+    assert float(loss.item()) == np.float32(wl_)
+
+
 def test_mlp_grad_deterministic(ctx):
     P = _params(3)
     rng = np.random.default_rng(5)
@@ -213,6 +260,26 @@ def test_fit_ranked_fallback(ctx, K):
     assert np.float64(r["obj"].item()).tobytes() == np.float64(ref["obj"]).tobytes()
     assert r["v"].cpu().numpy().tobytes() == ref["v"].tobytes()
     assert np.array_equal(r["row"].cpu().numpy(), ref["row"])
+
+
+@pytest.mark.parametrize("bias", [float("nan"), float("inf")])
+def test_fit_ranked_nonfinite_scores_fall_back(ctx, bias):
+    """Weights whose output bias is NaN (or +inf) give every column a
+    non-finite score: nothing separates the candidates, so the exhaustive
+    search runs even at threshold 0 and the result is the oracle's."""
+    from paper_2402_16712_amd import binding as B
+    X = wl.rank_one_matrix(300, 24, 3, 30, 20.0, 0.01, (24, 0))
+    lam = 0.05 * wl.max_column_mass(X)
+    P = _params(10)
+    P[M.OFF_B3] = bias
+    ctx.ranker_set_params(_dev(P))
+    r = ctx.fit_ranked(B.device_matrix(X), lam, 4, 0.0)
+    ref = O.fit(X, lam)
+    assert not np.any(np.isfinite(r["scores"].cpu().numpy()))
+    assert int(r["status"].item()) == 0
+    assert int(r["used_fallback"].item()) == 1
+    assert int(r["j"].item()) == ref["j"]
+    assert r["v"].cpu().numpy().tobytes() == ref["v"].tobytes()
 
 
 def test_fit_ranked_bad_args(ctx):
