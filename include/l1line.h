@@ -119,6 +119,27 @@ int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                int32_t *median_row, double *z_all, int32_t *status,
                void *stream);
 
+/* For callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, arguments, outputs and errors as l1line_fit, with the
+ * workspace in a fixed device array of L1LINE_NOALLOC_SCRATCH_MB MiB that the
+ * library holds on every GPU it runs on until the process ends.  The call
+ * allocates nothing (no hipMalloc / hipFree, no pinned staging: its metadata
+ * travels as kernel arguments).  The workspace needs about 36 m^2 + 64 m
+ * bytes plus a few KB, so m <= L1LINE_NOALLOC_MAX_M (n up to L1LINE_MAX_N).
+ * Every call on one GPU, from any context, stream or thread, shares that
+ * GPU's array and leaves its contents there; each call re-initialises what
+ * it reads.  Calls that overlap in time on the same GPU race: the caller
+ * must serialise them (one stream, or events).  Host errors: as l1line_fit,
+ * plus ESIZE for m > L1LINE_NOALLOC_MAX_M and EHIP when the array's device
+ * address could not be obtained when the context was created. */
+#define L1LINE_NOALLOC_SCRATCH_MB 40
+#define L1LINE_NOALLOC_MAX_M 1024
+int l1line_fit_noalloc(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
+                       int64_t ld, double lambda, double *v, int64_t *j,
+                       double *obj, int32_t *median_row, double *z_all,
+                       int32_t *status, void *stream);
+
 /* Algorithm 1 along a path of L penalties, each ratio list built once per
  * (j, k) and reused for every lambda (the solution for each lambda is the
  * one l1line_fit returns for it, bit for bit).

@@ -18,9 +18,11 @@ OK, EINVAL, EHIP, ENONFINITE, ERANGE, ENOMEM, EWIDE, ESIZE, EINTERNAL, EIO, ENOM
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
 MAX_N = 16384
 MAX_LAMBDAS = 128
+NOALLOC_MAX_M = 1024
 
 EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_error", "l1line_column_stats",
-           "l1line_fit", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
+           "l1line_fit", "l1line_fit_noalloc", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune",
+           "l1line_tune_get",
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
            "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
            "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train",
@@ -71,6 +73,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_strerror.restype = ctypes.c_char_p
         L.l1line_column_stats.argtypes = [P, P, I64, I64, I64, P, P, P, P]
         L.l1line_fit.argtypes = [P, P, I64, I64, I64, D, P, P, P, P, P, P, P]
+        L.l1line_fit_noalloc.argtypes = [P, P, I64, I64, I64, D, P, P, P, P, P, P, P]
         L.l1line_fit_path.argtypes = [P, P, I64, I64, I64, P, I64, P, P, P, P, P, P, P]
         L.l1line_fit_batch.argtypes = [P, P, I64, I32, P]
         L.l1line_autotune.argtypes = [P, P, I64, P, P]
@@ -85,7 +88,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_profile.argtypes = [P, I32]
         L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),
                                           ctypes.POINTER(I64), I32]
-        for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit",
+        for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit", "l1line_fit_noalloc",
                   "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
                   "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
                   "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked",
@@ -209,6 +212,21 @@ class Context:
         _check(lib().l1line_fit(self._h, _ptr(X), n, m, ld, float(lam), _ptr(out["v"]), _ptr(out["j"]),
                                 _ptr(out["obj"]), _ptr(out["row"]), _ptr(out["z_all"]),
                                 _ptr(out["status"]), self._stream()), "l1line_fit")
+        return out
+
+    def fit_noalloc(self, X, lam: float, out=None):
+        """l1line_fit_noalloc: as fit(), the workspace in the library's fixed
+        device array.  `out` (optional): a dict from an earlier call whose
+        tensors are reused, so the call itself allocates nothing."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        if out is None:
+            out = dict(v=self._empty((m,), torch.float64), j=self._empty((1,), torch.int64),
+                       obj=self._empty((1,), torch.float64), row=self._empty((m,), torch.int32),
+                       z_all=self._empty((m,), torch.float64), status=self._empty((1,), torch.int32))
+        _check(lib().l1line_fit_noalloc(self._h, _ptr(X), n, m, ld, float(lam), _ptr(out["v"]), _ptr(out["j"]),
+                                        _ptr(out["obj"]), _ptr(out["row"]), _ptr(out["z_all"]),
+                                        _ptr(out["status"]), self._stream()), "l1line_fit_noalloc")
         return out
 
     def fit_path(self, X, lambdas, rows: bool = True, z_all: bool = True):

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -66,6 +67,7 @@ struct l1line_ctx_s {
   // that take more than 64 KB (segment kernels, path sort, MLP backward)
   bool attr_seg, attr_sort, attr_bwd;
   uint64_t rk_seed, rk_cursor;  // training-set seed and next example (checkpoint state)
+  void *scratch;            // this device's address of the no-alloc workspace (null if unavailable)
 };
 
 #define HIP_TRY(expr)                                   \
@@ -97,6 +99,34 @@ struct ProfScope {
 };
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------- no-alloc workspace
+// Workspace of l1line_fit_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  In host code the name is
+// only a host-side stand-in: kernels and copies take the device address that
+// hipGetSymbolAddress returns, fetched once per device (with that device
+// current) when the first context on it is created.
+constexpr size_t NOALLOC_BYTES = (size_t)L1LINE_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// The calling thread's current device must be `device`.
+static void *scratch_address(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
 
 static void drop_graph(l1line_ctx ctx) {
   if (ctx->graph) {
@@ -322,10 +352,10 @@ struct BatchPtrs {
   ColInfo *ci;
 };
 
-static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, hipStream_t s,
-                     const TuneParams &tp, float *only_seg_ms, const RunOpts &ro = kNoOpts,
-                     BatchPtrs *outp = nullptr) {
-  BatchLayout Ly;
+// Sizes, work items and workspace layout of a batch call (no allocation for
+// B == 1: its items are implicit).
+static int plan_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, const TuneParams &tp,
+                      const RunOpts &ro, BatchLayout &Ly, std::vector<WorkItem> &items) {
   memset(&Ly, 0, sizeof Ly);
   Ly.B = (int)B;
   Ly.nmax = 1;
@@ -351,7 +381,6 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
 
   // work items: split every problem's k range so the whole batch offers
   // about items_per_cu items per compute unit, each with >= kchunk_min k
-  std::vector<WorkItem> items;
   const double target = (double)tp.items_per_cu * ctx->num_cu;
   if (B == 1) {
     const int m = (int)probs[0].m;
@@ -412,61 +441,79 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     Ly.nitems = (int)items.size();
   }
   layout_sizes(Ly);
-  int st = ensure_ws(ctx, Ly.bytes, s);
-  if (st) return st;
-  st = ensure_stage(ctx, Ly.meta_bytes);
-  if (st) return st;
+  return L1LINE_OK;
+}
 
-  // metadata into the pinned staging buffer
-  char *h = (char *)ctx->stage;
-  char *d = (char *)ctx->ws;
+// The problem descriptor of problem b with the batch's workspace offsets.
+struct MetaCursor {
+  long long col, z, out, wsoff, lamoff, pairoff, tiles;
+};
+static ProbDesc prob_desc(const l1line_problem &p, const MetaCursor &c) {
+  ProbDesc q;
+  q.X = p.X;
+  q.ld = p.ld;
+  q.n = (int)p.n;
+  q.m = (int)p.m;
+  q.L = (int)p.L;
+  q.lam_off = (int)c.lamoff;
+  q.col_off = (int)c.col;
+  q.out_off = (int)c.out;
+  q.ws_off = c.wsoff;
+  q.z_off = c.z;
+  q.pair_off = c.pairoff;
+  q.Vout = p.V;
+  q.Jout = (long long *)p.J;
+  q.OBJout = p.OBJ;
+  q.ROWout = p.ROW;
+  q.ZALLout = p.ZALL;
+  q.status = p.status;
+  return q;
+}
+static void advance(MetaCursor &c, const l1line_problem &p, const RunOpts &ro, int64_t B) {
+  c.col += p.m;
+  c.z += p.L * p.m;
+  c.out += p.L;
+  c.wsoff += p.L * p.m * p.m;
+  c.lamoff += p.L;
+  c.pairoff += p.m * p.m;
+  const int64_t mj = (ro.cand && B == 1) ? ro.ncand : p.m;
+  c.tiles += ((mj + SS_TILE - 1) / SS_TILE) * ((p.m + SS_TILE - 1) / SS_TILE);
+}
+
+// The metadata block (the first Ly.meta_bytes of the workspace) in host memory h.
+static void fill_meta(char *h, const BatchLayout &Ly, const l1line_problem *probs, int64_t B,
+                      const std::vector<WorkItem> &items, const RunOpts &ro) {
   memset(h, 0, Ly.meta_bytes);
   ProbDesc *hd = (ProbDesc *)(h + Ly.o_desc);
   int *hcol = (int *)(h + Ly.o_colstart), *hz = (int *)(h + Ly.o_zstart), *ho = (int *)(h + Ly.o_ostart);
   int *ht = (int *)(h + Ly.o_tstart);
   double *hlam = (double *)(h + Ly.o_lam);
-  long long col = 0, z = 0, out = 0, wsoff = 0, lamoff = 0, pairoff = 0, tiles = 0;
+  MetaCursor c = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t b = 0; b < B; ++b) {
     const l1line_problem &p = probs[b];
-    ProbDesc &q = hd[b];
-    q.X = p.X;
-    q.ld = p.ld;
-    q.n = (int)p.n;
-    q.m = (int)p.m;
-    q.L = (int)p.L;
-    q.lam_off = (int)lamoff;
-    q.col_off = (int)col;
-    q.out_off = (int)out;
-    q.ws_off = wsoff;
-    q.z_off = z;
-    q.pair_off = pairoff;
-    q.Vout = p.V;
-    q.Jout = (long long *)p.J;
-    q.OBJout = p.OBJ;
-    q.ROWout = p.ROW;
-    q.ZALLout = p.ZALL;
-    q.status = p.status;
-    hcol[b] = (int)col;
-    hz[b] = (int)z;
-    ho[b] = (int)out;
-    ht[b] = (int)tiles;
-    for (int64_t t = 0; t < p.L; ++t) hlam[lamoff + t] = p.lambdas[t];
-    col += p.m;
-    z += p.L * p.m;
-    out += p.L;
-    wsoff += p.L * p.m * p.m;
-    lamoff += p.L;
-    pairoff += p.m * p.m;
-    const int64_t mj = (ro.cand && B == 1) ? ro.ncand : p.m;
-    tiles += ((mj + SS_TILE - 1) / SS_TILE) * ((p.m + SS_TILE - 1) / SS_TILE);
+    hd[b] = prob_desc(p, c);
+    hcol[b] = (int)c.col;
+    hz[b] = (int)c.z;
+    ho[b] = (int)c.out;
+    ht[b] = (int)c.tiles;
+    for (int64_t t = 0; t < p.L; ++t) hlam[c.lamoff + t] = p.lambdas[t];
+    advance(c, p, ro, B);
   }
-  hcol[B] = (int)col;
-  ht[B] = (int)tiles;
-  hz[B] = (int)z;
-  ho[B] = (int)out;
+  hcol[B] = (int)c.col;
+  ht[B] = (int)c.tiles;
+  hz[B] = (int)c.z;
+  ho[B] = (int)c.out;
   if (!items.empty()) memcpy(h + Ly.o_items, items.data(), sizeof(WorkItem) * items.size());
   memcpy(h + Ly.o_xstart, Ly.xstart, sizeof Ly.xstart);
+}
 
+// The launch sequence of one batch call on stream ls, the workspace at d
+// (its metadata block already in place or written by an earlier kernel on
+// ls).  `prof`: bracket the kernels with the context's timing events;
+// t0 / t1 (optional): events recorded around the segment kernel.
+static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, char *d, int64_t B,
+                      const TuneParams &tp, const RunOpts &ro, bool prof, hipEvent_t t0, hipEvent_t t1,
+                      BatchPtrs *outp) {
   const ProbDesc *dP = (const ProbDesc *)(d + Ly.o_desc);
   const int *dcol = (const int *)(d + Ly.o_colstart), *dz = (const int *)(d + Ly.o_zstart),
             *dout = (const int *)(d + Ly.o_ostart), *dtile = (const int *)(d + Ly.o_tstart);
@@ -480,21 +527,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   int *dR = (int *)(d + Ly.o_R), *dzflag = (int *)(d + Ly.o_zflag);
   double2 *dDZ = (double2 *)(d + Ly.o_DZ);
   if (outp) *outp = BatchPtrs{dV, dR, dci};
-
-  uint64_t key = fnv1a(h, Ly.meta_bytes, 1469598103934665603ull);
-  key = fnv1a(&tp, sizeof tp, key);
-  key = fnv1a(&ctx->ws, sizeof ctx->ws, key);
-  key = fnv1a(&ro, sizeof ro, key);
-  const bool use_graph = (flags & L1LINE_BATCH_GRAPH) && !ctx->profiling && !only_seg_ms;
-  if (use_graph && ctx->graph && ctx->graph_key == key) {
-    // the device metadata of this layout is still in place: replay
-    HIP_TRY(hipGraphLaunch(ctx->graph, s));
-    return L1LINE_OK;
-  }
-  drop_graph(ctx);
-  HIP_TRY(hipMemcpyAsync(d, h, Ly.meta_bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(ctx->stage_done, s));
-  ctx->stage_pending = true;
+  l1line_ctx pc = prof ? ctx : nullptr;
 
   // window list capacity: the larger path list where the LDS allows it
   const size_t lds_max = seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS, WIN_CAP);
@@ -516,6 +549,78 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
   }
   const long long all_items = Ly.ksplit ? (long long)Ly.nitems * SEG_XCDS : (long long)Ly.nitems;
   const int grid_seg = (int)std::max(1ll, std::min(all_items, (long long)tp.blocks_per_cu * ctx->num_cu));
+  {
+    ProfScope ps(pc, ls, "colprep");
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 16ll, 0);
+    hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
+                       (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
+  }
+  {
+    ProfScope ps(pc, ls, "signsum");
+    hipLaunchKernelGGL(k_signsum_batch, dim3((unsigned)Ly.total_tiles), dim3(256), 0, ls, dP, dtile, (int)B,
+                       (B == 1) ? ro.cand : nullptr, ro.ncand, dDZ, ro.gate, ro.gate_on);
+  }
+  if (t0) HIP_TRY(hipEventRecord(t0, ls));
+  {
+    ProfScope ps(pc, ls, "fit_seg");
+    // single-penalty problems take the instantiation tuned for one target
+    const bool multi = Ly.Lmax > 1;
+    auto kseg = sxj_rows > 0 ? (multi ? k_seg_batch<true, true> : k_seg_batch<true, false>)
+                             : (multi ? k_seg_batch<false, true> : k_seg_batch<false, false>);
+    hipLaunchKernelGGL(kseg, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
+                       Ly.nitems, Ly.ksplit, dcounter, dxstart, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand,
+                       ro.ncand,
+                       ro.gate, ro.gate_on, lcap, sxj_rows);
+  }
+  if (t1) HIP_TRY(hipEventRecord(t1, ls));
+  {
+    ProfScope ps(pc, ls, "reduce");
+    hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)Ly.total_z), dim3(64), 0, ls, dP, dz, (int)B, dlam, dV, dE,
+                       dZ, dzflag, ro.jmask, ro.gate, ro.gate_on);
+  }
+  {
+    ProfScope ps(pc, ls, "argmin");
+    hipLaunchKernelGGL(k_argmin_batch, dim3((unsigned)Ly.total_out), dim3(256), 0, ls, dP, dout, (int)B, dV, dR,
+                       dZ, dzflag, dci, dsegflags, ro.jmask, ro.gate, ro.gate_on, ctx->sticky);
+  }
+  return L1LINE_OK;
+}
+
+static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, hipStream_t s,
+                     const TuneParams &tp, float *only_seg_ms, const RunOpts &ro = kNoOpts,
+                     BatchPtrs *outp = nullptr) {
+  BatchLayout Ly;
+  std::vector<WorkItem> items;
+  int st = plan_batch(ctx, probs, B, tp, ro, Ly, items);
+  if (st) return st;
+  st = ensure_ws(ctx, Ly.bytes, s);
+  if (st) return st;
+  st = ensure_stage(ctx, Ly.meta_bytes);
+  if (st) return st;
+
+  // metadata into the pinned staging buffer
+  char *h = (char *)ctx->stage;
+  char *d = (char *)ctx->ws;
+  fill_meta(h, Ly, probs, B, items, ro);
+
+  uint64_t key = fnv1a(h, Ly.meta_bytes, 1469598103934665603ull);
+  key = fnv1a(&tp, sizeof tp, key);
+  key = fnv1a(&ctx->ws, sizeof ctx->ws, key);
+  key = fnv1a(&ro, sizeof ro, key);
+  const bool use_graph = (flags & L1LINE_BATCH_GRAPH) && !ctx->profiling && !only_seg_ms;
+  if (use_graph && ctx->graph && ctx->graph_key == key) {
+    // the device metadata of this layout is still in place: replay
+    if (outp) {
+      BatchPtrs bp{(double *)(d + Ly.o_V), (int *)(d + Ly.o_R), (ColInfo *)(d + Ly.o_ci)};
+      *outp = bp;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->graph, s));
+    return L1LINE_OK;
+  }
+  drop_graph(ctx);
+  HIP_TRY(hipMemcpyAsync(d, h, Ly.meta_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ctx->stage_done, s));
+  ctx->stage_pending = true;
 
   hipStream_t ls = s;
   if (use_graph) {
@@ -526,51 +631,18 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     ls = ctx->cap_stream;
   }
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  {
-    ProfScope ps(ctx, ls, "colprep");
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 16ll, 0);
-    hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
-                       (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
-  }
-  {
-    ProfScope ps(ctx, ls, "signsum");
-    hipLaunchKernelGGL(k_signsum_batch, dim3((unsigned)Ly.total_tiles), dim3(256), 0, ls, dP, dtile, (int)B,
-                       (B == 1) ? ro.cand : nullptr, ro.ncand, dDZ, ro.gate, ro.gate_on);
-  }
   if (only_seg_ms) {
     HIP_TRY(hipEventCreate(&t0));
     HIP_TRY(hipEventCreate(&t1));
-    HIP_TRY(hipEventRecord(t0, ls));
   }
-  {
-    ProfScope ps(ctx, ls, "fit_seg");
-    // single-penalty problems take the instantiation tuned for one target
-    const bool multi = Ly.Lmax > 1;
-    auto kseg = sxj_rows > 0 ? (multi ? k_seg_batch<true, true> : k_seg_batch<true, false>)
-                             : (multi ? k_seg_batch<false, true> : k_seg_batch<false, false>);
-    hipLaunchKernelGGL(kseg, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
-                       Ly.nitems, Ly.ksplit, dcounter, dxstart, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand,
-                       ro.ncand,
-                       ro.gate, ro.gate_on, lcap, sxj_rows);
-  }
-  if (only_seg_ms) HIP_TRY(hipEventRecord(t1, ls));
-  {
-    ProfScope ps(ctx, ls, "reduce");
-    hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)Ly.total_z), dim3(64), 0, ls, dP, dz, (int)B, dlam, dV, dE,
-                       dZ, dzflag, ro.jmask, ro.gate, ro.gate_on);
-  }
-  {
-    ProfScope ps(ctx, ls, "argmin");
-    hipLaunchKernelGGL(k_argmin_batch, dim3((unsigned)Ly.total_out), dim3(256), 0, ls, dP, dout, (int)B, dV, dR,
-                       dZ, dzflag, dci, dsegflags, ro.jmask, ro.gate, ro.gate_on, ctx->sticky);
-  }
+  st = launch_seq(ctx, ls, Ly, d, B, tp, ro, true, t0, t1, outp);
   const hipError_t le = hipGetLastError();
   if (use_graph) {
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
-    if (le != hipSuccess || ce != hipSuccess) {
+    if (st || le != hipSuccess || ce != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return L1LINE_EHIP;
+      return st ? st : L1LINE_EHIP;
     }
     hipGraphExec_t ex = nullptr;
     const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -581,6 +653,7 @@ static int run_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int
     HIP_TRY(hipGraphLaunch(ctx->graph, s));
     return L1LINE_OK;
   }
+  if (st) return st;
   if (le != hipSuccess) return L1LINE_EHIP;
   if (only_seg_ms) {
     HIP_TRY(hipEventSynchronize(t1));
@@ -669,6 +742,7 @@ int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path) {
   c->rk_have_w = c->rk_have_state = false;
   c->rk_step = 0;
   c->rk_seed = c->rk_cursor = 0;
+  c->scratch = scratch_address(device);   // device is current (hipSetDevice above)
   if (tune_cache_path) c->tune_path = tune_cache_path;
   tune_load(c);
   if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
@@ -803,6 +877,61 @@ static int fit_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64
 int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, double *v,
                int64_t *j, double *obj, int32_t *median_row, double *z_all, int32_t *status, void *stream) {
   return note(ctx, fit_impl(ctx, X, n, m, ld, lambda, v, j, obj, median_row, z_all, status, stream));
+}
+
+// Metadata of a one-problem call written by a kernel from its arguments, so
+// that the no-alloc call needs no host staging buffer.  One thread.
+__global__ void k_meta_single(ProbDesc pd, double lam, long long tiles, BatchLayout Ly, char *d) {
+  if (threadIdx.x != 0) return;
+  *(ProbDesc *)(d + Ly.o_desc) = pd;
+  int *col = (int *)(d + Ly.o_colstart), *z = (int *)(d + Ly.o_zstart), *o = (int *)(d + Ly.o_ostart),
+      *t = (int *)(d + Ly.o_tstart);
+  col[0] = 0;
+  col[1] = pd.m;
+  z[0] = 0;
+  z[1] = pd.m;
+  o[0] = 0;
+  o[1] = 1;
+  t[0] = 0;
+  t[1] = (int)tiles;
+  *(double *)(d + Ly.o_lam) = lam;
+  int *xs = (int *)(d + Ly.o_xstart);
+  for (int x = 0; x <= SEG_XCDS; ++x) xs[x] = Ly.xstart[x];
+}
+
+static int fit_noalloc_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
+                            double *v, int64_t *j, double *obj, int32_t *median_row, double *z_all,
+                            int32_t *status, void *stream) {
+  if (!ctx || !v || !j || !obj) return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  st = check_lambdas(&lambda, 1);
+  if (st) return st;
+  if (m > L1LINE_NOALLOC_MAX_M) return L1LINE_ESIZE;
+  if (!ctx->scratch) return L1LINE_EHIP;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, z_all, status);
+  BatchLayout Ly;
+  std::vector<WorkItem> items;        // stays empty: one problem's items are implicit
+  st = plan_batch(ctx, &p, 1, ctx->tune, kNoOpts, Ly, items);
+  if (st) return st;
+  if (Ly.bytes > NOALLOC_BYTES || !items.empty()) return L1LINE_ESIZE;
+  const MetaCursor c0 = {0, 0, 0, 0, 0, 0, 0};
+  MetaCursor c1 = c0;
+  advance(c1, p, kNoOpts, 1);
+  char *d = (char *)ctx->scratch;
+  hipLaunchKernelGGL(k_meta_single, dim3(1), dim3(64), 0, s, prob_desc(p, c0), lambda, c1.tiles, Ly, d);
+  st = launch_seq(ctx, s, Ly, d, 1, ctx->tune, kNoOpts, false, nullptr, nullptr, nullptr);
+  if (st) return st;
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
+int l1line_fit_noalloc(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, double *v,
+                       int64_t *j, double *obj, int32_t *median_row, double *z_all, int32_t *status,
+                       void *stream) {
+  return note(ctx, fit_noalloc_impl(ctx, X, n, m, ld, lambda, v, j, obj, median_row, z_all, status, stream));
 }
 
 static int fit_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas,

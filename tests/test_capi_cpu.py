@@ -42,6 +42,7 @@ def test_header_constants_match_binding():
     consts = dict(re.findall(r"#define (L1LINE_\w+) \(?(-?\d+)\)?", text))
     assert int(consts["L1LINE_MAX_N"]) == B.MAX_N
     assert int(consts["L1LINE_MAX_LAMBDAS"]) == B.MAX_LAMBDAS
+    assert int(consts["L1LINE_NOALLOC_MAX_M"]) == B.NOALLOC_MAX_M
     assert int(consts["L1LINE_EWIDE"]) == B.EWIDE and int(consts["L1LINE_ERANGE"]) == B.ERANGE
 
 
@@ -73,6 +74,22 @@ def test_fit_host_argument_checks():
     assert _fit(f.h, 1, 10, 4, 10, float("inf")) == B.EINVAL
     assert _fit(f.h, 1, 10, 4, 10, 0.5, v=0) == B.EINVAL     # null output
     assert _fit(f.h, 1, B.MAX_N + 1, 4, B.MAX_N + 1, 0.5) == B.ESIZE
+
+
+def test_fit_noalloc_host_argument_checks():
+    f = _Fake()
+    P = ctypes.c_void_p
+
+    def call(h, X, n, m, ld, lam, v=1):
+        return B.lib().l1line_fit_noalloc(h, P(X), n, m, ld, lam, P(v) if v else None, P(1), P(1), None, None,
+                                          None, None)
+    assert call(None, 1, 10, 4, 10, 0.5) == B.EINVAL
+    assert call(f.h, 0, 10, 4, 10, 0.5) == B.EINVAL
+    assert call(f.h, 1, 10, 4, 9, 0.5) == B.EINVAL
+    assert call(f.h, 1, 10, 4, 10, float("nan")) == B.EINVAL
+    assert call(f.h, 1, 10, 4, 10, 0.5, v=0) == B.EINVAL
+    assert call(f.h, 1, B.MAX_N + 1, 4, B.MAX_N + 1, 0.5) == B.ESIZE
+    assert call(f.h, 1, 10, B.NOALLOC_MAX_M + 1, 10, 0.5) == B.ESIZE
 
 
 def test_path_host_argument_checks():
