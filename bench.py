@@ -343,7 +343,7 @@ def main():
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     kern = {}
-    for name in ("colprep", "signsum", "fit_seg", "reduce", "argmin"):
+    for name in ("colprep", "signsum", "zero_seg", "fit_seg", "reduce", "argmin"):
         ms, cnt = ctx.profile_read(name)
         kern[name] = ms / max(cnt, 1)
     ctx.profile_read(reset=True)

@@ -411,7 +411,7 @@ int l1line_solution_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
  * context launches is bracketed by HIP events on its stream.
  * l1line_profile_read waits for the recorded events, returns the summed
  * duration (ms) and launch count of the kernels whose name is `kernel`
- * ("colprep", "signsum", "fit_seg", "reduce", "argmin", "features",
+ * ("colprep", "signsum", "zero_seg", "fit_seg", "reduce", "argmin", "features",
  * "mlp_fwd", "mlp_bwd", "bp_count", "bp_emit", "sp_resid", "sp_delta",
  * "sp_sort", "sp_bounds", "sp_sweep"; NULL = all), and with
  * reset != 0

@@ -38,6 +38,7 @@ struct ProbDesc {
   long long ws_off;     // first element of this problem's L*m*m block in V / E / R
   long long z_off;      // first element of this problem's L*m block in Z / zflag
   long long pair_off;   // first element of this problem's m*m block of sign sums
+  long long mask_off;   // first word of this problem's zero-segment mask (mj ceil(m / 64) words)
   double *Vout;         // L*m
   long long *Jout;      // L
   double *OBJout;       // L
@@ -825,6 +826,7 @@ k_signsum_one(const double *__restrict__ X, int n, int m, long long ld, double2 
 constexpr int SEG_WAVES = 4;
 constexpr int SAMPLE_ROWS = 128;
 constexpr int SXJ_LDS_MAX = 4096;   // longest column j copied to LDS (32 KB)
+constexpr int SEG_MASK_WORDS = 64;  // zero-segment mask words an item reads into LDS (4096 k)
 
 __host__ __device__ constexpr size_t seg_sxj_bytes(int n) {
   return ((size_t)((n + 63) / 64) * 64 * 8 + 15) / 16 * 16;
@@ -832,6 +834,222 @@ __host__ __device__ constexpr size_t seg_sxj_bytes(int n) {
 __host__ __device__ constexpr size_t seg_lds_bytes(int n, int L, int lcap) {
   return seg_sxj_bytes(n) + SAMPLE_ROWS * 4 + (size_t)L * 16 +
          SEG_WAVES * (sizeof(WaveScratch) + (size_t)lcap * (sizeof(uint64_t) + sizeof(unsigned short))) + 16;
+}
+
+
+// ------------------------------------------------ division-free window pass
+// Fast form of the exact pass.  For a row with a = x_ij != 0 and b = x_ik the
+// ratio is q = b / a = u / |a| with u = b sgn(a) (exact), so q <= bound
+// exactly when u <= bound |a|.  Comparing u with fl(bound' |a|), bound' the
+// window bound moved outwards by 2^-49 of its magnitude, decides without a
+// division, and rigorously, whether fl(q) lies at or below the window (its
+// weight |a| joins an FP64 sum) or above it (dropped); rows inside the guard
+// band or the window are listed by row and get their exact key (one IEEE
+// divide each) in a second pass over the list, which keeps the window's
+// elements (key, row) in row order -- the list the exact pass builds.  Zero
+// bounds are sign tests: u < 0 is u <= -2^-1074 (the smallest subnormal).
+// Valid when every nonzero magnitude of columns j and k lies in
+// [2^-300, 2^300]: then q and the products stay normal.
+constexpr int FAST_BEXP_LO = 1023 - 300, FAST_BEXP_HI = 1023 + 300;
+
+__device__ __forceinline__ bool fast_columns(const ColInfo &c) {
+  return c.nnz == 0 || (c.bemin >= FAST_BEXP_LO && c.bemax <= FAST_BEXP_HI);
+}
+
+// thresholds: "at or below the window" = u <= fma(lo_g, |a|, c_lo), "above
+// the window" = u > fma(hi_g, |a|, c_hi)
+struct FastBounds {
+  double lo_g, c_lo, hi_g, c_hi;
+};
+__device__ __forceinline__ FastBounds fast_bounds(uint64_t plo, uint64_t phi) {
+  constexpr double TINY = 0x1p-1074;
+  FastBounds f{0.0, 0.0, 0.0, 0.0};
+  if (plo == 0) {
+    f.c_lo = -__builtin_inf();                      // nothing at or below
+  } else if (plo == KEY_ZERO - 1) {
+    f.c_lo = -TINY;                                  // every negative ratio
+  } else {
+    const double lo = ratio_of_key(plo);
+    f.lo_g = lo - fabs(lo) * 0x1p-49;
+  }
+  if (phi == KEY_NONE - 1) {
+    f.c_hi = __builtin_inf();                        // nothing above
+  } else if (phi == KEY_ZERO - 1) {
+    f.c_hi = -TINY;                                  // every ratio >= 0
+  } else {
+    const double hi = ratio_of_key(phi);
+    f.hi_g = hi + fabs(hi) * 0x1p-49;
+  }
+  return f;
+}
+
+// floor(x / 2^e0) for a finite x >= 0 below 2^(e0 + 127)
+__device__ __forceinline__ u128 fixed_floor(double x, int e0) {
+  return x > 0.0 ? fixed_of(x, e0) : (u128)0;
+}
+
+// The fast pass over the rows of segment (j, k) for the window (plo, phi]:
+// lk / lr receive the window's elements in row order (count nwin; nwin >
+// lcap reports an overflow, the list then unusable), and [SA, SB] brackets
+// the exact weight of the elements at or below the window (units 2^e0).
+template <class LdJ, class LdK>
+__device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ldk, uint64_t plo, uint64_t phi,
+                                                 uint64_t *lk, unsigned short *lr, int lcap, int &nwin, u128 &SA,
+                                                 u128 &SB) {
+  const FastBounds f = fast_bounds(plo, phi);
+  const int lane = s.lane, T = s.T;
+  double S = 0.0;
+  int nc = 0;
+  // rows in batches of FB slots, every load of a batch issued before the
+  // first is used (one slot at a time left the wave waiting on L2 latency)
+  constexpr int FB = 8;
+  for (int t0 = 0; t0 < T; t0 += FB) {
+    double av[FB], bv[FB];
+#pragma unroll
+    for (int r = 0; r < FB; ++r) {
+      const int i = lane + 64 * (t0 + r);
+      const bool in = t0 + r < T;
+      av[r] = in ? ldj(i) : 0.0;
+      bv[r] = in ? ldk(i) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < FB; ++r) {
+      const int i = lane + 64 * (t0 + r);
+      const double a = av[r], b = bv[r];
+      const double aa = fabs(a);
+      const double u =
+          __longlong_as_double(__double_as_longlong(b) ^ (__double_as_longlong(a) & (long long)KEY_ZERO));
+      const bool valid = a != 0.0;
+      const bool below = valid && u <= fma(f.lo_g, aa, f.c_lo);
+      const bool above = u > fma(f.hi_g, aa, f.c_hi);
+      S = fma(aa, below ? 1.0 : 0.0, S);
+      const bool cand = valid && !below && !above;
+      const uint64_t cm = __ballot(cand);
+      const int pos = nc + lanes_below(cm);
+      nc += __builtin_popcountll(cm);
+      if (cand && pos < lcap) lr[pos] = (unsigned short)i;
+    }
+  }
+  nc = uni_int(nc);
+  wave_lds_sync();
+  int nw = 0;
+  if (nc <= lcap) {
+    // exact keys of the listed rows, GB slots of gathers in flight; the
+    // window's elements are compacted to the front (an entry never moves
+    // above its own slot, and a batch is read before it is written)
+    constexpr int GB = 4;
+    for (int e0 = 0; e0 < nc; e0 += 64 * GB) {
+      int rows[GB];
+      double av[GB], bv[GB];
+#pragma unroll
+      for (int r = 0; r < GB; ++r) {
+        const int e = e0 + 64 * r + lane;
+        rows[r] = e < nc ? (int)lr[e] : -1;
+      }
+#pragma unroll
+      for (int r = 0; r < GB; ++r) {
+        const int row = rows[r] < 0 ? 0 : rows[r];
+        av[r] = sxj_at(s, row);
+        bv[r] = gld(s.xk + row);
+      }
+#pragma unroll
+      for (int r = 0; r < GB; ++r) {
+        const bool in = rows[r] >= 0;
+        const uint64_t key = key_of_pair(in, av[r], bv[r]);
+        const bool le = in && key <= plo;
+        const bool inw = in && key > plo && key <= phi;
+        S = fma(fabs(av[r]), le ? 1.0 : 0.0, S);
+        const uint64_t wm = __ballot(inw);
+        const int pos = nw + lanes_below(wm);
+        nw += __builtin_popcountll(wm);
+        if (inw) {
+          lk[pos] = key;
+          lr[pos] = (unsigned short)rows[r];
+        }
+      }
+    }
+    nw = uni_int(nw);
+  } else {
+    nw = nc;                                         // overflow
+  }
+  wave_lds_sync();
+  nwin = nw;
+  // FP64 sum of nonnegative terms: each lane adds at most T + ceil(nc / 64)
+  // terms in sequence, then six tree levels; the error is below
+  // (terms + 8) 2^-52 of the sum
+  const double St = wave_sum_dbl(S);
+  const double dlt = (double)(T + ((min(nc, lcap) + 63) >> 6) + 8) * 0x1p-52 * St;
+  SA = fixed_floor(St - dlt, s.e0);
+  SB = fixed_floor(St + dlt, s.e0) + 1;
+}
+
+// The side of the minimiser of segment (j, k) at penalty lam from the sign
+// sums dz = (D_jk, Zr_jk): 0 when 0 minimises g_jk, 1 negative, 2 positive,
+// 3 undecided (the exact pass decides).  Decision margin 2^-32 (W_j + lam):
+// far above the rounding error of the sign sums (at most ~n 2^-52 of W_j,
+// plus n 2^-1022 should the matrix unit flush subnormal terms: hence the
+// floor on the margin).  unc: the sums cannot be trusted for this segment.
+__device__ __forceinline__ int sign_sum_side(double2 dz, double lam, double Wj, bool unc) {
+  const double M = 0x1p-32 * (Wj + lam);
+  const double d1 = lam + dz.y + dz.x;               // >= 0  <=>  2A <= W + lambda
+  const double d2 = lam + dz.y - dz.x;               // >= 0  <=>  W <= 2B + lambda
+  if (unc || !(M >= 0x1p-1000)) return 3;
+  if (d1 > M && d2 > M) return 0;
+  if (d1 < -M) return 1;
+  if (d2 < -M) return 2;
+  return 3;
+}
+
+// The sign sums cannot decide segment (j, k) when a ratio could underflow to
+// 0 (exponent fields more than 1000 apart) or a sum is not finite.
+__device__ __forceinline__ bool sign_sums_unsure(const ColInfo &cj, const ColInfo &ck, double2 dz) {
+  const bool maybe_tiny = ck.nnz > 0 && cj.nnz > 0 && ck.bemin - cj.bemax < -1000;
+  return maybe_tiny || !isfinite(dz.x) || !isfinite(dz.y);
+}
+
+// Segments settled by the sign sums alone.  One thread per pair (j, k), one
+// wave per 64 consecutive k of a preserved column: where every penalty of the
+// problem has 0 as a minimiser (sign_sum_side, the segment kernel's own test),
+// writes v_k = 0, e_jk = the R64 mass of column k, row -1 for every penalty
+// and sets bit k & 63 of mask word (jj, k >> 6); the segment kernel skips such
+// segments.  wstart[b] = first mask word of problem b (mj ceil(m / 64) words,
+// mj = ncand with a candidate list, problem 0 only, else m).
+__global__ void __launch_bounds__(256)
+k_zero_segments(const ProbDesc *__restrict__ P, const int *__restrict__ wstart, int B, int total_words,
+                const double *__restrict__ lam_all, const ColInfo *__restrict__ ci,
+                const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
+                int *__restrict__ R, unsigned long long *__restrict__ mask, const int *__restrict__ cand,
+                const int *__restrict__ gate, int gate_on) {
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w >= total_words) return;
+  if (gate && *gate != gate_on) return;
+  const int b = find_owner(wstart, B, w);
+  const ProbDesc d = P[b];
+  const int wpr = (d.m + 63) >> 6;
+  const int wl = w - wstart[b];
+  const int jj = wl / wpr, k = (wl - jj * wpr) * 64 + lane;
+  const int j = cand ? cand[jj] : jj;
+  bool skip = false;
+  if (k < d.m && k != j) {
+    const ColInfo cj = ci[d.col_off + j], ck = ci[d.col_off + k];
+    if (!cj.flags && !ck.flags) {
+      const double2 dz = DZ[d.pair_off + (long long)j * d.m + k];
+      const bool unc = sign_sums_unsure(cj, ck, dz);
+      const double *lam = lam_all + d.lam_off;
+      skip = true;
+      for (int t = 0; t < d.L && skip; ++t) skip = sign_sum_side(dz, lam[t], cj.W, unc) == 0;
+      if (skip) {
+        const long long mm = (long long)d.m * d.m, base = d.ws_off + (long long)j * d.m + k;
+        for (int t = 0; t < d.L; ++t) {
+          V[base + t * mm] = 0.0;
+          E[base + t * mm] = ck.W;
+          R[base + t * mm] = -1;
+        }
+      }
+    }
+  }
+  const unsigned long long bits = __ballot(skip);
+  if (lane == 0) mask[d.mask_off + wl] = bits;
 }
 
 // exact A (negative ratios), B (non-positive), counts, one sample per side
@@ -874,7 +1092,8 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
                                          const double2 *__restrict__ DZ, int j, int kbeg, int kend,
                                          double *__restrict__ V,
                                          double *__restrict__ E, int *__restrict__ R, int *__restrict__ segflags,
-                                         int lcap, int sxj_rows, unsigned char *smem) {
+                                         const unsigned long long *__restrict__ maskrow, int lcap, int sxj_rows,
+                                         unsigned char *smem) {
   const int T = (n + 63) >> 6;
   // column j in LDS when the launch reserved room for it (n <= sxj_rows),
   // else read from global memory (it stays in L2 across the item's k)
@@ -895,6 +1114,13 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
   const double *__restrict__ sxj = kLdsJ ? (const double *)sxj_lds : xjg;
   for (int t = threadIdx.x; t < L; t += blockDim.x) slam[t] = lambda_fixed(lam[t], cj.e0);
   if (threadIdx.x == 0) *knext = kbeg;
+  // the item's words of the zero-segment mask (segments settled by
+  // k_zero_segments are skipped)
+  __shared__ unsigned long long smask[SEG_MASK_WORDS];
+  const int w0 = kbeg >> 6, nwords = kend > kbeg ? ((kend - 1) >> 6) - w0 + 1 : 0;
+  const bool use_mask = maskrow != nullptr && nwords <= SEG_MASK_WORDS;
+  if (use_mask)
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) smask[w] = maskrow[w0 + w];
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -947,6 +1173,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     if (lane == 0) k = atomicAdd(knext, 1);
     k = uni_int(__shfl(k, 0));
     if (k >= kend) break;
+    if (use_mask && ((smask[(k >> 6) - w0] >> (k & 63)) & 1ull)) continue;
     const long long base = (long long)j * m + k;
     if (k == j || cj.flags) {
       if (lane == 0) {
@@ -961,13 +1188,13 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     const ColInfo ck = ci[k];
     const SegIO s{X + (long long)k * ld, sxj, n, T, Tp, cj.e0, lane, kLdsJ};
     const double Wk = ck.W;
+    const bool fast_seg = fast_columns(cj) && fast_columns(ck);
 
     // 1. sign sums.  |x_ik / x_ij| can underflow to 0 only if the exponent
     // fields differ by more than 1000: the column ranges rule that out for the
     // whole segment in the usual case, else the exact pass decides.
-    const bool maybe_tiny = ck.nnz > 0 && cj.nnz > 0 && ck.bemin - cj.bemax < -1000;
     const double2 dz = DZ[(long long)j * m + k];
-    const bool unc = maybe_tiny || !isfinite(dz.x) || !isfinite(dz.y);
+    const bool unc = sign_sums_unsure(cj, ck, dz);
 
     bool have_exact = false;
     ExactSides ex;
@@ -983,18 +1210,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         const int t = g0 + lane;
         const bool in = t < L;
         int side = 0;
-        if (in) {
-          const double lamt = lam[t];
-          // decision margin 2^-32 (W + lambda), as below
-          const double M = 0x1p-32 * (Wd + lamt);
-          const double d1 = lamt + dz.y + dz.x;
-          const double d2 = lamt + dz.y - dz.x;
-          if (unc || !(M >= 0x1p-1000)) side = 3;
-          else if (d1 > M && d2 > M) side = 0;
-          else if (d1 < -M) side = 1;
-          else if (d2 < -M) side = 2;
-          else side = 3;
-        }
+        if (in) side = sign_sum_side(dz, lam[t], Wd, unc);
         if (__ballot(side == 3)) {
           if (!have_exact) {
             ex = exact_sides(s);
@@ -1013,19 +1229,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       }
     } else {
       for (int t = 0; t < L; ++t) {
-        const double lamt = lam[t];
-        // decision margin 2^-32 (W + lambda): far above the rounding error of
-        // the sign sums (at most ~n 2^-52 of W, plus n 2^-1022 should the
-        // matrix unit flush subnormal terms: hence the floor on M)
-        const double M = 0x1p-32 * (Wd + lamt);
-        const double d1 = lamt + dz.y + dz.x;        // >= 0  <=>  2A <= W + lambda
-        const double d2 = lamt + dz.y - dz.x;        // >= 0  <=>  W <= 2B + lambda
-        int side;
-        if (unc || !(M >= 0x1p-1000)) side = 3;
-        else if (d1 > M && d2 > M) side = 0;
-        else if (d1 < -M) side = 1;
-        else if (d2 < -M) side = 2;
-        else side = 3;
+        int side = sign_sum_side(dz, lam[t], Wd, unc);
         if (side == 3) {
           if (!have_exact) {
             ex = exact_sides(s);
@@ -1102,125 +1306,166 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         if (plo > khi0) plo = khi0;
         if (phi < plo) phi = plo;
 
-        // exact pass: weight at or below the window; the window's elements
-        // go to the LDS list (in row order)
-        // the weight below the window in three FP64 sums of 37-bit chunks
-        // (whole numbers below 2^53: every add is exact)
-        double c0s = 0.0, c1s = 0.0, c2s = 0.0;
-        int nwin = 0;
-        // columns j and k are read one slot ahead so the loads overlap the
-        // divide; the weight reuses x_ij
-        // (one penalty: rows past n read 0, key NONE and no weight; several:
-        // clamped to row 0, which spills less there)
         const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, n), rj = col_rsrc(s.lds ? s.xk : s.sxj, n);
-        auto ldj = [&](int i) { return kMulti ? sxj_at(s, i < n ? i : 0) : sxj_pad(s, rj, i); };
-        auto ldk = [&](int i) { return kMulti ? gld(s.xk + (i < n ? i : 0)) : col_ld(rk, i * 8); };
-        double anext = ldj(lane), bnext = ldk(lane);
-        for (int tt = 0; tt < T; ++tt) {
-          const int i = lane + 64 * tt;
-          const double a = anext, b = bnext;
-          if (tt + 1 < T) {
-            anext = ldj(i + 64);
-            bnext = ldk(i + 64);
+        // columns read through the range-checked descriptor (0 past row n)
+        // or the zero-padded LDS copy: no clamps
+        auto ldjp = [&](int i) { return sxj_pad(s, rj, i); };
+        auto ldkp = [&](int i) { return col_ld(rk, i * 8); };
+        // the division-free pass first; the exact pass when the columns'
+        // ranges rule the fast one out, or when the weight below the window,
+        // known from it only within an interval, leaves the selection open
+        bool use_fast = fast_seg;
+        bool ovf = false;
+        while (true) {
+          int nwin = 0;
+          u128 SlwA, SlwB;
+          if (use_fast) {
+            fast_window_pass(s, ldjp, ldkp, plo, phi, lk, lr, lcap, nwin, SlwA, SlwB);
+          } else {
+            // exact pass: weight at or below the window; the window's
+            // elements go to the LDS list (in row order).  The weight below
+            // the window in three FP64 sums of 37-bit chunks (whole numbers
+            // below 2^53: every add is exact)
+            double c0s = 0.0, c1s = 0.0, c2s = 0.0;
+            // columns j and k are read one slot ahead so the loads overlap
+            // the divide; the weight reuses x_ij (one penalty: rows past n
+            // read 0, key NONE and no weight; several: clamped to row 0,
+            // which spills less there)
+            auto ldj = [&](int i) { return kMulti ? sxj_at(s, i < n ? i : 0) : ldjp(i); };
+            auto ldk = [&](int i) { return kMulti ? gld(s.xk + (i < n ? i : 0)) : ldkp(i); };
+            double anext = ldj(lane), bnext = ldk(lane);
+            for (int tt = 0; tt < T; ++tt) {
+              const int i = lane + 64 * tt;
+              const double a = anext, b = bnext;
+              if (tt + 1 < T) {
+                anext = ldj(i + 64);
+                bnext = ldk(i + 64);
+              }
+              const uint64_t key = key_of_pair(i < n, a, b);
+              const bool valid = key != KEY_NONE;
+              const bool le_lo = valid && key <= plo;
+              const bool inwin = valid && key > plo && key <= phi;
+              {
+                double c0, c1, c2;
+                weight_chunks(a, s.e0, c0, c1, c2);
+                // masked adds as fma with a 0/1 factor: the same exact sums
+                // (whole numbers below 2^53; c 0 adds +0), one op each
+                const double fl = le_lo ? 1.0 : 0.0;
+                c0s = fma(c0, fl, c0s);
+                c1s = fma(c1, fl, c1s);
+                c2s = fma(c2, fl, c2s);
+              }
+              const uint64_t wm = __ballot(inwin);
+              const int pos = nwin + lanes_below(wm);
+              nwin += __builtin_popcountll(wm);
+              if (inwin && pos < lcap) {
+                lk[pos] = key;
+                lr[pos] = (unsigned short)i;
+              }
+            }
+            SlwA = SlwB = chunks_to_u128(wave_sum_dbl(c0s), wave_sum_dbl(c1s), wave_sum_dbl(c2s));
+            nwin = uni_int(nwin);
+            wave_lds_sync();
           }
-          const uint64_t key = key_of_pair(i < n, a, b);
-          const bool valid = key != KEY_NONE;
-          const bool le_lo = valid && key <= plo;
-          const bool inwin = valid && key > plo && key <= phi;
-          {
-            double c0, c1, c2;
-            weight_chunks(a, s.e0, c0, c1, c2);
-            // masked adds as fma with a 0/1 factor: the same exact sums
-            // (whole numbers below 2^53; c 0 adds +0), one op each
-            const double fl = le_lo ? 1.0 : 0.0;
-            c0s = fma(c0, fl, c0s);
-            c1s = fma(c1, fl, c1s);
-            c2s = fma(c2, fl, c2s);
+          if (nwin > lcap) {
+            ovf = true;
+            break;
           }
-          const uint64_t wm = __ballot(inwin);
-          const int pos = nwin + lanes_below(wm);
-          nwin += __builtin_popcountll(wm);
-          if (inwin && pos < lcap) {
-            lk[pos] = key;
-            lr[pos] = (unsigned short)i;
+          const u128 lamf = act ? slam[tl] : (u128)0;
+          const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
+          const bool want = mine && !hit;
+          const uint64_t wantm = __ballot(want);
+          u128 SloA = SlwA, SloB = SlwB;
+          bool amb = false;
+          if (__builtin_popcountll(wantm) == 1 && nwin > 128) {
+            // one target: only the quarter of the window that holds it is
+            // sorted.  Three sample keys around the target split the list;
+            // the exact weights below them pick the part (a contiguous range
+            // of the sorted order), which is compacted to the list's front.
+            const u128 tau1 = uni_u128(shfl_u128(tau, __builtin_ctzll(wantm)));
+            uint64_t piv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              int ix = (int)floor((wlo + 0.04 * (c - 1)) * SAMPLE_ROWS);
+              ix = ix < 0 ? 0 : (ix >= SAMPLE_ROWS ? SAMPLE_ROWS - 1 : ix);
+              piv[c] = uni_u64(shfl_u64((ix & 1) ? sb : sa, ix >> 1));
+            }
+            piv[1] = piv[1] < piv[0] ? piv[0] : piv[1];
+            piv[2] = piv[2] < piv[1] ? piv[1] : piv[2];
+            u128 a0 = 0, a1 = 0, a2 = 0;
+            for (int e = lane; e < nwin; e += 64) {
+              const uint64_t key = lk[e];
+              const u128 w = fixed_of_col(sxj_at(s, lr[e]), s.e0);
+              a0 += key < piv[0] ? w : (u128)0;
+              a1 += key < piv[1] ? w : (u128)0;
+              a2 += key < piv[2] ? w : (u128)0;
+            }
+            a0 = wave_sum_u128(a0);
+            a1 = wave_sum_u128(a1);
+            a2 = wave_sum_u128(a2);
+            const int c = (SlwA + a0 < tau1 ? 1 : 0) + (SlwA + a1 < tau1 ? 1 : 0) + (SlwA + a2 < tau1 ? 1 : 0);
+            const int cB = (SlwB + a0 < tau1 ? 1 : 0) + (SlwB + a1 < tau1 ? 1 : 0) + (SlwB + a2 < tau1 ? 1 : 0);
+            if (c != cB) {
+              amb = true;
+            } else {
+              const uint64_t plo2 = c == 0 ? 0 : piv[c - 1], phi2 = c == 3 ? KEY_NONE : piv[c];
+              const u128 ac = c == 0 ? (u128)0 : (c == 1 ? a0 : (c == 2 ? a1 : a2));
+              SloA = SlwA + ac;
+              SloB = SlwB + ac;
+              // stable in-place compaction: an element never moves above its
+              // own slot, so slots not yet read are never overwritten
+              int kept = 0;
+              for (int e0 = 0; e0 < nwin; e0 += 64) {
+                const int e = e0 + lane;
+                const bool in = e < nwin;
+                const uint64_t key = in ? lk[e] : 0;
+                const unsigned short row = in ? lr[e] : 0;
+                const bool keep = in && (c == 0 || key >= plo2) && (c == 3 || key < phi2);
+                const uint64_t km = __ballot(keep);
+                const int d = kept + lanes_below(km);
+                kept += __builtin_popcountll(km);
+                if (keep) {
+                  lk[d] = key;
+                  lr[d] = row;
+                }
+              }
+              nwin = uni_int(kept);
+              wave_lds_sync();
+            }
           }
+          if (!amb) {
+            const int N = wave_sort_list(lk, lr, nwin, lane);
+            u128 tot, incl;
+            wave_list_sums(s, lk, lr, N >> 6, tot, incl);
+            uint64_t k2 = KEY_NONE;
+            int r2 = -1;
+            bool h2 = false;
+            wave_resolve(s, lk, lr, N >> 6, SloA, tot, incl, want, tau, k2, r2, h2);
+            if (SloA != SloB) {
+              // the answer must not depend on where in [SloA, SloB] the
+              // exact weight below the list lies
+              uint64_t k3 = KEY_NONE;
+              int r3 = -1;
+              bool h3 = false;
+              wave_resolve(s, lk, lr, N >> 6, SloB, tot, incl, want, tau, k3, r3, h3);
+              amb = __ballot(want && (h2 != h3 || k2 != k3 || r2 != r3)) != 0;
+            }
+            if (!amb && h2) {
+              okey = k2;
+              orow = r2;
+              hit = true;
+            }
+          }
+          wave_lds_sync();
+          if (!amb) break;
+          use_fast = false;                          // redo the pass exactly
         }
-        const u128 Slw = chunks_to_u128(wave_sum_dbl(c0s), wave_sum_dbl(c1s), wave_sum_dbl(c2s));
-        nwin = uni_int(nwin);
-        wave_lds_sync();
-        if (nwin > lcap) {
+        if (ovf) {
           // the list cannot hold the window: after the shared window, retry
           // each penalty with its own; a single penalty goes to the rounds
           if (pass == 0 && __builtin_popcountll(nzg) == 1) break;
           continue;
         }
-        const u128 lamf = act ? slam[tl] : (u128)0;
-        const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
-        const bool want = mine && !hit;
-        const uint64_t wantm = __ballot(want);
-        u128 Slo = Slw;
-        if (__builtin_popcountll(wantm) == 1 && nwin > 128) {
-          // one target: only the quarter of the window that holds it is
-          // sorted.  Three sample keys around the target split the list; the
-          // exact weights below them pick the part (a contiguous range of the
-          // sorted order), which is compacted to the list's front.
-          const u128 tau1 = uni_u128(shfl_u128(tau, __builtin_ctzll(wantm)));
-          uint64_t piv[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            int ix = (int)floor((wlo + 0.04 * (c - 1)) * SAMPLE_ROWS);
-            ix = ix < 0 ? 0 : (ix >= SAMPLE_ROWS ? SAMPLE_ROWS - 1 : ix);
-            piv[c] = uni_u64(shfl_u64((ix & 1) ? sb : sa, ix >> 1));
-          }
-          piv[1] = piv[1] < piv[0] ? piv[0] : piv[1];
-          piv[2] = piv[2] < piv[1] ? piv[1] : piv[2];
-          u128 a0 = 0, a1 = 0, a2 = 0;
-          for (int e = lane; e < nwin; e += 64) {
-            const uint64_t key = lk[e];
-            const u128 w = fixed_of_col(sxj_at(s, lr[e]), s.e0);
-            a0 += key < piv[0] ? w : (u128)0;
-            a1 += key < piv[1] ? w : (u128)0;
-            a2 += key < piv[2] ? w : (u128)0;
-          }
-          a0 = wave_sum_u128(a0);
-          a1 = wave_sum_u128(a1);
-          a2 = wave_sum_u128(a2);
-          const int c = (Slw + a0 < tau1 ? 1 : 0) + (Slw + a1 < tau1 ? 1 : 0) + (Slw + a2 < tau1 ? 1 : 0);
-          const uint64_t plo2 = c == 0 ? 0 : piv[c - 1], phi2 = c == 3 ? KEY_NONE : piv[c];
-          Slo = Slw + (c == 0 ? (u128)0 : (c == 1 ? a0 : (c == 2 ? a1 : a2)));
-          // stable in-place compaction: an element never moves above its own
-          // slot, so slots not yet read are never overwritten
-          int kept = 0;
-          for (int e0 = 0; e0 < nwin; e0 += 64) {
-            const int e = e0 + lane;
-            const bool in = e < nwin;
-            const uint64_t key = in ? lk[e] : 0;
-            const unsigned short row = in ? lr[e] : 0;
-            const bool keep = in && (c == 0 || key >= plo2) && (c == 3 || key < phi2);
-            const uint64_t km = __ballot(keep);
-            const int d = kept + lanes_below(km);
-            kept += __builtin_popcountll(km);
-            if (keep) {
-              lk[d] = key;
-              lr[d] = row;
-            }
-          }
-          nwin = uni_int(kept);
-          wave_lds_sync();
-        }
-        const int N = wave_sort_list(lk, lr, nwin, lane);
-        u128 tot, incl;
-        wave_list_sums(s, lk, lr, N >> 6, tot, incl);
-        uint64_t k2 = KEY_NONE;
-        int r2 = -1;
-        bool h2 = false;
-        wave_resolve(s, lk, lr, N >> 6, Slo, tot, incl, want, tau, k2, r2, h2);
-        if (h2) {
-          okey = k2;
-          orow = r2;
-          hit = true;
-        }
-        wave_lds_sync();
         // the shared window held: the targets it missed go to the rounds
         if (pass == 0) break;
       }
@@ -1334,7 +1579,8 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
             const ColInfo *__restrict__ ci,
             const double2 *__restrict__ DZ, double *__restrict__ V, double *__restrict__ E,
             int *__restrict__ R, int *__restrict__ segflags, const int *__restrict__ cand, int ncand,
-            const int *__restrict__ gate, int gate_on, int lcap, int sxj_rows) {
+            const int *__restrict__ gate, int gate_on, const unsigned long long *__restrict__ segmask, int lcap,
+            int sxj_rows) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_item, s_tried;                  // s_tried: XCD partitions found empty
   if (gate && *gate != gate_on) return;
@@ -1360,13 +1606,16 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
     __syncthreads();
     if (q < 0) break;
     WorkItem it;
+    int jj;                                        // row of the item's column in the mask
     if (items) {
       it = items[q];
+      jj = it.j;
     } else {
       const int m0 = P[0].m;
       const int mj = cand ? ncand : m0;
       const int x = q / nitems, c = q % nitems;
-      const int part = x * chunks + c / mj, jj = c % mj;
+      const int part = x * chunks + c / mj;
+      jj = c % mj;
       const int kchunk = (m0 + SEG_XCDS * chunks - 1) / (SEG_XCDS * chunks);
       it.b = 0;
       it.j = cand ? cand[jj] : jj;
@@ -1375,9 +1624,11 @@ k_seg_batch(const ProbDesc *__restrict__ P, const WorkItem *__restrict__ items, 
       if (it.kbeg >= it.kend) continue;            // an empty part of a narrow matrix
     }
     const ProbDesc d = P[it.b];
+    const unsigned long long *maskrow =
+        segmask ? segmask + d.mask_off + (long long)jj * ((d.m + 63) >> 6) : nullptr;
     seg_item<kLdsJ, kMulti>(d.X, d.n, d.m, d.ld, ci + d.col_off, lam_all + d.lam_off, d.L, DZ + d.pair_off, it.j,
-                    it.kbeg, it.kend, V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, lcap,
-                    sxj_rows, smem);
+                    it.kbeg, it.kend, V + d.ws_off, E + d.ws_off, R + d.ws_off, segflags + d.col_off, maskrow,
+                    lcap, sxj_rows, smem);
   }
 }
 

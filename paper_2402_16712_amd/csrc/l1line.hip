@@ -285,9 +285,10 @@ static int check_problem(const l1line_problem &p) {
 struct BatchLayout {
   int B, nitems, ksplit, nmax, Lmax;
   int xstart[SEG_XCDS + 1];   // explicit items: XCD x owns [xstart[x], xstart[x + 1])
-  long long total_cols, total_z, total_out, total_ws, total_lam, total_pairs, total_tiles;
-  size_t o_desc, o_colstart, o_zstart, o_ostart, o_tstart, o_lam, o_items, o_counter, o_xstart, meta_bytes;
-  size_t o_ci, o_segflags, o_DZ, o_V, o_E, o_R, o_Z, o_zflag, bytes;
+  long long total_cols, total_z, total_out, total_ws, total_lam, total_pairs, total_tiles, total_words;
+  size_t o_desc, o_colstart, o_zstart, o_ostart, o_tstart, o_wstart, o_lam, o_items, o_counter, o_xstart,
+      meta_bytes;
+  size_t o_ci, o_segflags, o_DZ, o_mask, o_V, o_E, o_R, o_Z, o_zflag, bytes;
 };
 
 static void layout_sizes(BatchLayout &Ly) {
@@ -298,6 +299,7 @@ static void layout_sizes(BatchLayout &Ly) {
   Ly.o_zstart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_ostart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_tstart = take(sizeof(int) * (Ly.B + 1));
+  Ly.o_wstart = take(sizeof(int) * (Ly.B + 1));
   Ly.o_lam = take(sizeof(double) * Ly.total_lam);
   Ly.o_items = take(sizeof(WorkItem) * (Ly.ksplit ? 0 : Ly.nitems));
   Ly.o_counter = take(sizeof(int) * 16);
@@ -306,6 +308,7 @@ static void layout_sizes(BatchLayout &Ly) {
   Ly.o_ci = take(sizeof(ColInfo) * Ly.total_cols);
   Ly.o_segflags = take(sizeof(int) * Ly.total_cols);
   Ly.o_DZ = take(2 * sizeof(double) * Ly.total_pairs);
+  Ly.o_mask = take(sizeof(unsigned long long) * Ly.total_words);
   Ly.o_V = take(sizeof(double) * Ly.total_ws);
   Ly.o_E = take(sizeof(double) * Ly.total_ws);
   Ly.o_R = take(sizeof(int) * Ly.total_ws);
@@ -371,12 +374,13 @@ static int plan_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, co
     Ly.total_pairs += p.m * p.m;
     const int64_t mj = (ro.cand && B == 1) ? ro.ncand : p.m;
     Ly.total_tiles += ((mj + SS_TILE - 1) / SS_TILE) * ((p.m + SS_TILE - 1) / SS_TILE);
+    Ly.total_words += mj * ((p.m + 63) / 64);
     Ly.nmax = std::max<int>(Ly.nmax, (int)p.n);
     Ly.Lmax = std::max<int>(Ly.Lmax, (int)p.L);
     total_cost += (double)p.n * (double)p.m * (double)p.m;
   }
   if (Ly.total_cols > (1ll << 30) || Ly.total_z > (1ll << 30) || Ly.total_out > (1ll << 30) ||
-      Ly.total_tiles > (1ll << 30))
+      Ly.total_tiles > (1ll << 30) || Ly.total_words > (1ll << 30))
     return L1LINE_EINVAL;
 
   // work items: split every problem's k range so the whole batch offers
@@ -446,7 +450,7 @@ static int plan_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, co
 
 // The problem descriptor of problem b with the batch's workspace offsets.
 struct MetaCursor {
-  long long col, z, out, wsoff, lamoff, pairoff, tiles;
+  long long col, z, out, wsoff, lamoff, pairoff, tiles, words;
 };
 static ProbDesc prob_desc(const l1line_problem &p, const MetaCursor &c) {
   ProbDesc q;
@@ -461,6 +465,7 @@ static ProbDesc prob_desc(const l1line_problem &p, const MetaCursor &c) {
   q.ws_off = c.wsoff;
   q.z_off = c.z;
   q.pair_off = c.pairoff;
+  q.mask_off = c.words;
   q.Vout = p.V;
   q.Jout = (long long *)p.J;
   q.OBJout = p.OBJ;
@@ -478,6 +483,7 @@ static void advance(MetaCursor &c, const l1line_problem &p, const RunOpts &ro, i
   c.pairoff += p.m * p.m;
   const int64_t mj = (ro.cand && B == 1) ? ro.ncand : p.m;
   c.tiles += ((mj + SS_TILE - 1) / SS_TILE) * ((p.m + SS_TILE - 1) / SS_TILE);
+  c.words += mj * ((p.m + 63) / 64);
 }
 
 // The metadata block (the first Ly.meta_bytes of the workspace) in host memory h.
@@ -486,9 +492,9 @@ static void fill_meta(char *h, const BatchLayout &Ly, const l1line_problem *prob
   memset(h, 0, Ly.meta_bytes);
   ProbDesc *hd = (ProbDesc *)(h + Ly.o_desc);
   int *hcol = (int *)(h + Ly.o_colstart), *hz = (int *)(h + Ly.o_zstart), *ho = (int *)(h + Ly.o_ostart);
-  int *ht = (int *)(h + Ly.o_tstart);
+  int *ht = (int *)(h + Ly.o_tstart), *hw = (int *)(h + Ly.o_wstart);
   double *hlam = (double *)(h + Ly.o_lam);
-  MetaCursor c = {0, 0, 0, 0, 0, 0, 0};
+  MetaCursor c = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t b = 0; b < B; ++b) {
     const l1line_problem &p = probs[b];
     hd[b] = prob_desc(p, c);
@@ -496,11 +502,13 @@ static void fill_meta(char *h, const BatchLayout &Ly, const l1line_problem *prob
     hz[b] = (int)c.z;
     ho[b] = (int)c.out;
     ht[b] = (int)c.tiles;
+    hw[b] = (int)c.words;
     for (int64_t t = 0; t < p.L; ++t) hlam[c.lamoff + t] = p.lambdas[t];
     advance(c, p, ro, B);
   }
   hcol[B] = (int)c.col;
   ht[B] = (int)c.tiles;
+  hw[B] = (int)c.words;
   hz[B] = (int)c.z;
   ho[B] = (int)c.out;
   if (!items.empty()) memcpy(h + Ly.o_items, items.data(), sizeof(WorkItem) * items.size());
@@ -516,7 +524,8 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
                       BatchPtrs *outp) {
   const ProbDesc *dP = (const ProbDesc *)(d + Ly.o_desc);
   const int *dcol = (const int *)(d + Ly.o_colstart), *dz = (const int *)(d + Ly.o_zstart),
-            *dout = (const int *)(d + Ly.o_ostart), *dtile = (const int *)(d + Ly.o_tstart);
+            *dout = (const int *)(d + Ly.o_ostart), *dtile = (const int *)(d + Ly.o_tstart),
+            *dwst = (const int *)(d + Ly.o_wstart);
   const double *dlam = (const double *)(d + Ly.o_lam);
   const WorkItem *ditems = Ly.ksplit ? nullptr : (const WorkItem *)(d + Ly.o_items);
   int *dcounter = (int *)(d + Ly.o_counter);
@@ -526,6 +535,7 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
   double *dV = (double *)(d + Ly.o_V), *dE = (double *)(d + Ly.o_E), *dZ = (double *)(d + Ly.o_Z);
   int *dR = (int *)(d + Ly.o_R), *dzflag = (int *)(d + Ly.o_zflag);
   double2 *dDZ = (double2 *)(d + Ly.o_DZ);
+  unsigned long long *dmask = (unsigned long long *)(d + Ly.o_mask);
   if (outp) *outp = BatchPtrs{dV, dR, dci};
   l1line_ctx pc = prof ? ctx : nullptr;
 
@@ -560,6 +570,12 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
     hipLaunchKernelGGL(k_signsum_batch, dim3((unsigned)Ly.total_tiles), dim3(256), 0, ls, dP, dtile, (int)B,
                        (B == 1) ? ro.cand : nullptr, ro.ncand, dDZ, ro.gate, ro.gate_on);
   }
+  {
+    ProfScope ps(pc, ls, "zero_seg");
+    hipLaunchKernelGGL(k_zero_segments, dim3((unsigned)((Ly.total_words + 3) / 4)), dim3(256), 0, ls, dP, dwst,
+                       (int)B, (int)Ly.total_words, dlam, dci, dDZ, dV, dE, dR, dmask,
+                       (B == 1) ? ro.cand : nullptr, ro.gate, ro.gate_on);
+  }
   if (t0) HIP_TRY(hipEventRecord(t0, ls));
   {
     ProfScope ps(pc, ls, "fit_seg");
@@ -570,7 +586,7 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
     hipLaunchKernelGGL(kseg, dim3((unsigned)grid_seg), dim3(64 * SEG_WAVES), lds, ls, dP, ditems,
                        Ly.nitems, Ly.ksplit, dcounter, dxstart, dlam, dci, dDZ, dV, dE, dR, dsegflags, ro.cand,
                        ro.ncand,
-                       ro.gate, ro.gate_on, lcap, sxj_rows);
+                       ro.gate, ro.gate_on, dmask, lcap, sxj_rows);
   }
   if (t1) HIP_TRY(hipEventRecord(t1, ls));
   {
@@ -894,6 +910,9 @@ __global__ void k_meta_single(ProbDesc pd, double lam, long long tiles, BatchLay
   o[1] = 1;
   t[0] = 0;
   t[1] = (int)tiles;
+  int *ws = (int *)(d + Ly.o_wstart);
+  ws[0] = 0;
+  ws[1] = (int)Ly.total_words;
   *(double *)(d + Ly.o_lam) = lam;
   int *xs = (int *)(d + Ly.o_xstart);
   for (int x = 0; x <= SEG_XCDS; ++x) xs[x] = Ly.xstart[x];
@@ -917,7 +936,7 @@ static int fit_noalloc_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   st = plan_batch(ctx, &p, 1, ctx->tune, kNoOpts, Ly, items);
   if (st) return st;
   if (Ly.bytes > NOALLOC_BYTES || !items.empty()) return L1LINE_ESIZE;
-  const MetaCursor c0 = {0, 0, 0, 0, 0, 0, 0};
+  const MetaCursor c0 = {0, 0, 0, 0, 0, 0, 0, 0};
   MetaCursor c1 = c0;
   advance(c1, p, kNoOpts, 1);
   char *d = (char *)ctx->scratch;
