@@ -313,3 +313,100 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
+
+// ------------------------------------------------------ VALU lane exchanges
+// x of lane (lane ^ m), m in {1, 2, 4, 8, 16, 32} (a constant once the
+// caller's loop is unrolled), without an LDS round trip: DPP quad permutes
+// for 1 and 2, two row shifts merged through bank masks for 4, the row
+// rotation by 8, and gfx950's row swaps (v_permlane16_swap,
+// v_permlane32_swap) for 16 and 32.  Lane layouts checked on the hardware.
+// Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t xswap32(uint32_t x, int m) {
+  const int v = (int)x;
+  switch (m) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 4: {
+      const int t = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0x5, false);    // row_shl:4, banks 0 and 2
+      return (uint32_t)__builtin_amdgcn_update_dpp(t, v, 0x114, 0xF, 0xA, false); // row_shr:4, banks 1 and 3
+    }
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    case 16: {
+      const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+      return (threadIdx.x & 16) ? p[0] : p[1];
+    }
+    default: {
+      const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+      return (threadIdx.x & 32) ? p[0] : p[1];
+    }
+  }
+}
+__device__ __forceinline__ uint64_t xswap64(uint64_t x, int m) {
+  return ((uint64_t)xswap32((uint32_t)(x >> 32), m) << 32) | xswap32((uint32_t)x, m);
+}
+__device__ __forceinline__ double xswapd(double x, int m) {
+  return __longlong_as_double((long long)xswap64((uint64_t)__double_as_longlong(x), m));
+}
+__device__ __forceinline__ u128 xswap128(u128 x, int m) {
+  return (((u128)xswap64((uint64_t)(x >> 64), m)) << 64) | xswap64((uint64_t)x, m);
+}
+__device__ __forceinline__ u128 readlane_u128(u128 x, int l) {
+  const uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
+  const uint32_t w0 = __builtin_amdgcn_readlane((int)(uint32_t)lo, l), w1 = __builtin_amdgcn_readlane((int)(uint32_t)(lo >> 32), l),
+                 w2 = __builtin_amdgcn_readlane((int)(uint32_t)hi, l), w3 = __builtin_amdgcn_readlane((int)(uint32_t)(hi >> 32), l);
+  return (((u128)(((uint64_t)w3 << 32) | w2)) << 64) | (((uint64_t)w1 << 32) | w0);
+}
+
+// The same reductions, scans and sorts as above through VALU exchanges
+// (the segment kernel's wave-convergent hot paths).
+__device__ __forceinline__ u128 wave_sum_u128_x(u128 x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += xswap128(x, d);
+  return uni_u128(x);
+}
+
+__device__ __forceinline__ double wave_sum_dbl_x(double x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = x + xswapd(x, d);
+  return __longlong_as_double((long long)uni_u64((uint64_t)__double_as_longlong(x)));
+}
+
+// R64 tree (p[l] = p[l] + p[l + d] for d = 32..1, the result in lane 0): for
+// l < d the partner l ^ d is l + d, so lane 0 adds the same values in the
+// same order as wave_r64_tree.
+__device__ __forceinline__ double wave_r64_tree_x(double p) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) p = p + xswapd(p, d);
+  return p;
+}
+
+// inclusive scan: at level d a lane adds the total of the partner half-block
+// when its own bit d is set (exact integer adds)
+__device__ __forceinline__ u128 wave_incl_scan_u128_x(u128 x, int lane) {
+  u128 tot = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const u128 o = xswap128(tot, d);
+    x += (lane & d) ? o : (u128)0;
+    tot += o;
+  }
+  return x;
+}
+
+__device__ __forceinline__ void wave_sort_key_row_x(uint64_t &key, int &row, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t ok = xswap64(key, stride);
+      const int orow = (int)xswap32((uint32_t)row, stride);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      const bool other_less = ok < key || (ok == key && orow < row);
+      const bool other_greater = ok > key || (ok == key && orow > row);
+      const bool take = (lower == up) ? other_less : other_greater;
+      key = take ? ok : key;
+      row = take ? orow : row;
+    }
+  }
+}

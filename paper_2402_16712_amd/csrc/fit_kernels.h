@@ -467,7 +467,7 @@ __device__ __forceinline__ void wave_list_sums(const SegIO &s, const uint64_t *l
     const bool valid = lk[e] != KEY_NONE;
     tot += seg_weight(s, valid ? (int)lr[e] : 0, valid);
   }
-  incl = wave_incl_scan_u128(tot, s.lane);
+  incl = wave_incl_scan_u128_x(tot, s.lane);
 }
 
 // Lane-parallel resolution: every lane with a target (active) finds the first
@@ -507,6 +507,46 @@ __device__ __forceinline__ void wave_resolve(const SegIO &s, const uint64_t *lk,
   }
 }
 
+// Resolution of one target tau, the same on every lane: the entry's owner is
+// the first lane whose inclusive sum, counted from Slo, reaches tau (one
+// ballot), and a walk over that lane's E entries finds the entry.  The exact
+// weight below the list is known to lie in [SloA, SloB]; amb = the answer is
+// not the same at both ends (then nothing is reported).
+__device__ __forceinline__ void wave_resolve_one(const SegIO &s, const uint64_t *lk, const unsigned short *lr,
+                                                 int E, u128 SloA, u128 SloB, u128 tot, u128 incl, u128 tau,
+                                                 uint64_t &okey, int &orow, bool &hit, bool &amb) {
+  auto find = [&](u128 Slo, uint64_t &k, int &r) -> bool {
+    const uint64_t owner = __ballot(Slo + incl >= tau);
+    if (!(tau > Slo) || owner == 0) return false;
+    const int lo = __builtin_ctzll(owner);
+    u128 run = Slo + readlane_u128(incl, lo) - readlane_u128(tot, lo);
+    for (int q = 0; q < E; ++q) {
+      const int e = E * lo + q;
+      const uint64_t key = lk[e];
+      const bool valid = key != KEY_NONE;
+      run += seg_weight(s, valid ? (int)lr[e] : 0, valid);
+      if (valid && run >= tau) {
+        k = key;
+        r = (int)lr[e];
+        return true;
+      }
+    }
+    return false;
+  };
+  uint64_t k2 = KEY_NONE;
+  int r2 = -1;
+  hit = find(SloA, k2, r2);
+  amb = false;
+  if (SloB != SloA) {
+    uint64_t k3 = KEY_NONE;
+    int r3 = -1;
+    const bool h3 = find(SloB, k3, r3);
+    amb = h3 != hit || k3 != k2 || r3 != r2;
+  }
+  okey = k2;
+  orow = r2;
+}
+
 // e_jk = R64 over i of |x_ik - fl(v x_ij)| (result in lane 0).  kPad: rows
 // past n are read as 0 instead of masked (the single-penalty kernels; the
 // several-penalty ones keep the masked loop, which spills less there)
@@ -522,12 +562,15 @@ __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
     const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, s.n), rj = col_rsrc(s.lds ? s.xk : s.sxj, s.n);
     int t0 = 0;
     for (; t0 + RB <= s.T; t0 += RB) {
-      double xk[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) xk[r] = col_ld(rk, (s.lane + 64 * (t0 + r)) * 8);
+      double xk[RB], xj[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const double prod = v * sxj_pad(s, rj, s.lane + 64 * (t0 + r));
+        xk[r] = col_ld(rk, (s.lane + 64 * (t0 + r)) * 8);
+        xj[r] = sxj_pad(s, rj, s.lane + 64 * (t0 + r));
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const double prod = v * xj[r];
         const double d = xk[r] - prod;
         p = p + fabs(d);
       }
@@ -538,7 +581,7 @@ __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
       const double d = col_ld(rk, i * 8) - prod;
       p = p + fabs(d);
     }
-    return wave_r64_tree(p);
+    return wave_r64_tree_x(p);
   }
   // (an infinite ratio: v 0 is NaN, so the rows past n are masked)
   for (int t0 = 0; t0 < s.T; t0 += RB) {
@@ -557,7 +600,7 @@ __device__ __forceinline__ double wave_residual(const SegIO &s, double v) {
       p = p + (in ? fabs(d) : 0.0);
     }
   }
-  return wave_r64_tree(p);
+  return wave_r64_tree_x(p);
 }
 
 // G residuals in one pass over the rows (the same sums as wave_residual,
@@ -589,7 +632,7 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
       }
     }
 #pragma unroll
-    for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree(p[r]), 0);
+    for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree_x(p[r]), 0);
     return;
   }
   const int l0 = s.lane < s.n ? s.lane : 0;
@@ -611,7 +654,7 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
     }
   }
 #pragma unroll
-  for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree(p[r]), 0);
+  for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree_x(p[r]), 0);
 }
 
 // Bitonic sort of 128 keys held two per lane (element 2*lane + r), ascending.
@@ -671,6 +714,57 @@ __device__ __forceinline__ void wave_sort2_kr(uint64_t &ka, int &ra, uint64_t &k
   }
 }
 
+// wave_sort2 and wave_sort2_kr through VALU lane exchanges (same networks)
+__device__ __forceinline__ void wave_sort2_x(uint64_t &a, uint64_t &b, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const bool up = ((2 * lane) & size) == 0;
+      if (stride == 1) {
+        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+        a = up ? lo : hi;
+        b = up ? hi : lo;
+      } else {
+        const int ls = stride >> 1;
+        const uint64_t oa = xswap64(a, ls), ob = xswap64(b, ls);
+        const bool keep_min = (((2 * lane) & stride) == 0) == up;
+        a = keep_min ? (oa < a ? oa : a) : (oa > a ? oa : a);
+        b = keep_min ? (ob < b ? ob : b) : (ob > b ? ob : b);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sort2_kr_x(uint64_t &ka, int &ra, uint64_t &kb, int &rb, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const bool up = ((2 * lane) & size) == 0;
+      if (stride == 1) {
+        const bool sw = (kb < ka || (kb == ka && rb < ra)) == up;
+        const uint64_t tk = ka;
+        const int tr = ra;
+        ka = sw ? kb : ka;
+        ra = sw ? rb : ra;
+        kb = sw ? tk : kb;
+        rb = sw ? tr : rb;
+      } else {
+        const int ls = stride >> 1;
+        const bool keep_min = (((2 * lane) & stride) == 0) == up;
+        const uint64_t oka = xswap64(ka, ls), okb = xswap64(kb, ls);
+        const int ora = (int)xswap32((uint32_t)ra, ls), orb = (int)xswap32((uint32_t)rb, ls);
+        const bool la = oka < ka || (oka == ka && ora < ra), lb = okb < kb || (okb == kb && orb < rb);
+        ka = la == keep_min ? oka : ka;
+        ra = la == keep_min ? ora : ra;
+        kb = lb == keep_min ? okb : kb;
+        rb = lb == keep_min ? orb : rb;
+      }
+    }
+  }
+}
+
 // Sorts the window list lk/lr[0, nlist) ascending in (key, row) and pads it
 // with (KEY_NONE, 0xFFFF) to N = the returned power of two (>= 64).  Lists of
 // up to 128 are sorted in registers (shuffles, no LDS round trips per stage)
@@ -680,7 +774,7 @@ __device__ __forceinline__ int wave_sort_list(uint64_t *lk, unsigned short *lr, 
   if (nlist <= 64) {
     uint64_t k = lane < nlist ? lk[lane] : KEY_NONE;
     int r = lane < nlist ? (int)lr[lane] : 0xFFFF;
-    wave_sort_key_row(k, r, lane);
+    wave_sort_key_row_x(k, r, lane);
     wave_lds_sync();
     lk[lane] = k;
     lr[lane] = (unsigned short)r;
@@ -690,7 +784,7 @@ __device__ __forceinline__ int wave_sort_list(uint64_t *lk, unsigned short *lr, 
   const int e = 2 * lane;
   uint64_t ka = e < nlist ? lk[e] : KEY_NONE, kb = e + 1 < nlist ? lk[e + 1] : KEY_NONE;
   int ra = e < nlist ? (int)lr[e] : 0xFFFF, rb = e + 1 < nlist ? (int)lr[e + 1] : 0xFFFF;
-  wave_sort2_kr(ka, ra, kb, rb, lane);
+  wave_sort2_kr_x(ka, ra, kb, rb, lane);
   wave_lds_sync();
   lk[e] = ka;
   lr[e] = (unsigned short)ra;
@@ -977,7 +1071,7 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
   // FP64 sum of nonnegative terms: each lane adds at most T + ceil(nc / 64)
   // terms in sequence, then six tree levels; the error is below
   // (terms + 8) 2^-52 of the sum
-  const double St = wave_sum_dbl(S);
+  const double St = wave_sum_dbl_x(S);
   const double dlt = (double)(T + ((min(nc, lcap) + 63) >> 6) + 8) * 0x1p-52 * St;
   SA = fixed_floor(St - dlt, s.e0);
   SB = fixed_floor(St + dlt, s.e0) + 1;
@@ -1257,7 +1351,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     const bool neg = sd == 1;
     const uint64_t klo0 = neg ? 0ull : KEY_ZERO, khi0 = neg ? KEY_ZERO - 1 : KEY_NONE - 1;
     uint64_t sa = seg_key(s, srow[lane]), sb = seg_key(s, srow[lane + 64]);
-    wave_sort2(sa, sb, lane);
+    wave_sort2_x(sa, sb, lane);
     int prev_row = -2;
     double prev_e = 0.0;
     // penalties in groups of 64, lane l holding the target of penalty 64 g + l
@@ -1363,7 +1457,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
                 lr[pos] = (unsigned short)i;
               }
             }
-            SlwA = SlwB = chunks_to_u128(wave_sum_dbl(c0s), wave_sum_dbl(c1s), wave_sum_dbl(c2s));
+            SlwA = SlwB = chunks_to_u128(wave_sum_dbl_x(c0s), wave_sum_dbl_x(c1s), wave_sum_dbl_x(c2s));
             nwin = uni_int(nwin);
             wave_lds_sync();
           }
@@ -1400,9 +1494,9 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
               a1 += key < piv[1] ? w : (u128)0;
               a2 += key < piv[2] ? w : (u128)0;
             }
-            a0 = wave_sum_u128(a0);
-            a1 = wave_sum_u128(a1);
-            a2 = wave_sum_u128(a2);
+            a0 = wave_sum_u128_x(a0);
+            a1 = wave_sum_u128_x(a1);
+            a2 = wave_sum_u128_x(a2);
             const int c = (SlwA + a0 < tau1 ? 1 : 0) + (SlwA + a1 < tau1 ? 1 : 0) + (SlwA + a2 < tau1 ? 1 : 0);
             const int cB = (SlwB + a0 < tau1 ? 1 : 0) + (SlwB + a1 < tau1 ? 1 : 0) + (SlwB + a2 < tau1 ? 1 : 0);
             if (c != cB) {
@@ -1440,15 +1534,21 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             uint64_t k2 = KEY_NONE;
             int r2 = -1;
             bool h2 = false;
-            wave_resolve(s, lk, lr, N >> 6, SloA, tot, incl, want, tau, k2, r2, h2);
-            if (SloA != SloB) {
-              // the answer must not depend on where in [SloA, SloB] the
-              // exact weight below the list lies
-              uint64_t k3 = KEY_NONE;
-              int r3 = -1;
-              bool h3 = false;
-              wave_resolve(s, lk, lr, N >> 6, SloB, tot, incl, want, tau, k3, r3, h3);
-              amb = __ballot(want && (h2 != h3 || k2 != k3 || r2 != r3)) != 0;
+            if constexpr (!kMulti) {
+              // one penalty: its target sits in lane 0
+              if (wantm & 1ull) wave_resolve_one(s, lk, lr, N >> 6, SloA, SloB, tot, incl, uni_u128(tau), k2, r2, h2, amb);
+              h2 = h2 && lane == 0;
+            } else {
+              wave_resolve(s, lk, lr, N >> 6, SloA, tot, incl, want, tau, k2, r2, h2);
+              if (SloA != SloB) {
+                // the answer must not depend on where in [SloA, SloB] the
+                // exact weight below the list lies
+                uint64_t k3 = KEY_NONE;
+                int r3 = -1;
+                bool h3 = false;
+                wave_resolve(s, lk, lr, N >> 6, SloB, tot, incl, want, tau, k3, r3, h3);
+                amb = __ballot(want && (h2 != h3 || k2 != k3 || r2 != r3)) != 0;
+              }
             }
             if (!amb && h2) {
               okey = k2;
