@@ -996,7 +996,7 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
   int nc = 0;
   // rows in batches of FB slots, every load of a batch issued before the
   // first is used (one slot at a time left the wave waiting on L2 latency)
-  constexpr int FB = 8;
+  constexpr int FB = 4;
   for (int t0 = 0; t0 < T; t0 += FB) {
     double av[FB], bv[FB];
 #pragma unroll
@@ -1189,6 +1189,9 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
                                          const unsigned long long *__restrict__ maskrow, int lcap, int sxj_rows,
                                          unsigned char *smem) {
   const int T = (n + 63) >> 6;
+  // penalties: the single-penalty instantiation has exactly one (one group,
+  // one pass, trip counts the compiler sees)
+  const int Lg = kMulti ? L : 1;
   // column j in LDS when the launch reserved room for it (n <= sxj_rows),
   // else read from global memory (it stays in L2 across the item's k)
   constexpr bool lds_j = kLdsJ;
@@ -1271,7 +1274,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     const long long base = (long long)j * m + k;
     if (k == j || cj.flags) {
       if (lane == 0) {
-        for (int t = 0; t < L; ++t) {
+        for (int t = 0; t < Lg; ++t) {
           V[t * mm + base] = (k == j) ? 1.0 : __longlong_as_double(0x7ff8000000000000ll);
           E[t * mm + base] = 0.0;
           R[t * mm + base] = -1;
@@ -1322,7 +1325,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         if (nzm) sd = __shfl(side, __builtin_ctzll(nzm));
       }
     } else {
-      for (int t = 0; t < L; ++t) {
+      for (int t = 0; t < Lg; ++t) {
         int side = sign_sum_side(dz, lam[t], Wd, unc);
         if (side == 3) {
           if (!have_exact) {
@@ -1341,7 +1344,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     }
     if ((nz0 | nz1) == 0) {
       // v_k = 0 at every penalty: e_jk = R64 sum of |x_ik|
-      for (int t = lane; t < L; t += 64) {
+      for (int t = lane; t < Lg; t += 64) {
         V[t * mm + base] = 0.0;
         E[t * mm + base] = Wk;
         R[t * mm + base] = -1;
@@ -1355,7 +1358,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     int prev_row = -2;
     double prev_e = 0.0;
     // penalties in groups of 64, lane l holding the target of penalty 64 g + l
-    for (int g = 0; 64 * g < L; ++g) {
+    for (int g = 0; 64 * g < Lg; ++g) {
       const uint64_t nzg = g ? nz1 : nz0;
       const int tl = 64 * g + lane;
       const bool act = ((nzg >> lane) & 1ull) != 0;
@@ -1376,7 +1379,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       // the ratios of the weighted row sample bracket the targets: a key
       // window; one exact pass lists the window's elements, one sort serves
       // every penalty.  A window too wide for the list is retried per penalty.
-      for (int pass = 0; nzg && pass <= 64; ++pass) {
+      for (int pass = 0; nzg && pass <= (kMulti ? 64 : 0); ++pass) {
         double wlo = qmin, whi = qmax;
         bool mine = act;
         if (pass > 0) {
@@ -1595,7 +1598,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       // residuals, reused while the selected row repeats: the group's targets
       // whose row differs from the previous target's are the jobs, scored up
       // to RJ at a time in one pass over the rows
-      const int tend = min(L, 64 * g + 64);
+      const int tend = min(Lg, 64 * g + 64);
       const int cnt = tend - 64 * g;
       int orw_l = -1;
       double v_l = 0.0;

@@ -23,6 +23,7 @@
 #include "bp_kernels.h"
 #include "comp_kernels.h"
 #include "path_kernels.h"
+#include "peak_kernels.h"
 
 // ------------------------------------------------------------------- context
 struct ProfRec {
@@ -815,6 +816,84 @@ int l1line_destroy(l1line_ctx ctx) {
   delete ctx;
   return st;
 }
+
+// Measured ceilings (microbenchmarks of peak_kernels.h), best of 3 timed
+// runs after one warm-up each.
+static int measure_peaks_impl(l1line_ctx ctx, double *out) {
+  if (!ctx || !out) return L1LINE_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const long long n16 = (1ll << 30) / 16;             // 1 GiB per copy buffer
+  const int grid = ctx->num_cu * 8;
+  void *a = nullptr, *b = nullptr, *sink = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = L1LINE_OK;
+  if (hipMalloc(&a, n16 * 16) != hipSuccess || hipMalloc(&b, n16 * 16) != hipSuccess ||
+      hipMalloc(&sink, (size_t)grid * 256 * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    st = L1LINE_ENOMEM;
+  }
+  if (!st && (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    st = L1LINE_EHIP;
+  if (!st && hipMemsetAsync(a, 0, n16 * 16, s) != hipSuccess) st = L1LINE_EHIP;
+  auto best_ms = [&](auto launch) -> float {
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && !st; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) { st = L1LINE_EHIP; break; }
+      launch();
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = L1LINE_EHIP;
+        break;
+      }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = L1LINE_EHIP; break; }
+      if (rep > 0 && ms < best) best = ms;                 // rep 0 warms up
+    }
+    return best;
+  };
+  if (!st) {
+    const float ms = best_ms([&] {
+      hipLaunchKernelGGL(k_peak_copy, dim3(ctx->num_cu * 16), dim3(256), 0, s, (const double2 *)a, (double2 *)b, n16);
+    });
+    out[0] = 2.0 * n16 * 16 / (ms * 1e-3) / 1e9;
+  }
+  if (!st) {
+    const float ms = best_ms([&] {
+      hipLaunchKernelGGL(k_peak_lds, dim3(grid), dim3(256), 0, s, (unsigned *)sink);
+    });
+    out[1] = (double)grid * 256 * PEAK_LDS_ITER * 4 * 16 / (ms * 1e-3) / 1e9;
+  }
+  if (!st) {
+    const float ms = best_ms([&] {
+      hipLaunchKernelGGL(k_peak_fma, dim3(grid), dim3(256), 0, s, (double *)sink, 0.999999, 1e-7);
+    });
+    out[2] = (double)grid * 256 * PEAK_FMA_ITER * 8 * 2 / (ms * 1e-3) / 1e12;
+  }
+  if (!st) {
+    const float ms = best_ms([&] {
+      hipLaunchKernelGGL(k_peak_mfma_f64, dim3(grid), dim3(256), 0, s, (double *)sink, 1e-3);
+    });
+    out[3] = (double)grid * 4 * PEAK_MFMA_ITER * 4 * 2048 / (ms * 1e-3) / 1e12;
+  }
+  if (!st) {
+    const float ms = best_ms([&] {
+      hipLaunchKernelGGL(k_peak_mfma_bf16, dim3(grid), dim3(256), 0, s, (float *)sink, 1e-3f);
+    });
+    out[4] = (double)grid * 4 * PEAK_MFMA_ITER * 4 * 16384 / (ms * 1e-3) / 1e12;
+  }
+  if (!st && hipGetLastError() != hipSuccess) st = L1LINE_EHIP;
+  if (s) (void)hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  if (sink) (void)hipFree(sink);
+  return st;
+}
+
+int l1line_measure_peaks(l1line_ctx ctx, double *out) { return note(ctx, measure_peaks_impl(ctx, out)); }
 
 int l1line_profile(l1line_ctx ctx, int enable) {
   if (!ctx) return L1LINE_EINVAL;
