@@ -26,14 +26,43 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU lane-op issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# (= the 78.6 TFLOP/s FP64 vector peak with an FMA counted as 2 flops).
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU operations per ratio element of the segment kernel: the
-# correctly rounded IEEE FP64 divide (10: 2 div_scale, rcp, 5 fma, div_fmas,
-# div_fixup), key + sign classification (4), exact 128-bit weight
-# accumulation (4), residual mul/sub/add (3).
-OPS_PER_ELEMENT = 21
+# MI355X published peaks (the roofline denominators; the measured ceilings
+# of l1line_measure_peaks are reported beside them)
+PEAK_FP64_TFLOPS = 78.6        # FP64 vector (an FMA counts 2)
+PEAK_FP64_MFMA_TFLOPS = 78.6   # FP64 matrix
+PEAK_HBM_GBPS = 8000.0
+CLOCK_HZ = 2.4e9
+SIMDS = 256 * 4
+
+
+def algorithmic_work(X):
+    """FP64 operations the method performs on one exhaustive fit, by the
+    plain algorithm: every ratio element (x_ij != 0, k != j) one IEEE divide
+    and one prefix-sum add; every residual term (all n rows of every (j, k),
+    k != j) one multiply, one subtract and one add (the absolute value is a
+    sign bit).  Elements skipped by the sign-sum test still count: the
+    figure measures the method's work per second."""
+    n, m = X.shape
+    elements = float(np.count_nonzero(X, axis=0).sum()) * (m - 1)
+    residual_terms = float(n) * m * (m - 1)
+    return {"ratio_elements": elements, "residual_terms": residual_terms,
+            "flops": 2.0 * elements + 3.0 * residual_terms}
+
+
+def signsum_mfma_issued(X):
+    """FP64 MFMAs k_signsum_batch issues on X (column-major n x m): the
+    matrix is staged in 32-row steps and 64-column tiles (zero padded); per
+    64 x 64 output tile, every block of 4 rows x 16 columns k costs one
+    16x16x4 MFMA per wave (4 waves) for D, and one more for Zr only when the
+    block holds an exact zero (padding included)."""
+    n, m = X.shape
+    n_pad, m_pad = -(-n // 32) * 32, -(-m // 64) * 64
+    Z = np.ones((n_pad, m_pad), dtype=bool)
+    Z[:n, :m] = (X == 0.0)
+    blocks_zero = int(Z.reshape(n_pad // 4, 4, m_pad // 16, 16).any(axis=(1, 3)).sum())
+    blocks = (n_pad // 4) * (m_pad // 16)
+    jtiles = m_pad // 64
+    return {"mfma_D": blocks * jtiles * 4, "mfma_Zr": blocks_zero * jtiles * 4, "flops_per_mfma": 2 * 16 * 16 * 4}
 
 
 def _args():
@@ -49,9 +78,10 @@ def _args():
     ap.add_argument("--legs", default="path,batch,ranked,breakpoints,components,solution_path",
                     help="extra workloads reported beside the main line (comma list; '' for none)")
     ap.add_argument("--ranked-instances", type=int, default=3)
-    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
-                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE counter files (bench run and --calibrate-copy "
-                         "run) into profiles/traffic.json and exit")
+    ap.add_argument("--no-tune", action="store_true", help="time with the default launch parameters only")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV [SQ_CSV]: turn rocprofv3 counter files "
+                         "(bench run and --calibrate-copy run) into profiles/traffic.json and exit")
     return ap.parse_args()
 
 
@@ -80,8 +110,9 @@ def _source_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_key):
-    """HBM bytes per launch from the committed counter summary, if it was
+def _counters(kernel_key):
+    """The committed counter record of the dominant kernel (HBM bytes per
+    launch from FETCH_SIZE / WRITE_SIZE, SQ instruction counts), if it was
     taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -91,7 +122,7 @@ def _traffic(kernel_key):
         return None
     if not rec or rec.get("source_hash") != _source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def _pmc_per_dispatch(path, counter):
@@ -111,33 +142,51 @@ def _pmc_per_dispatch(path, counter):
     return {k: tot[k] / len(disp[k]) for k in tot}
 
 
-def pmc_summary(fetch_csv, write_csv, copyf_csv, copyw_csv):
-    """HBM bytes per launch of the segment kernels from the FETCH_SIZE and
-    WRITE_SIZE counters, each scaled by what the counter reads for a copy of
-    exactly 512 MiB (bench.py --calibrate-copy)."""
+def pmc_summary(fetch_csv, write_csv, copyf_csv, copyw_csv, sq_csv=None):
+    """The dominant kernel's counter record: HBM bytes per launch of
+    k_seg_batch from the FETCH_SIZE and WRITE_SIZE counters, each scaled by
+    what the counter reads for a copy of exactly 512 MiB (bench.py
+    --calibrate-copy), and (optional) SQ_INSTS_VALU / SQ_INSTS_LDS per launch."""
     nbytes = 512 << 20
     cf = _pmc_per_dispatch(copyf_csv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"] * 1024
     cw = _pmc_per_dispatch(copyw_csv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"] * 1024
     fs, ws = nbytes / cf, nbytes / cw
     f = _pmc_per_dispatch(fetch_csv, "FETCH_SIZE")
     w = _pmc_per_dispatch(write_csv, "WRITE_SIZE")
-    kern = ("k_seg_batch", "k_signsum_batch")
-    fetch = sum(f[k] for k in kern) * 1024 * fs
-    write = sum(w[k] for k in kern) * 1024 * ws
-    rec = {"seg_2000x2000": {"kernels": list(kern), "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
-                             "write_bytes": write, "fetch_scale": fs, "write_scale": ws,
-                             "per_kernel_kib_raw": {k: {"FETCH_SIZE": f[k], "WRITE_SIZE": w[k]} for k in kern},
-                             "source_hash": _source_hash()}}
+    kern = "k_seg_batch"
+    fetch = f[kern] * 1024 * fs
+    write = w[kern] * 1024 * ws
+    rec = {"kernel": kern, "bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+           "fetch_scale": fs, "write_scale": ws,
+           "raw_kib": {"FETCH_SIZE": f[kern], "WRITE_SIZE": w[kern]}, "source_hash": _source_hash()}
+    if sq_csv:
+        rec["sq_insts_valu"] = _pmc_per_dispatch(sq_csv, "SQ_INSTS_VALU")[kern]
+        rec["sq_insts_lds"] = _pmc_per_dispatch(sq_csv, "SQ_INSTS_LDS")[kern]
+    out = {"seg_2000x2000": rec}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
-        json.dump(rec, fh, indent=1)
-    print(json.dumps(rec))
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(p, lam, z_gpu, columns):
-    """Time the oracle on a bounded sample of candidate columns j (all k for
-    each), on every host core via a thread pool; check each sampled z_j
-    against the GPU bit for bit."""
+    """The oracle timed on the host: a bounded sample of candidate columns j
+    (all k for each) of the timed workload on every host thread (a thread
+    pool over j) and on one thread, one warm-up then three timed runs each
+    (fits/s from the best run); every sampled z_j compared with the GPU's bit
+    for bit.  Also the 200 x 20 workload in full, both ways."""
     from oracle import oracle as O
+    from paper_2402_16712_amd import workloads as wl
     O.build()
     cores = max(1, min(os.cpu_count() or 1, 32))
     m = p.X.shape[1]
@@ -150,17 +199,34 @@ def cpu_baseline(p, lam, z_gpu, columns):
     def one(j):
         return j, O.fit_j(X, j, [lam])["ZJ"][0]
 
-    O.fit_j(X, js[0], [lam])   # warm-up (page-in, library load)
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=cores) as ex:
-        res = list(ex.map(one, js))
-    dt = time.perf_counter() - t0
+    def timed(fn, runs=3):
+        fn()                                              # warm-up
+        best = float("inf")
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            out = fn()
+            best = min(best, time.perf_counter() - t0)
+        return out, best
+
+    def pool():
+        with ThreadPoolExecutor(max_workers=cores) as ex:
+            return list(ex.map(one, js))
+
+    res, dt = timed(pool)
     mism = [j for j, z in res if np.float64(z).tobytes() != np.float64(z_gpu[j]).tobytes()]
-    fits_per_s = (len(js) / m) / dt
-    return dict(value=fits_per_s, unit="fits/s", cores=cores, kind="oracle",
-                sample=f"{len(js)} of {m} candidate columns j (all k each) of the timed "
-                       f"workload, {dt:.1f} s wall on {cores} threads; fits/s = "
-                       f"(columns/m)/seconds",
+    js1 = js[:max(1, len(js) // cores)]
+    _, dt1 = timed(lambda: [one(j) for j in js1])
+    small = wl.small_fit(0)
+    slam = float(small.lambdas[0])
+    _, ds_all = timed(lambda: O.fit(small.X, slam, nthreads=cores))
+    _, ds_one = timed(lambda: O.fit(small.X, slam, nthreads=1))
+    return dict(value=(len(js) / m) / dt, unit="fits/s", cores=cores, kind="oracle",
+                sample=f"{len(js)} of {m} candidate columns j (all k each) of the timed workload on "
+                       f"{cores} threads, best of 3 runs after a warm-up ({dt:.2f} s); fits/s = (columns/m)/s",
+                single_thread=(len(js1) / m) / dt1,
+                single_thread_sample=f"{len(js1)} columns on 1 thread, best of 3 ({dt1:.2f} s)",
+                cpu_model=_cpu_model(),
+                small_fit_200x20={"fits_per_s_all_threads": 1.0 / ds_all, "fits_per_s_one_thread": 1.0 / ds_one},
                 z_mismatches=len(mism))
 
 
@@ -195,21 +261,30 @@ def leg_path(ctx, seed, steps, stream):
 
 def leg_batch(ctx, steps, stream):
     """512 uneven problems (n 50..4000, m 10..500, 16 penalties each), one
-    batch call replayed from a captured graph."""
+    batch call replayed from a captured graph: with the default launch
+    parameters, then with the autotuned entry of the batch's size class."""
     from paper_2402_16712_amd import binding as B
     from paper_2402_16712_amd import workloads as wl
     probs = wl.uneven_batch()
     dev = [(B.device_matrix(p.X), p.lambdas) for p in probs]
     arr, outs, keep = ctx._batch_args(dev, False, False)
-    ctx.fit_batch_prepared(arr, len(dev), graph=True)       # capture
-    ctx.fit_batch_prepared(arr, len(dev), graph=True)       # replay
-    _, ms = _timed(lambda: ctx.fit_batch_prepared(arr, len(dev), graph=True), steps, stream)
+
+    def timed():
+        ctx.fit_batch_prepared(arr, len(dev), graph=True)       # capture
+        ctx.fit_batch_prepared(arr, len(dev), graph=True)       # replay
+        return _timed(lambda: ctx.fit_batch_prepared(arr, len(dev), graph=True), steps, stream)[1]
+
+    default_params, _ = ctx.tune_lookup(dev)
+    default_ms = timed()
+    tuned = ctx.autotune(dev)
+    ms = timed()
     bad = sum(int(o["status"].item()) != 0 for o in outs)
     medians = sum(p.m * (p.m - 1) * len(p.lambdas) for p in probs)
     del keep
     return {"workload": "512 uneven matrices n~U{50..4000} m~U{10..500}, 16 penalties each, graph replay",
             "ms_per_batch": ms, "problems_per_s": len(probs) * 1000.0 / ms,
-            "medians_per_s": medians * 1000.0 / ms, "nonzero_status": bad}
+            "medians_per_s": medians * 1000.0 / ms, "nonzero_status": bad,
+            "launch_params": {"tuned": tuned, "default": list(default_params), "default_ms_per_batch": default_ms}}
 
 
 def leg_breakpoints(ctx, seed, steps, stream):
@@ -327,6 +402,13 @@ def main():
     X = B.device_matrix(p.X)
     stream = torch.cuda.current_stream()
 
+    # the default launch parameters, then the autotuned ones of this size
+    # class (tuning runs before the timed region)
+    out = ctx.fit(X, lam)
+    torch.cuda.synchronize()
+    _, default_ms = _timed(lambda: ctx.fit(X, lam, rows=False, z_all=False), max(3, a.steps // 2), stream)
+    default_params = ctx.tune_get()
+    tuned_params = ctx.autotune([(X, [lam])]) if not a.no_tune else default_params
     for _ in range(a.warmup):
         out = ctx.fit(X, lam)
     torch.cuda.synchronize()
@@ -358,27 +440,39 @@ def main():
     z_gpu = out["z_all"].cpu().numpy()
     j_star = int(out["j"].item())
 
-    # roofline of the dominant kernel, the segment kernel, together with its
-    # division-free first pass (the sign sums): one launch of each = one
-    # fit's m(m-1) segments
-    nnz = np.count_nonzero(p.X, axis=0)
-    elements = float(nnz.sum()) * (m - 1)          # ratio elements per launch
-    seg_ms = kern["fit_seg"] + kern["signsum"]
-    achieved = elements * OPS_PER_ELEMENT / (seg_ms / 1000.0)
-    roof = {"bound": "alu", "kernel": "k_seg_batch + k_signsum_batch", "achieved": achieved / 1e12,
-            "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane-ops)",
-            "frac": achieved / VALU_PEAK_OPS, "traffic": _traffic("seg_2000x2000"),
-            "ops_per_element": OPS_PER_ELEMENT, "elements_per_launch": elements,
-            "avg_launch_ms": seg_ms}
+    # roofline of the dominant kernel, k_seg_batch (one launch = the m(m-1)
+    # segments of one fit), against the method's algorithmic FP64 work
+    work = algorithmic_work(p.X)
+    seg_s = kern["fit_seg"] / 1000.0
+    achieved = work["flops"] / seg_s / 1e12
+    peaks = ctx.measure_peaks()
+    rec = _counters("seg_2000x2000")
+    roof = {"bound": "alu", "kernel": "k_seg_batch", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": rec.get("bytes_per_launch") if rec else None,
+            "work": dict(work, basis="per fit: 2 flops per ratio element (IEEE divide, prefix-sum add), "
+                                     "3 per residual term (mul, sub, add)"),
+            "avg_launch_ms": kern["fit_seg"],
+            "peak_measured": peaks["fp64_valu_TFLOPs"], "frac_measured": achieved / peaks["fp64_valu_TFLOPs"]}
+    if rec and rec.get("sq_insts_valu"):
+        # VALU issue: every wave64 instruction occupies a SIMD for 4 cycles
+        busy = rec["sq_insts_valu"] * 4.0 / (SIMDS * CLOCK_HZ * seg_s)
+        roof["issue"] = {"valu_instructions_per_launch": rec["sq_insts_valu"],
+                         "lds_instructions_per_launch": rec.get("sq_insts_lds"),
+                         "valu_busy": busy,
+                         "basis": "SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time)"}
 
-    # the sign-sum contraction on the FP64 matrix units: 2 products of
-    # m x n x m, 2 flops per multiply-add (the zero-indicator product is
-    # skipped where a block has no zero, so this counts it in full)
-    ss_flops = 2.0 * 2.0 * m * m * n
-    roof_ss = {"bound": "mfma", "kernel": "k_signsum_batch", "achieved": ss_flops / (kern["signsum"] / 1000.0) / 1e12,
-               "peak": 78.6, "unit": "TFLOP/s (FP64 matrix)",
-               "frac": ss_flops / (kern["signsum"] / 1000.0) / 78.6e12, "flops_per_launch": ss_flops,
-               "avg_launch_ms": kern["signsum"]}
+    # the sign-sum contraction on the FP64 matrix units: the MFMAs the
+    # kernel issues (the Zr product only for 4 x 16 blocks holding a zero)
+    mf = signsum_mfma_issued(p.X)
+    ss_flops = (mf["mfma_D"] + mf["mfma_Zr"]) * mf["flops_per_mfma"]
+    ss_s = kern["signsum"] / 1000.0
+    roof_ss = {"bound": "mfma", "kernel": "k_signsum_batch", "achieved": ss_flops / ss_s / 1e12,
+               "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s (FP64 matrix)",
+               "frac": ss_flops / ss_s / 1e12 / PEAK_FP64_MFMA_TFLOPS, "flops_per_launch": ss_flops,
+               "mfma_issued": mf, "avg_launch_ms": kern["signsum"],
+               "peak_measured": peaks["fp64_mfma_TFLOPs"],
+               "frac_measured": ss_flops / ss_s / 1e12 / peaks["fp64_mfma_TFLOPs"]}
 
     line = {
         "metric": "fits/s & weighted-medians/s, 2000x2000 FP64; learned top-K vs exhaustive",
@@ -391,10 +485,13 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"exhaustive fit {n}x{m} FP64 (rank-one signal, Laplace noise, "
                                f"10% outlier rows, 1% zeros), lambda = 0.05 * max column mass, "
-                               f"all {m} candidate j", "n": n, "m": m, "L": 1, "seed": a.seed},
+                               f"all {m} candidate j", "n": n, "m": m, "L": 1, "seed": a.seed,
+                   "launch_params": {"tuned": tuned_params, "default": default_params,
+                                     "default_ms_per_step": default_ms}},
         "kernels_ms": kern,
         "roofline": roof,
         "roofline_signsum": roof_ss,
+        "peaks_measured": peaks,
         "j_star": j_star,
     }
     legs = [x for x in a.legs.split(",") if x]

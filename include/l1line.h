@@ -186,18 +186,34 @@ typedef struct {
 int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
                      int flags, void *stream);
 
-/* Autotuner: runs the batch under every candidate of a small grid of launch
- * parameters (persistent workgroups per compute unit, fewest k per work
- * item, work items per compute unit), times the segment kernel with HIP
- * events, keeps the fastest in the context and writes it to params_out
- * (HOST [3], nullable).  Synchronises the stream. */
+/* Autotuner.  Launch parameters are kept per size class: one problem or a
+ * batch, one penalty or several, and the bit lengths of the largest n, the
+ * largest m and (halved) the total work sum n m^2 L.  l1line_autotune runs
+ * the given problems under every candidate of a small grid (persistent
+ * workgroups per compute unit {2,3,4} x fewest k per work item {8,32,128},
+ * or {64,256,512} for one problem, x work items per compute unit
+ * {12,24,48} for a batch), times the segment kernel with HIP events, and
+ * stores the fastest as the entry of their size class: every later call
+ * of that class (fit, path, batch, ranked fit, breakpoints, components,
+ * solution path) launches with it; other classes keep the default.  The
+ * entry also goes to the context's cache file (keyed by the device's
+ * architecture name; read by l1line_create), and to params_out (HOST [3],
+ * nullable).  Results never depend on the parameters.  Synchronises the
+ * stream. */
 int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
                     void *stream, int32_t *params_out);
 
-/* Read / set the context's launch parameters (HOST [3]: workgroups per CU in
- * [1, 16], fewest k per item >= 1, items per CU in [1, 4096]). */
+/* Read / set the context's default launch parameters, used for size
+ * classes without a tuned entry (HOST [3]: workgroups per CU in [1, 16],
+ * fewest k per item >= 1, items per CU in [1, 4096]). */
 int l1line_tune_get(l1line_ctx ctx, int32_t *params);
 int l1line_tune_set(l1line_ctx ctx, const int32_t *params);
+
+/* The launch parameters a call with these problems uses (HOST [3]) and
+ * whether they are a tuned entry of its size class (tuned, HOST [1],
+ * nullable: 1 tuned, 0 default).  EINVAL as l1line_fit_batch. */
+int l1line_tune_lookup(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
+                       int32_t *params, int32_t *tuned);
 
 /* ------------------------------------------------------------------------
  * Learned candidate ranker.  Exhaustive search solves every preserved
@@ -406,6 +422,18 @@ int l1line_solution_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                          double *lam, int64_t *j, int32_t *k, double *v,
                          int32_t *row, double *E, double *P, int32_t *status,
                          void *stream);
+
+/* Measured ceilings of the device, for roofline figures (microbenchmarks,
+ * best of 3 timed runs each after a warm-up):
+ *   out[0] HBM copy bandwidth, GB/s (bytes read + written; 1 GiB buffers)
+ *   out[1] LDS read bandwidth, GB/s (16-byte reads, conflict-free)
+ *   out[2] FP64 VALU, TFLOP/s (independent FMA chains, 2 flops each)
+ *   out[3] FP64 matrix, TFLOP/s (v_mfma_f64_16x16x4f64)
+ *   out[4] BF16 matrix, TFLOP/s (v_mfma_f32_16x16x32_bf16)
+ * out is a HOST array of L1LINE_PEAKS doubles.  Synchronous; allocates and
+ * frees 2 GiB of scratch.  Errors: EINVAL (null), ENOMEM, EHIP. */
+#define L1LINE_PEAKS 5
+int l1line_measure_peaks(l1line_ctx ctx, double *out);
 
 /* Kernel timing for measurement tools.  While enabled, every kernel the
  * context launches is bracketed by HIP events on its stream.

@@ -26,7 +26,8 @@ EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_er
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
            "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
            "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train",
-           "l1line_breakpoints", "l1line_components", "l1line_solution_path"]
+           "l1line_breakpoints", "l1line_components", "l1line_solution_path", "l1line_measure_peaks",
+           "l1line_tune_lookup"]
 BATCH_GRAPH = 1
 FEATURES = 32
 MLP_PARAMS = 20865
@@ -79,6 +80,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_autotune.argtypes = [P, P, I64, P, P]
         L.l1line_tune_get.argtypes = [P, P]
         L.l1line_tune_set.argtypes = [P, P]
+        L.l1line_tune_lookup.argtypes = [P, P, I64, P, P]
         F32 = ctypes.c_float
         L.l1line_ranker_features.argtypes = [P, P, I64, I64, I64, D, P, P]
         L.l1line_mlp_forward.argtypes = [P, P, P, I64, P, P]
@@ -86,6 +88,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_mlp_adam.argtypes = [P, P, P, P, P, I64, F32, P]
         L.l1line_fit_ranked.argtypes = [P, P, I64, I64, I64, D, I32, F32, P, P, P, P, P, P, P, P]
         L.l1line_profile.argtypes = [P, I32]
+        L.l1line_measure_peaks.argtypes = [P, P]
         L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),
                                           ctypes.POINTER(I64), I32]
         for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit", "l1line_fit_noalloc",
@@ -94,7 +97,7 @@ def lib() -> ctypes.CDLL:
                   "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked",
                   "l1line_last_error", "l1line_ranker_load", "l1line_ranker_save", "l1line_ranker_set_params",
                   "l1line_ranker_get_params", "l1line_ranker_train", "l1line_breakpoints",
-                  "l1line_components"):
+                  "l1line_components", "l1line_measure_peaks", "l1line_tune_lookup"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -169,6 +172,14 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def measure_peaks(self):
+        """Measured ceilings: dict hbm_GBps, lds_GBps, fp64_valu_TFLOPs,
+        fp64_mfma_TFLOPs, bf16_mfma_TFLOPs (l1line_measure_peaks)."""
+        out = (ctypes.c_double * 5)()
+        _check(lib().l1line_measure_peaks(self._h, ctypes.cast(out, ctypes.c_void_p)), "l1line_measure_peaks")
+        return dict(zip(("hbm_GBps", "lds_GBps", "fp64_valu_TFLOPs", "fp64_mfma_TFLOPs", "bf16_mfma_TFLOPs"),
+                        list(out)))
 
     def profile(self, enable: bool):
         _check(lib().l1line_profile(self._h, int(bool(enable))), "l1line_profile")
@@ -290,6 +301,18 @@ class Context:
         _check(lib().l1line_autotune(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems),
                                      self._stream(), params), "l1line_autotune")
         return list(params)
+
+    def tune_lookup(self, problems):
+        """((workgroups per CU, fewest k per item, items per CU), tuned) a
+        call with these problems (list of (X, lambdas)) launches with."""
+        arr, outs, keep = self._batch_args(problems, False, False)
+        params = (ctypes.c_int32 * 3)()
+        tuned = ctypes.c_int32()
+        _check(lib().l1line_tune_lookup(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems),
+                                        ctypes.cast(params, ctypes.c_void_p), ctypes.byref(tuned)),
+               "l1line_tune_lookup")
+        del keep, outs
+        return tuple(params), bool(tuned.value)
 
     def tune_get(self):
         params = (ctypes.c_int32 * 3)()

@@ -37,6 +37,16 @@ struct TuneParams {
   int items_per_cu;    // target number of work items per compute unit
 };
 
+// Size class of a launch, the key of autotuned launch parameters: one
+// problem or a batch, one penalty or several, and the bit lengths of the
+// largest n, the largest m and (halved) of the total work sum n m^2 L.
+struct TuneKey {
+  int batch, multi, nb, mb, wb;
+  bool operator==(const TuneKey &o) const {
+    return batch == o.batch && multi == o.multi && nb == o.nb && mb == o.mb && wb == o.wb;
+  }
+};
+
 struct l1line_ctx_s {
   int device;
   int num_cu;
@@ -49,7 +59,10 @@ struct l1line_ctx_s {
   hipStream_t cap_stream;   // stream used to capture launch graphs
   hipGraphExec_t graph;     // cached graph of the last captured batch layout
   uint64_t graph_key;
-  TuneParams tune;
+  TuneParams tune;          // default launch parameters (size classes without a tuned entry)
+  std::vector<std::pair<TuneKey, TuneParams>> tuned;   // autotuned entries per size class
+  std::vector<std::string> tune_foreign;               // cache lines of other architectures, kept
+  std::string arch;         // gcnArchName of the device (cache key)
   bool profiling;
   std::vector<ProfRec> prof;
   void *rk;                 // ranker scratch (features, sign sums, MLP buffers)
@@ -701,28 +714,89 @@ static l1line_problem single(const double *X, int64_t n, int64_t m, int64_t ld, 
 
 static const TuneParams kDefaultTune = {3, 8, 24};
 
+static int bitlen(double x) {
+  int b = 0;
+  while (x >= 1.0 && b < 200) {
+    x *= 0.5;
+    ++b;
+  }
+  return b;
+}
+
+static TuneKey tune_key(const l1line_problem *probs, int64_t B) {
+  int64_t nmax = 1, mmax = 1, lmax = 1;
+  double work = 0.0;
+  for (int64_t b = 0; b < B; ++b) {
+    nmax = std::max<int64_t>(nmax, probs[b].n);
+    mmax = std::max<int64_t>(mmax, probs[b].m);
+    lmax = std::max<int64_t>(lmax, probs[b].L);
+    work += (double)probs[b].n * (double)probs[b].m * (double)probs[b].m * (double)probs[b].L;
+  }
+  return TuneKey{B > 1 ? 1 : 0, lmax > 1 ? 1 : 0, bitlen((double)nmax), bitlen((double)mmax), bitlen(work) / 2};
+}
+
+// The launch parameters of a call: its size class's tuned entry, else the default.
+static TuneParams tune_for(l1line_ctx ctx, const l1line_problem *probs, int64_t B, bool *tuned = nullptr) {
+  const TuneKey key = tune_key(probs, B);
+  for (const auto &e : ctx->tuned)
+    if (e.first == key) {
+      if (tuned) *tuned = true;
+      return e.second;
+    }
+  if (tuned) *tuned = false;
+  return ctx->tune;
+}
+
 extern "C" {
 
-// Launch-parameter cache: one text line "l1line-tune <workgroups per CU>
-// <fewest k per item> <items per CU>"; a missing or malformed file is ignored.
+// Launch-parameter cache, text lines:
+//   l1line-tune <workgroups per CU> <fewest k per item> <items per CU>      (default)
+//   l1line-tune-class <arch> <batch> <multi> <nb> <mb> <wb> <wg/CU> <k> <items/CU>
+// Entries of other architectures are kept when the file is rewritten;
+// malformed lines are ignored.
+static bool tune_ok(int a, int k, int i) {
+  return a >= 1 && a <= 16 && k >= 1 && k <= (1 << 20) && i >= 1 && i <= 4096;
+}
+
 static void tune_load(l1line_ctx c) {
   if (c->tune_path.empty()) return;
   FILE *f = fopen(c->tune_path.c_str(), "r");
   if (!f) return;
-  int a = 0, k = 0, i = 0;
-  if (fscanf(f, "l1line-tune %d %d %d", &a, &k, &i) == 3 && a >= 1 && a <= 16 && k >= 1 && k <= (1 << 20) &&
-      i >= 1 && i <= 4096)
-    c->tune = TuneParams{a, k, i};
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    int a = 0, k = 0, i = 0;
+    char arch[160];
+    TuneKey key;
+    if (sscanf(line, "l1line-tune %d %d %d", &a, &k, &i) == 3) {
+      if (tune_ok(a, k, i)) c->tune = TuneParams{a, k, i};
+    } else if (sscanf(line, "l1line-tune-class %159s %d %d %d %d %d %d %d %d", arch, &key.batch, &key.multi, &key.nb,
+                      &key.mb, &key.wb, &a, &k, &i) == 9) {
+      if (!tune_ok(a, k, i)) continue;
+      if (c->arch == arch) {
+        c->tuned.push_back({key, TuneParams{a, k, i}});
+      } else {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        c->tune_foreign.push_back(l);
+      }
+    }
+  }
   fclose(f);
 }
 
 static int tune_save(l1line_ctx c) {
   if (c->tune_path.empty()) return L1LINE_OK;
-  FILE *f = fopen(c->tune_path.c_str(), "w");
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
   if (!f) return L1LINE_EIO;
-  const int ok = fprintf(f, "l1line-tune %d %d %d\n", c->tune.blocks_per_cu, c->tune.kchunk_min,
-                         c->tune.items_per_cu) > 0;
-  return (fclose(f) == 0 && ok) ? L1LINE_OK : L1LINE_EIO;
+  bool ok = fprintf(f, "l1line-tune %d %d %d\n", c->tune.blocks_per_cu, c->tune.kchunk_min, c->tune.items_per_cu) > 0;
+  for (const auto &e : c->tuned)
+    ok = ok && fprintf(f, "l1line-tune-class %s %d %d %d %d %d %d %d %d\n", c->arch.c_str(), e.first.batch,
+                       e.first.multi, e.first.nb, e.first.mb, e.first.wb, e.second.blocks_per_cu,
+                       e.second.kchunk_min, e.second.items_per_cu) > 0;
+  for (const auto &l : c->tune_foreign) ok = ok && fprintf(f, "%s\n", l.c_str()) > 0;
+  if (fclose(f) != 0 || !ok) return L1LINE_EIO;
+  return rename(tmp.c_str(), c->tune_path.c_str()) == 0 ? L1LINE_OK : L1LINE_EIO;
 }
 
 int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path) {
@@ -760,6 +834,9 @@ int l1line_create(l1line_ctx *ctx, int device, const char *tune_cache_path) {
   c->rk_step = 0;
   c->rk_seed = c->rk_cursor = 0;
   c->scratch = scratch_address(device);   // device is current (hipSetDevice above)
+  c->arch = prop.gcnArchName[0] ? std::string(prop.gcnArchName) : std::string("unknown");
+  for (auto &ch : c->arch)
+    if (ch == ' ') ch = '_';
   if (tune_cache_path) c->tune_path = tune_cache_path;
   tune_load(c);
   if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
@@ -966,7 +1043,7 @@ static int fit_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64
   if (st) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, z_all, status);
-  return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, ctx->tune, nullptr);
+  return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, tune_for(ctx, &p, 1), nullptr);
 }
 
 int l1line_fit(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, double *v,
@@ -1012,7 +1089,8 @@ static int fit_noalloc_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, z_all, status);
   BatchLayout Ly;
   std::vector<WorkItem> items;        // stays empty: one problem's items are implicit
-  st = plan_batch(ctx, &p, 1, ctx->tune, kNoOpts, Ly, items);
+  const TuneParams tp = tune_for(ctx, &p, 1);
+  st = plan_batch(ctx, &p, 1, tp, kNoOpts, Ly, items);
   if (st) return st;
   if (Ly.bytes > NOALLOC_BYTES || !items.empty()) return L1LINE_ESIZE;
   const MetaCursor c0 = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1020,7 +1098,7 @@ static int fit_noalloc_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   advance(c1, p, kNoOpts, 1);
   char *d = (char *)ctx->scratch;
   hipLaunchKernelGGL(k_meta_single, dim3(1), dim3(64), 0, s, prob_desc(p, c0), lambda, c1.tiles, Ly, d);
-  st = launch_seq(ctx, s, Ly, d, 1, ctx->tune, kNoOpts, false, nullptr, nullptr, nullptr);
+  st = launch_seq(ctx, s, Ly, d, 1, tp, kNoOpts, false, nullptr, nullptr, nullptr);
   if (st) return st;
   HIP_TRY(hipGetLastError());
   return L1LINE_OK;
@@ -1042,7 +1120,7 @@ static int fit_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, 
   if (st) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const l1line_problem p = single(X, n, m, ld, lambdas, L, V, J, OBJ, ROW, ZALL, status);
-  return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, ctx->tune, nullptr);
+  return run_batch(ctx, &p, 1, 0, (hipStream_t)stream, tune_for(ctx, &p, 1), nullptr);
 }
 
 int l1line_fit_path(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, const double *lambdas,
@@ -1059,7 +1137,7 @@ static int fit_batch_impl(l1line_ctx ctx, const l1line_problem *probs, int64_t B
     if (st) return st;
   }
   HIP_TRY(hipSetDevice(ctx->device));
-  return run_batch(ctx, probs, B, flags, (hipStream_t)stream, ctx->tune, nullptr);
+  return run_batch(ctx, probs, B, flags, (hipStream_t)stream, tune_for(ctx, probs, B), nullptr);
 }
 
 int l1line_fit_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int flags, void *stream) {
@@ -1076,15 +1154,21 @@ static int autotune_impl(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
   hipStream_t s = (hipStream_t)stream;
   const bool was_profiling = ctx->profiling;
   ctx->profiling = false;
-  TuneParams best = ctx->tune;
+  TuneParams best = tune_for(ctx, probs, B);
   float best_ms = 1e30f;
+  // the grid: persistent workgroups per CU x fewest k per item x items per
+  // CU; one problem's items are implicit (items per CU unused, at least 256
+  // k per item unless more is asked), so its grid varies the first two
   const int bpc[] = {2, 3, 4};
-  const int kmin[] = {8, 32, 128};
-  const int ipc[] = {12, 24, 48};
+  const int kmin_batch[] = {8, 32, 128}, kmin_one[] = {64, 256, 512};
+  const int ipc_batch[] = {12, 24, 48}, ipc_one[] = {24};
+  const int *kmin = B > 1 ? kmin_batch : kmin_one;
+  const int *ipc = B > 1 ? ipc_batch : ipc_one;
+  const int nipc = B > 1 ? 3 : 1;
   for (int a : bpc)
-    for (int k : kmin)
-      for (int i : ipc) {
-        const TuneParams tp{a, k, i};
+    for (int kq = 0; kq < 3; ++kq)
+      for (int iq = 0; iq < nipc; ++iq) {
+        const TuneParams tp{a, kmin[kq], ipc[iq]};
         float ms = 0.f;
         const int st = run_batch(ctx, probs, B, 0, s, tp, &ms);
         if (st) {
@@ -1096,7 +1180,14 @@ static int autotune_impl(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
           best = tp;
         }
       }
-  ctx->tune = best;
+  const TuneKey key = tune_key(probs, B);
+  bool found = false;
+  for (auto &e : ctx->tuned)
+    if (e.first == key) {
+      e.second = best;
+      found = true;
+    }
+  if (!found) ctx->tuned.push_back({key, best});
   ctx->profiling = was_profiling;
   drop_graph(ctx);
   if (params_out) {
@@ -1118,6 +1209,21 @@ int l1line_tune_set(l1line_ctx ctx, const int32_t *params) {
     return L1LINE_EINVAL;
   ctx->tune = TuneParams{params[0], params[1], params[2]};
   drop_graph(ctx);
+  return L1LINE_OK;
+}
+
+int l1line_tune_lookup(l1line_ctx ctx, const l1line_problem *probs, int64_t B, int32_t *params, int32_t *tuned) {
+  if (!ctx || !probs || !params || B < 1 || B > (1 << 20)) return note(ctx, L1LINE_EINVAL);
+  for (int64_t b = 0; b < B; ++b) {
+    const int st = check_problem(probs[b]);
+    if (st) return note(ctx, st);
+  }
+  bool t = false;
+  const TuneParams tp = tune_for(ctx, probs, B, &t);
+  params[0] = tp.blocks_per_cu;
+  params[1] = tp.kchunk_min;
+  params[2] = tp.items_per_cu;
+  if (tuned) *tuned = t ? 1 : 0;
   return L1LINE_OK;
 }
 
@@ -1304,11 +1410,11 @@ static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, nullptr, status);
   // exact solve of the K candidates
   const RunOpts rc{cand, (int)K, mask, nullptr, 0};
-  st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, rc);
+  st = run_batch(ctx, &p, 1, 0, s, tune_for(ctx, &p, 1), nullptr, rc);
   if (st) return st;
   // exhaustive solve, which does nothing unless the margin test failed
   const RunOpts rf{nullptr, 0, nullptr, flag, 1};
-  st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, rf);
+  st = run_batch(ctx, &p, 1, 0, s, tune_for(ctx, &p, 1), nullptr, rf);
   if (st) return st;
   if (used_fallback) hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, s, flag, used_fallback);
   HIP_TRY(hipGetLastError());
@@ -1513,7 +1619,7 @@ int l1line_ranker_train(l1line_ctx ctx, const char *ckpt_path, int64_t steps, ui
     const double lam = 0.05 * big;
     // labels: the exact z_j of every column
     const l1line_problem p = single(X, n, m, n, &lam, 1, V, J, OBJ, nullptr, Z, nullptr);
-    st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr);
+    st = run_batch(ctx, &p, 1, 0, s, tune_for(ctx, &p, 1), nullptr);
     if (st) break;
     st = ranker_features(ctx, X, n, m, n, lam, F, s);
     if (st) break;
@@ -1567,7 +1673,7 @@ static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   const l1line_problem p = single(X, n, m, ld, &zero, 1, (double *)(b + o_v), (int64_t *)(b + o_j),
                                   (double *)(b + o_obj), nullptr, nullptr, status);
   BatchPtrs bp;
-  st = run_batch(ctx, &p, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
+  st = run_batch(ctx, &p, 1, 0, s, tune_for(ctx, &p, 1), nullptr, kNoOpts, &bp);
   if (st) return st;
   const long long nseg = (long long)m * m;
   const unsigned grid = (unsigned)std::max(8ll, std::min((nseg + 3) / 4, (long long)ctx->num_cu * 8));
@@ -1631,7 +1737,7 @@ static int components_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   for (int64_t c = 0; c < p; ++c) {
     const l1line_problem pr = single(work, n, m, n, &lambda, 1, V + c * m, J + c, OBJ + c, nullptr, nullptr,
                                      cst + c);
-    st = run_batch(ctx, &pr, 1, 0, s, ctx->tune, nullptr);
+    st = run_batch(ctx, &pr, 1, 0, s, tune_for(ctx, &pr, 1), nullptr);
     if (st) return st;
     if (c == p - 1) break;
     hipLaunchKernelGGL(k_gs, dim3(1), dim3(64), 0, s, (const double *)(V + c * m), Wb, cw, (int)c, (int)m, U,
@@ -1696,7 +1802,7 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
   const l1line_problem p0 = single(X, n, m, ld, &zero, 1, (double *)(b + o_v), (int64_t *)(b + o_j),
                                    (double *)(b + o_obj), nullptr, nullptr, fst);
   BatchPtrs bp;
-  st = run_batch(ctx, &p0, 1, 0, s, ctx->tune, nullptr, kNoOpts, &bp);
+  st = run_batch(ctx, &p0, 1, 0, s, tune_for(ctx, &p0, 1), nullptr, kNoOpts, &bp);
   if (st) return st;
   const unsigned grid = (unsigned)std::max(8ll, std::min((mm + 3) / 4, (long long)ctx->num_cu * 8));
   BpList bl;

@@ -123,6 +123,67 @@ def evaluate(ctx: B.Context, indices, K: int = 32, margin: float = 0.05, rel_tol
     return rows
 
 
+def ablation(ctx: B.Context, indices, params_trained, params_untrained, K: int = 32, margin: float = 0.05,
+             rel_tol: float = 1e-9, **kw):
+    """What the trained network gains: on each evaluation matrix, the exact
+    z_j of every column (exhaustive fit) judge four rankings of the columns
+    -- the trained MLP, the same MLP with untrained (He-init) weights, the
+    column l1 mass alone (heaviest first: z_j falls with W_j) and the slope
+    aggregate A1 alone (feature 6, largest first).  For each: whether the
+    optimal column is among the K best ranked (hit), whether the best exact
+    objective among those K is within rel_tol of the optimum (what the
+    ranked fit returns when it does not fall back), and whether the MLP's
+    score margin would trigger the exhaustive fallback."""
+    import torch
+    rows = []
+    for idx in indices:
+        X, lam = wl.ranker_matrix_torch(idx, device=ctx._torch_device, **kw)
+        ex = ctx.fit(X, lam)
+        F = ctx.features(X, lam)
+        z = ex["z_all"].to(torch.float64)
+        zstar = float(z.min().item())
+        jstar = int(ex["j"].item())
+        m = z.numel()
+        scores = {"trained": ctx.mlp_forward(params_trained, F).to(torch.float64),
+                  "untrained": ctx.mlp_forward(params_untrained, F).to(torch.float64),
+                  "column_mass": -X.abs().sum(dim=0),
+                  "slope_aggregate": -F[:, 6].to(torch.float64)}
+        row = {"index": idx, "n": int(X.shape[0]), "m": m}
+        kk = min(K, m)
+        for name, sc in scores.items():
+            sc = torch.where(torch.isnan(sc), torch.full_like(sc, float("inf")), sc)
+            order = torch.argsort(sc, stable=True)
+            top = order[:kk]
+            best = float(z[top].min().item())
+            # rank of the optimal column (0 = ranked first; ties in the
+            # score broken by the lower index, as the device's top-K does)
+            rank = int((order == jstar).nonzero()[0, 0].item())
+            r = {"hit": bool((top == jstar).any().item()), "within": abs(best - zstar) <= rel_tol * abs(zstar),
+                 "rank": rank}
+            if name in ("trained", "untrained") and kk < m:
+                r["fallback"] = bool(float((sc[order[kk]] - sc[order[0]]).item()) < margin)
+            row[name] = r
+        rows.append(row)
+    return rows
+
+
+def ablation_summary(rows):
+    out = {"instances": len(rows)}
+    for name in ("trained", "untrained", "column_mass", "slope_aggregate"):
+        ranks = [r[name]["rank"] for r in rows]
+        out[name] = {"hit_rate": sum(r[name]["hit"] for r in rows) / len(rows),
+                     "within_rate": sum(r[name]["within"] for r in rows) / len(rows),
+                     "top_k_rate": {str(k): sum(x < k for x in ranks) / len(rows) for k in (1, 2, 4, 8, 16, 32)},
+                     "mean_rank": sum(ranks) / len(rows)}
+        if "fallback" in rows[0][name]:
+            fb = [r[name]["fallback"] for r in rows]
+            out[name]["fallback_rate"] = sum(fb) / len(rows)
+            # the ranked fit's outcome: exact after a fallback, else the top-K optimum
+            out[name]["within_rate_with_fallback"] = sum(
+                r[name]["within"] or r[name]["fallback"] for r in rows) / len(rows)
+    return out
+
+
 EVAL_BASE = 90000        # evaluation matrices (10000 x 4000) are 90000, 90001, ...
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "ranker_weights.l1rk")
 
@@ -146,6 +207,14 @@ def _main(argv=None):
     e.add_argument("--m", type=int, default=4000)
     e.add_argument("--K", type=int, default=32)
     e.add_argument("--margin", type=float, default=0.05)
+    b = sub.add_parser("ablation", help="trained vs untrained weights vs column mass vs slope aggregate")
+    b.add_argument("--weights", default=WEIGHTS)
+    b.add_argument("--count", type=int, default=300)
+    b.add_argument("--n", type=int, default=10000)
+    b.add_argument("--m", type=int, default=4000)
+    b.add_argument("--K", type=int, default=32)
+    b.add_argument("--margin", type=float, default=0.05)
+    b.add_argument("--init-seed", type=int, default=1)
     a = ap.parse_args(argv)
     ctx = B.Context(0)
     if a.cmd == "train":
@@ -157,6 +226,16 @@ def _main(argv=None):
             print(json.dumps({"steps": done, "s": round(time.perf_counter() - t0, 2)}), flush=True)
         w, _, _ = B.read_ranker_file(a.ckpt)
         B.write_ranker_file(a.out, w)
+    elif a.cmd == "ablation":
+        import torch
+        trained = load_params(a.weights, ctx._torch_device)
+        untrained = torch.from_numpy(init_params(a.init_seed)).to(ctx._torch_device)
+        rows = []
+        for q in range(a.count):
+            r = ablation(ctx, [EVAL_BASE + q], trained, untrained, a.K, a.margin, n=a.n, m=a.m)[0]
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+        print(json.dumps(ablation_summary(rows)), flush=True)
     else:
         ctx.ranker_load(a.weights)
         rows = []

@@ -57,13 +57,38 @@ def test_traffic_summary_and_source_rule(tmp_path, monkeypatch):
                                   (1, "k_signsum_batch(int)", "FETCH_SIZE", 100.0)])
     w = _csv(tmp_path / "w.csv", [(1, "void k_seg_batch<true, false>(int)", "WRITE_SIZE", 300.0),
                                   (1, "k_signsum_batch(int)", "WRITE_SIZE", 60.0)])
-    bench.pmc_summary(f, w, cf, cw)
+    sq = _csv(tmp_path / "sq.csv", [(1, "void k_seg_batch<true, false>(int)", "SQ_INSTS_VALU", 5.0e9),
+                                    (1, "void k_seg_batch<true, false>(int)", "SQ_INSTS_LDS", 7.0e8)])
+    bench.pmc_summary(f, w, cf, cw, sq)
     rec = json.load(open(tmp_path / "profiles" / "traffic.json"))["seg_2000x2000"]
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
-    assert rec["bytes_per_launch"] == pytest.approx((1100.0 * 2.0 + 360.0) * 1024)
+    # the dominant kernel alone
+    assert rec["bytes_per_launch"] == pytest.approx((1000.0 * 2.0 + 300.0) * 1024)
+    assert rec["sq_insts_valu"] == 5.0e9 and rec["sq_insts_lds"] == 7.0e8
     assert rec["source_hash"] == "h1"
-    assert bench._traffic("seg_2000x2000") == pytest.approx(rec["bytes_per_launch"])
+    assert bench._counters("seg_2000x2000")["bytes_per_launch"] == pytest.approx(rec["bytes_per_launch"])
     # measured on other sources: not reported
     monkeypatch.setattr(bench, "_source_hash", lambda: "h2")
-    assert bench._traffic("seg_2000x2000") is None
-    assert bench._traffic("no_such_kernel") is None
+    assert bench._counters("seg_2000x2000") is None
+    assert bench._counters("no_such_kernel") is None
+
+
+def test_algorithmic_work_and_issued_mfma_counts():
+    import numpy as np
+    X = np.zeros((70, 130), order="F")
+    X[:, :] = 1.0
+    X[5, 3] = 0.0                       # one zero: one 4 x 16 block
+    w = bench.algorithmic_work(X)
+    assert w["ratio_elements"] == (70 * 130 - 1) * 129
+    assert w["residual_terms"] == 70 * 130 * 129
+    assert w["flops"] == 2 * w["ratio_elements"] + 3 * w["residual_terms"]
+    mf = bench.signsum_mfma_issued(X)
+    # padded to 96 rows x 192 columns: 24 x 12 blocks, 3 column tiles of 64, 4 waves
+    assert mf["mfma_D"] == 24 * 12 * 3 * 4
+    # zero blocks: the real zero, every block of padded rows (70..95 -> rows
+    # blocks 17..23 hold padding: 7 x 12) and of padded columns (130..191:
+    # column blocks 8..11 -> 4 x 24), without counting twice
+    pad_rows = 7 * 12
+    pad_cols = 4 * 24
+    both = 7 * 4
+    assert mf["mfma_Zr"] == (1 + pad_rows + pad_cols - both) * 3 * 4

@@ -126,16 +126,51 @@ def test_autotune_keeps_results(ctx):
     from paper_2402_16712_amd import binding as B
     probs = _small_batch(4)
     dev = [(B.device_matrix(X), lam) for X, lam in probs]
-    _say("case autotune")
+    _say("case autotune batch")
     before = _np(ctx.fit_batch(dev))
-    saved = ctx.tune_get()
+    default = ctx.tune_get()
     params = ctx.autotune(dev)
     assert params[0] in (2, 3, 4) and params[1] in (8, 32, 128) and params[2] in (12, 24, 48)
-    assert ctx.tune_get() == params
+    # the batch's size class launches with the tuned entry, the default stays
+    assert ctx.tune_lookup(dev) == (tuple(params), True)
+    assert ctx.tune_get() == default
     after = _np(ctx.fit_batch(dev))
     for q, (a, b) in enumerate(zip(after, before)):
         _eq(a, b, f"after tune {q}")
-    ctx.tune_set(saved)
+    # another size class (one problem) keeps the default
+    one = [dev[0]]
+    assert ctx.tune_lookup(one) == (tuple(default), False)
+
+
+def test_autotune_one_problem_class(tmp_path):
+    """One problem tunes its own class (the grid of implicit items); the
+    entry is read back from the cache file by a new context and leaves the
+    results bit for bit unchanged."""
+    import torch
+    from paper_2402_16712_amd import binding as B
+    path = str(tmp_path / "tune.txt")
+    p = wl.large_fit(3, n=900, m=120)
+    c = B.Context(0, tune_cache_path=path)
+    try:
+        X = B.device_matrix(p.X)
+        _say("case autotune one problem")
+        ref = {k: v.cpu().numpy() for k, v in c.fit(X, float(p.lambdas[0])).items()}
+        params = c.autotune([(X, p.lambdas)])
+        assert params[0] in (2, 3, 4) and params[1] in (64, 256, 512) and params[2] == 24
+        got = {k: v.cpu().numpy() for k, v in c.fit(X, float(p.lambdas[0])).items()}
+        torch.cuda.synchronize()
+        for k in ("v", "j", "obj", "row", "z_all"):
+            assert got[k].tobytes() == ref[k].tobytes(), k
+        lines = open(path).read().splitlines()
+        assert lines[0].startswith("l1line-tune ") and any(l.startswith("l1line-tune-class ") for l in lines)
+    finally:
+        c.close()
+    c2 = B.Context(0, tune_cache_path=path)
+    try:
+        X = B.device_matrix(p.X)
+        assert c2.tune_lookup([(X, p.lambdas)]) == (tuple(params), True)
+    finally:
+        c2.close()
 
 
 def test_path_full_size_sampled(ctx):

@@ -274,11 +274,12 @@ def test_sticky_error_and_tune_cache(tmp_path):
         assert c.last_error() == B.OK
         probs = [(B.device_matrix(wl.random_small(40 + q, 60, 5)), np.array([0.1, 1.0])) for q in range(3)]
         best = c.autotune(probs)
-        assert open(path).read().split() == ["l1line-tune"] + [str(x) for x in best]
+        cls = [l.split() for l in open(path).read().splitlines() if l.startswith("l1line-tune-class ")]
+        assert len(cls) == 1 and cls[0][-3:] == [str(x) for x in best]
     finally:
         c.close()
     c2 = B.Context(0, tune_cache_path=path)
     try:
-        assert c2.tune_get() == best
+        assert c2.tune_lookup(probs) == (tuple(best), True)
     finally:
         c2.close()

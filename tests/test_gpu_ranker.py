@@ -390,3 +390,29 @@ def test_trainer_resume(ctx, tmp_path):
     assert a.step == b.step == 5 and a.cursor == b.cursor
     assert a.params.cpu().numpy().tobytes() == b.params.cpu().numpy().tobytes()
     assert a.m2.cpu().numpy().tobytes() == b.m2.cpu().numpy().tobytes()
+
+
+def test_trained_network_gains_over_the_method_without_it():
+    """What the trained network adds, on the first 12 evaluation matrices
+    (10000 x 4000, the ranked fit's workload; exact z_j of every column from
+    the exhaustive fit): the optimal column is among the network's 32 best
+    on all of them and ranked near the top, while untrained weights and the
+    column mass miss it and the slope aggregate alone ranks it lower."""
+    from paper_2402_16712_amd import binding as B
+    from paper_2402_16712_amd import ranker
+    import torch
+    c = B.Context(0)
+    try:
+        trained = ranker.load_params(ranker.WEIGHTS)
+        untrained = torch.from_numpy(ranker.init_params(1)).to("cuda:0")
+        _say("ranker ablation 12 x 10000x4000")
+        rows = ranker.ablation(c, [ranker.EVAL_BASE + q for q in range(12)], trained, untrained, K=32,
+                                  n=10000, m=4000)
+        summ = ranker.ablation_summary(rows)
+    finally:
+        c.close()
+    t, u, cm, sa = (summ[k] for k in ("trained", "untrained", "column_mass", "slope_aggregate"))
+    assert t["hit_rate"] == 1.0 and t["within_rate"] == 1.0 and t["fallback_rate"] == 0.0
+    assert t["top_k_rate"]["8"] == 1.0
+    assert u["hit_rate"] <= 0.5 and cm["hit_rate"] <= 0.75
+    assert t["mean_rank"] < sa["mean_rank"] and t["top_k_rate"]["1"] > sa["top_k_rate"]["1"]
