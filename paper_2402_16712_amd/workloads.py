@@ -208,3 +208,17 @@ def ranker_matrix_torch(index: int, n=None, m=None, n_range=(500, 4000), m_range
     X = rank_one_matrix_torch(n, m, max(1, m // 10), n // 10, 20.0, 0.01, 1_000_003 * index + 17, device)
     lam = 0.05 * float(X.abs().sum(dim=0).max())
     return X, lam
+
+
+def accuracy_matrix(n: int, m: int, seed: int, noise_b: float = 1.0):
+    """The simulation of the paper's study of Algorithm 1 as lambda varies
+    (Sec. 3, "Effect of Varying m and n on Error and Sparsity"): a dense true
+    direction v with coordinates ~ U(-1, 1) scaled to unit l2 norm, scores
+    alpha ~ U(-100, 100), x_i = alpha_i v + Laplace(0, noise_b) noise, no
+    outliers.  Returns (X n x m column-major, v)."""
+    rng = _rng(10, seed, n, m)
+    v = rng.uniform(-1.0, 1.0, size=m)
+    v = v / np.sqrt(np.sum(v * v))
+    alpha = rng.uniform(-100.0, 100.0, size=n)
+    X = np.outer(alpha, v) + rng.laplace(0.0, noise_b, size=(n, m))
+    return np.asfortranarray(X), v
