@@ -65,12 +65,17 @@ extern "C" {
 #define L1LINE_EWIDE (-6)      /* a column's nonzero magnitudes span too many binades
                                   for exact 128-bit weight sums: (highest bit - lowest
                                   bit + 1) + bitlength(#nonzeros) > 124 (device)     */
-#define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N, or m above L1LINE_RANKER_MAX_M for the ranker (host check) */
+#define L1LINE_ESIZE (-7)      /* n above L1LINE_MAX_N (L1LINE_BP_MAX_N for Algorithms 2 and 3), or m
+                                  above L1LINE_RANKER_MAX_M for the ranker (host check) */
 #define L1LINE_EINTERNAL (-8)  /* a selection exceeded its round bound (device)      */
 #define L1LINE_EIO (-9)        /* a file could not be read or written, or is malformed */
 #define L1LINE_ENOMODEL (-10)  /* the context holds no ranker weights                */
 
-#define L1LINE_MAX_N 16384         /* rows per matrix (row ids are 16-bit in the segment lists) */
+#define L1LINE_MAX_N 65535         /* rows per matrix: the segment lists hold 16-bit row ids, and
+                                      with fewer than 2^16 nonzeros per column the 37-bit chunk
+                                      sums of the exact weights stay below 2^53 */
+#define L1LINE_BP_MAX_N 16384      /* rows per matrix for l1line_breakpoints and
+                                      l1line_solution_path (ESIZE above)           */
 #define L1LINE_MAX_LAMBDAS 128     /* penalties per call (passed by value)        */
 
 typedef struct l1line_ctx_s *l1line_ctx;

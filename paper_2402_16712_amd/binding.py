@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_PKG, "_build", "libl1line.so")
 
 OK, EINVAL, EHIP, ENONFINITE, ERANGE, ENOMEM, EWIDE, ESIZE, EINTERNAL, EIO, ENOMODEL = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
-MAX_N = 16384
+MAX_N = 65535
+BP_MAX_N = 16384
 MAX_LAMBDAS = 128
 NOALLOC_MAX_M = 1024
 

@@ -93,8 +93,9 @@ __device__ __forceinline__ u128 fixed_of_col(double a, int e0) {
 // in doubles: |a| / 2^e0 = c2 2^74 + c1 2^37 + c0.  Scaling by powers of two,
 // floor and the fused remainders are exact.  With the column range check
 // (|a| / 2^e0 < 2^(124 - b), b the bit length of the column's nonzero count,
-// at most 15) every chunk sum over a column stays below 2^53, so FP64 adds of
-// chunks are exact in any order.
+// at most 16 for fewer than 65536 rows) every chunk sum over a column stays
+// below 2^53 (c0, c1 < 2^37 summed fewer than 2^16 times; c2 < 2^(50 - b)),
+// so FP64 adds of chunks are exact in any order.
 __device__ __forceinline__ void weight_chunks(double a, int e0, double &c0, double &c1, double &c2) {
   const double ws = ldexp(fabs(a), -e0);
   c2 = floor(ws * 0x1p-74);
@@ -104,7 +105,7 @@ __device__ __forceinline__ void weight_chunks(double a, int e0, double &c0, doub
 }
 
 // A column through a raw buffer descriptor (word 3: 32-bit data format, no
-// swizzle); n <= 16384 rows, so n 8 bytes fits the size field.  Loads past
+// swizzle); n < 65536 rows, so n 8 bytes fits the size field.  Loads past
 // the column's end return 0, so a wave can run a uniform loop over row
 // steps with no bounds branch.
 constexpr int COL_RSRC_WORD3 = 0x00020000;

@@ -554,7 +554,9 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
   l1line_ctx pc = prof ? ctx : nullptr;
 
   // window list capacity: the larger path list where the LDS allows it
-  const size_t lds_max = seg_lds_bytes(L1LINE_MAX_N, L1LINE_MAX_LAMBDAS, WIN_CAP);
+  // the dynamic LDS the segment kernels may request (about 154 KB of the
+  // CU's 160 KB): the path list's larger capacity is taken when it fits
+  const size_t lds_max = seg_lds_bytes(4 * SXJ_LDS_MAX, L1LINE_MAX_LAMBDAS, WIN_CAP);
   // column j goes to LDS up to SXJ_LDS_MAX rows; longer ones are read from
   // global memory, which keeps room for more workgroups per CU
   const int sxj_rows = Ly.nmax <= SXJ_LDS_MAX ? Ly.nmax : 0;
@@ -1658,6 +1660,7 @@ static int breakpoints_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t 
   if (!ctx || !offsets || capacity < 0 || (capacity > 0 && (!lam || !v || !row))) return L1LINE_EINVAL;
   int st = check_matrix(X, n, m, ld);
   if (st) return st;
+  if (n > L1LINE_BP_MAX_N) return L1LINE_ESIZE;
   if (m > L1LINE_BP_MAX_M) return L1LINE_ESIZE;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
@@ -1767,6 +1770,7 @@ static int solution_path_impl(l1line_ctx ctx, const double *X, int64_t n, int64_
     return L1LINE_EINVAL;
   int st = check_matrix(X, n, m, ld);
   if (st) return st;
+  if (n > L1LINE_BP_MAX_N) return L1LINE_ESIZE;
   if (m > L1LINE_BP_MAX_M) return L1LINE_ESIZE;
   *count = 0;
   HIP_TRY(hipSetDevice(ctx->device));

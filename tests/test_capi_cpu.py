@@ -41,6 +41,7 @@ def test_header_constants_match_binding():
     text = open(os.path.join(ROOT, "include", "l1line.h")).read()
     consts = dict(re.findall(r"#define (L1LINE_\w+) \(?(-?\d+)\)?", text))
     assert int(consts["L1LINE_MAX_N"]) == B.MAX_N
+    assert int(consts["L1LINE_BP_MAX_N"]) == B.BP_MAX_N
     assert int(consts["L1LINE_MAX_LAMBDAS"]) == B.MAX_LAMBDAS
     assert int(consts["L1LINE_NOALLOC_MAX_M"]) == B.NOALLOC_MAX_M
     assert int(consts["L1LINE_EWIDE"]) == B.EWIDE and int(consts["L1LINE_ERANGE"]) == B.ERANGE
@@ -206,6 +207,9 @@ def test_components_and_breakpoints_host_checks():
     assert lib.l1line_breakpoints(f.h, P(1), 10, 4, 10, P(1), None, None, None, None, 5, None, None) == B.EINVAL
     assert lib.l1line_breakpoints(f.h, P(1), 10, 9000, 10, P(1), None, None, None, None, 0, None,
                                   None) == B.ESIZE
+    big = B.BP_MAX_N + 1                                   # Algorithms 2 and 3 keep the smaller row limit
+    assert lib.l1line_breakpoints(f.h, P(1), big, 4, big, P(1), None, None, None, None, 0, None,
+                                  None) == B.ESIZE
 
 
 def test_solution_path_host_checks():
@@ -223,4 +227,7 @@ def test_solution_path_host_checks():
     assert lib.l1line_solution_path(f.h, None, 10, 4, 10, 0, ctypes.byref(cnt), *([None] * 7), None,
                                     None) == B.EINVAL                                     # null X
     assert lib.l1line_solution_path(f.h, P(1), 10, 9000, 10, 0, ctypes.byref(cnt), *([None] * 7), None,
+                                    None) == B.ESIZE
+    big = B.BP_MAX_N + 1
+    assert lib.l1line_solution_path(f.h, P(1), big, 4, big, 0, ctypes.byref(cnt), *([None] * 7), None,
                                     None) == B.ESIZE

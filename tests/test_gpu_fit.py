@@ -98,6 +98,32 @@ def test_random_shapes_path(ctx, n, m):
     assert_path_equal(gpu_path(ctx, X, lams), O.fit_path(X, lams), f"{n}x{m}")
 
 
+@pytest.mark.parametrize("n,m,seed", [(20000, 6, 0), (50000, 4, 1), (65535, 3, 2)])
+def test_rows_beyond_16384(ctx, n, m, seed):
+    # more rows than the LDS copy of column j, up to the 16-bit row ids' limit
+    X = wl.random_small(3000 + seed, n, m, zero_frac=0.02)
+    mass = float(np.abs(X).sum(0).max())
+    lams = np.array([0.0, 1e-3 * mass, 0.05 * mass, 0.3 * mass, mass])
+    _say(f"case rows n={n} m={m}")
+    assert_path_equal(gpu_path(ctx, X, lams), O.fit_path(X, lams), f"{n}x{m}")
+    g = gpu_fit(ctx, X, float(lams[2]))
+    r = O.fit(X, float(lams[2]))
+    assert g["status"] == 0 and int(g["j"][0]) == r["j"] and g["z_all"].tobytes() == r["z_all"].tobytes()
+
+
+def test_rows_beyond_16384_structured_and_ties(ctx):
+    # the rank-one workload recipe with outlier rows at 30000 rows, and
+    # integer data at 40000 rows (thousands of tied ratios across the lists)
+    X = wl.rank_one_matrix(30000, 7, 2, 3000, 20.0, 0.01, (34, 30000))
+    lam = 0.05 * wl.max_column_mass(X)
+    _say("case rows 30000x7 rank one")
+    assert_path_equal(gpu_path(ctx, X, np.array([lam, 0.0])), O.fit_path(X, np.array([lam, 0.0])), "r1-30000")
+    Y = wl.random_small(77, 40000, 4, integer=True, zero_frac=0.1, span=3)
+    lams = np.array([0.0, 10.0, 1000.0, 20000.0])
+    _say("case rows 40000x4 integer")
+    assert_path_equal(gpu_path(ctx, Y, lams), O.fit_path(Y, lams), "int-40000")
+
+
 @pytest.mark.parametrize("seed,span", [(0, 1), (1, 2), (2, 2), (3, 3), (4, 5)])
 def test_integer_ties(ctx, seed, span):
     # integer data: many equal ratios and exact ties of the weighted median
