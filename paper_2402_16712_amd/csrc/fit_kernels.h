@@ -187,6 +187,19 @@ __device__ __forceinline__ uint64_t key_of_pair(bool in, double a, double b) {
   return ok ? key_of(r) : KEY_NONE;
 }
 
+// The top 32 bits of the key of row i's ratio, estimated by the hardware
+// reciprocal (x_ij != 0 at sample rows).  Sample keys only place window
+// bounds and pivots, and any keys are valid there (every element is decided
+// exactly against them), so neither the IEEE divide nor the low 32 bits of
+// the key are needed: a bound derived from a prefix p is p 2^32 (lower) or
+// p 2^32 + 2^32 - 1 (upper), at most 2^-20 relative off the sample's ratio.
+__device__ __forceinline__ uint32_t sample_key32(const SegIO &s, int i) {
+  const double a = sxj_at(s, i), b = gld(s.xk + i);
+  double r = b * __builtin_amdgcn_rcp(a);
+  r = r + 0.0;
+  return (uint32_t)(key_of(r) >> 32);
+}
+
 // exact weight |x_ij| / 2^e0 of row i, 0 where !valid
 __device__ __forceinline__ u128 seg_weight(const SegIO &s, int i, bool valid) {
   const double a = sxj_at(s, valid ? i : 0);
@@ -709,6 +722,29 @@ __device__ __forceinline__ void wave_sort2_kr(uint64_t &ka, int &ra, uint64_t &k
           kb = okb;
           rb = orb;
         }
+      }
+    }
+  }
+}
+
+// Bitonic sort of 128 32-bit keys held two per lane (element 2 lane + r),
+// ascending, through VALU lane exchanges.
+__device__ __forceinline__ void wave_sort2_u32_x(uint32_t &a, uint32_t &b, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const bool up = ((2 * lane) & size) == 0;
+      if (stride == 1) {
+        const uint32_t lo = min(a, b), hi = max(a, b);
+        a = up ? lo : hi;
+        b = up ? hi : lo;
+      } else {
+        const int ls = stride >> 1;
+        const uint32_t oa = xswap32(a, ls), ob = xswap32(b, ls);
+        const bool keep_min = (((2 * lane) & stride) == 0) == up;
+        a = keep_min ? min(oa, a) : max(oa, a);
+        b = keep_min ? min(ob, b) : max(ob, b);
       }
     }
   }
@@ -1353,8 +1389,14 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     }
     const bool neg = sd == 1;
     const uint64_t klo0 = neg ? 0ull : KEY_ZERO, khi0 = neg ? KEY_ZERO - 1 : KEY_NONE - 1;
-    uint64_t sa = seg_key(s, srow[lane]), sb = seg_key(s, srow[lane + 64]);
-    wave_sort2_x(sa, sb, lane);
+    // the sample's keys (top 32 bits), sorted across the wave
+    uint32_t sa = sample_key32(s, srow[lane]), sb = sample_key32(s, srow[lane + 64]);
+    wave_sort2_u32_x(sa, sb, lane);
+    // sample position ix as a lower or upper key bound
+    auto sample_lo = [&](int ix) {
+      return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((ix & 1) ? sb : sa), ix >> 1)) << 32;
+    };
+    auto sample_hi = [&](int ix) { return sample_lo(ix) | 0xFFFFFFFFull; };
     int prev_row = -2;
     double prev_e = 0.0;
     // penalties in groups of 64, lane l holding the target of penalty 64 g + l
@@ -1393,11 +1435,11 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         const int ihi = (int)ceil((whi + WDELTA) * SAMPLE_ROWS);
         uint64_t plo = klo0, phi = khi0;
         if (ilo >= 0 && ilo < SAMPLE_ROWS) {
-          const uint64_t v = uni_u64(shfl_u64((ilo & 1) ? sb : sa, ilo >> 1));
+          const uint64_t v = sample_lo(ilo);
           plo = v > plo ? v : plo;
         }
         if (ihi >= 0 && ihi < SAMPLE_ROWS) {
-          const uint64_t v = uni_u64(shfl_u64((ihi & 1) ? sb : sa, ihi >> 1));
+          const uint64_t v = sample_hi(ihi);
           phi = v < phi ? v : phi;
         }
         if (plo > khi0) plo = khi0;
@@ -1485,7 +1527,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             for (int c = 0; c < 3; ++c) {
               int ix = (int)floor((wlo + 0.04 * (c - 1)) * SAMPLE_ROWS);
               ix = ix < 0 ? 0 : (ix >= SAMPLE_ROWS ? SAMPLE_ROWS - 1 : ix);
-              piv[c] = uni_u64(shfl_u64((ix & 1) ? sb : sa, ix >> 1));
+              piv[c] = sample_lo(ix);
             }
             piv[1] = piv[1] < piv[0] ? piv[0] : piv[1];
             piv[2] = piv[2] < piv[1] ? piv[1] : piv[2];
