@@ -210,7 +210,9 @@ int l1line_autotune(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
 
 /* Read / set the context's default launch parameters, used for size
  * classes without a tuned entry (HOST [3]: workgroups per CU in [1, 16],
- * fewest k per item >= 1, items per CU in [1, 4096]). */
+ * fewest k per item >= 1, items per CU in [1, 4096]; initially 4, 8, 24:
+ * four 256-thread workgroups per CU fill the four wave slots per SIMD that
+ * the segment kernel's registers allow wherever its LDS leaves room). */
 int l1line_tune_get(l1line_ctx ctx, int32_t *params);
 int l1line_tune_set(l1line_ctx ctx, const int32_t *params);
 

@@ -1246,17 +1246,29 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     for (int i = threadIdx.x; i < T * 64; i += blockDim.x) sxj_lds[i] = i < n ? xjg[i] : 0.0;
   const double *__restrict__ sxj = kLdsJ ? (const double *)sxj_lds : xjg;
   for (int t = threadIdx.x; t < L; t += blockDim.x) slam[t] = lambda_fixed(lam[t], cj.e0);
-  if (threadIdx.x == 0) *knext = kbeg;
-  // the item's words of the zero-segment mask (segments settled by
-  // k_zero_segments are skipped)
-  __shared__ unsigned long long smask[SEG_MASK_WORDS];
-  const int w0 = kbeg >> 6, nwords = kend > kbeg ? ((kend - 1) >> 6) - w0 + 1 : 0;
-  const bool use_mask = maskrow != nullptr && nwords <= SEG_MASK_WORDS;
-  if (use_mask)
-    for (int w = threadIdx.x; w < nwords; w += blockDim.x) smask[w] = maskrow[w0 + w];
+  if (threadIdx.x == 0) *knext = 0;
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the item's live segments: k in [kbeg, kend) not settled by
+  // k_zero_segments.  Lane l holds word l of the item's mask inverted (bit b:
+  // segment 64 (w0 + l) + b is live) and the live count of the words below
+  // it; the waves claim live segments by their rank, so settled ones cost no
+  // claim.  Without the mask every segment of the range is live.
+  const int w0 = kbeg >> 6, nwords = kend > kbeg ? ((kend - 1) >> 6) - w0 + 1 : 0;
+  const bool use_mask = maskrow != nullptr && nwords <= SEG_MASK_WORDS;
+  uint64_t live = 0;
+  int kpre = 0, nlive = kend - kbeg;
+  if (use_mask) {
+    if (lane < nwords) {
+      const int lo = max(kbeg - 64 * (w0 + lane), 0), hi = min(kend - 64 * (w0 + lane), 64);
+      const uint64_t range = (hi == 64 ? ~0ull : (1ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
+      live = ~maskrow[w0 + lane] & range;
+    }
+    const int cnt = __builtin_popcountll(live);
+    kpre = wave_excl_scan_int(cnt, lane);
+    nlive = uni_int(__shfl(kpre + cnt, 63));
+  }
   if (wave == 0) {
     // systematic sample of SAMPLE_ROWS rows with probability ~ |x_ij|: lane l
     // owns the contiguous rows [l T, l T + T)
@@ -1301,12 +1313,25 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
   while (Tp < T) Tp <<= 1;
   int err = 0;
 
+  // claims are taken one segment ahead, so the counter's round trip overlaps
+  // the current segment (claims only grow: once one is past the live count,
+  // so is every later one)
+  int claim = 0;
+  if (lane == 0) claim = atomicAdd(knext, 1);
   while (true) {
-    int k = 0;
-    if (lane == 0) k = atomicAdd(knext, 1);
-    k = uni_int(__shfl(k, 0));
-    if (k >= kend) break;
-    if (use_mask && ((smask[(k >> 6) - w0] >> (k & 63)) & 1ull)) continue;
+    const int c = __builtin_amdgcn_readlane(claim, 0);
+    if (c >= nlive) break;
+    if (lane == 0) claim = atomicAdd(knext, 1);
+    int k = kbeg + c;
+    if (use_mask) {
+      // the c-th live segment: the last word whose live prefix is <= c, then
+      // the (c - prefix)-th set bit of that word
+      const int w = __builtin_popcountll(__ballot(lane < nwords && kpre <= c)) - 1;
+      const uint64_t lw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(live >> 32), w) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)live, w);
+      const int r = c - __builtin_amdgcn_readlane(kpre, w);
+      k = 64 * (w0 + w) + __builtin_ctzll(__ballot(((lw >> lane) & 1ull) && lanes_below(lw) == r));
+    }
     const long long base = (long long)j * m + k;
     if (k == j || cj.flags) {
       if (lane == 0) {

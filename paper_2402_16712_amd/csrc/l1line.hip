@@ -714,7 +714,7 @@ static l1line_problem single(const double *X, int64_t n, int64_t m, int64_t ld, 
   return p;
 }
 
-static const TuneParams kDefaultTune = {3, 8, 24};
+static const TuneParams kDefaultTune = {4, 8, 24};
 
 static int bitlen(double x) {
   int b = 0;
