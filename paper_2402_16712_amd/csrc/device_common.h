@@ -394,6 +394,19 @@ __device__ __forceinline__ u128 wave_incl_scan_u128_x(u128 x, int lane) {
   return x;
 }
 
+// FP64 inclusive scan by the same butterfly (each result takes at most six
+// rounded adds of partial sums)
+__device__ __forceinline__ double wave_incl_scan_dbl_x(double x, int lane) {
+  double tot = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = xswapd(tot, d);
+    x = (lane & d) ? x + o : x;
+    tot = tot + o;
+  }
+  return x;
+}
+
 __device__ __forceinline__ void wave_sort_key_row_x(uint64_t &key, int &row, int lane) {
 #pragma unroll
   for (int size = 2; size <= 64; size <<= 1) {

@@ -1213,6 +1213,130 @@ __device__ __forceinline__ ExactSides exact_sides(const SegIO &s) {
   return e;
 }
 
+// Selection of one target from the division-free pass's window list in
+// FP64.  The list holds the window's elements (row order, count nwin); the
+// exact weight below the window lies in [SA, SB] (units 2^e0); tau is the
+// target's threshold (same units): the answer is the first element, in
+// (key, row) order, at which the weight below the window plus the list's
+// prefix reaches tau -- what the exact selection finds.  Here the weights
+// |x_ij| are summed in FP64.  Every value compared is a sum of nonnegative
+// weights of column j or a difference of such sums, at most W_j, reached
+// through at most 40 roundings (list sums: 8 per lane and 6 tree levels;
+// 128-bit values converted with 3; the walk's running sum), so it lies
+// within 40 u W_j of its exact value (u = 2^-53).  A comparison whose
+// operands differ by more than tol = 2^-38 W_j (2^15 u W_j) therefore has
+// the exact comparison's outcome; a closer one sets amb, and the caller
+// redoes the segment with the exact pass.  Live segments have lambda < W_j,
+// so tau is at most W_j.  Lists over 128 elements are first cut at three
+// sample keys (piv, ascending) to the part that holds the target, as the
+// exact path does.
+__device__ __forceinline__ void select_one_fp64(const SegIO &s, uint64_t *lk, unsigned short *lr, int &nwin,
+                                                int lane, u128 SA, u128 SB, u128 tau, double Wd,
+                                                const uint64_t *piv, uint64_t &okey, int &orow, bool &hit,
+                                                bool &amb) {
+  const double tol = 0x1p-38 * Wd;
+  // tau - (weight below the list) at both ends of the interval, in the
+  // column's own units; 0 when tau is at or below it (exactly known)
+  auto real_of = [&](u128 x) { return ldexp(u128_to_double_approx(x), s.e0); };
+  double DA = tau > SA ? real_of(tau - SA) : 0.0, DB = tau > SB ? real_of(tau - SB) : 0.0;
+  bool und = false;
+  if (nwin > 128) {
+    const uint64_t p0 = piv[0], p1 = piv[1] < p0 ? p0 : piv[1], p2 = piv[2] < p1 ? p1 : piv[2];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int e = lane; e < nwin; e += 64) {
+      const uint64_t key = lk[e];
+      const double w = fabs(sxj_at(s, lr[e]));
+      a0 = a0 + (key < p0 ? w : 0.0);
+      a1 = a1 + (key < p1 ? w : 0.0);
+      a2 = a2 + (key < p2 ? w : 0.0);
+    }
+    a0 = wave_sum_dbl_x(a0);
+    a1 = wave_sum_dbl_x(a1);
+    a2 = wave_sum_dbl_x(a2);
+    // parts below the target: pivots p with (weight below p) < D
+    auto below = [&](double D) {
+      const double d0 = a0 - D, d1 = a1 - D, d2 = a2 - D;
+      und = und || fabs(d0) <= tol || fabs(d1) <= tol || fabs(d2) <= tol;
+      return (d0 < 0.0 ? 1 : 0) + (d1 < 0.0 ? 1 : 0) + (d2 < 0.0 ? 1 : 0);
+    };
+    const int c = below(DA), cB = below(DB);
+    if (und || c != cB) {
+      amb = true;
+      return;
+    }
+    const uint64_t plo2 = c == 0 ? 0 : (c == 1 ? p0 : (c == 2 ? p1 : p2)), phi2 = c == 0 ? p0 : (c == 1 ? p1 : p2);
+    const double base = c == 0 ? 0.0 : (c == 1 ? a0 : (c == 2 ? a1 : a2));
+    // (c > 0: base < D by more than tol at both ends, so both stay positive)
+    DA = DA - base;
+    DB = DB - base;
+    // stable in-place compaction: an element never moves above its own
+    // slot, so slots not yet read are never overwritten
+    int kept = 0;
+    for (int e0 = 0; e0 < nwin; e0 += 64) {
+      const int e = e0 + lane;
+      const bool in = e < nwin;
+      const uint64_t key = in ? lk[e] : 0;
+      const unsigned short row = in ? lr[e] : 0;
+      const bool keep = in && (c == 0 || key >= plo2) && (c == 3 || key < phi2);
+      const uint64_t km = __ballot(keep);
+      const int d = kept + lanes_below(km);
+      kept += __builtin_popcountll(km);
+      if (keep) {
+        lk[d] = key;
+        lr[d] = row;
+      }
+    }
+    nwin = uni_int(kept);
+    wave_lds_sync();
+  }
+  const int N = wave_sort_list(lk, lr, nwin, lane);
+  const int E = N >> 6;
+  // lane l owns the sorted entries [E l, E l + E)
+  double tot = 0.0;
+  for (int q = 0; q < E; ++q) {
+    const int e = E * lane + q;
+    const bool valid = lk[e] != KEY_NONE;
+    tot = tot + (valid ? fabs(sxj_at(s, lr[e])) : 0.0);
+  }
+  const double incl = wave_incl_scan_dbl_x(tot, lane);
+  auto find = [&](double D, uint64_t &k, int &r) -> bool {
+    if (!(D > 0.0)) return false;                  // tau at or below the list
+    const double df = incl - D;
+    und = und || __ballot(fabs(df) <= tol) != 0;
+    const uint64_t owner = __ballot(df >= 0.0);
+    if (owner == 0) return false;                  // above the list
+    const int lo = __builtin_ctzll(owner);
+    double run = __shfl(incl, lo) - __shfl(tot, lo);
+    for (int q = 0; q < E; ++q) {
+      const int e = E * lo + q;
+      const uint64_t key = lk[e];
+      if (key == KEY_NONE) break;
+      run = run + fabs(sxj_at(s, lr[e]));
+      const double d = run - D;
+      und = und || fabs(d) <= tol;
+      if (d >= 0.0) {
+        k = key;
+        r = (int)lr[e];
+        return true;
+      }
+    }
+    und = true;                                    // (the owner's entries must reach D)
+    return false;
+  };
+  uint64_t kA = KEY_NONE, kB = KEY_NONE;
+  int rA = -1, rB = -1;
+  const bool hA = find(DA, kA, rA);
+  const bool hB = DB == DA ? hA : find(DB, kB, rB);
+  if (DB == DA) {
+    kB = kA;
+    rB = rA;
+  }
+  amb = amb || und || hA != hB || kA != kB || rA != rB;
+  okey = kA;
+  orow = rA;
+  hit = hA;
+}
+
 // One work item, by the whole workgroup (every thread calls it).  ci, V, E,
 // R and segflags are this problem's slices.  kLdsJ: column j is copied to LDS
 // (the pointer's address space is then known to the compiler: LDS loads).
@@ -1541,6 +1665,33 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
           const uint64_t wantm = __ballot(want);
           u128 SloA = SlwA, SloB = SlwB;
           bool amb = false;
+          if constexpr (!kMulti) {
+            if (use_fast) {
+              // one target after the division-free pass: the rest in FP64
+              // with rigorous margins (a close call is redone exactly)
+              uint64_t piv[3];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                int ix = (int)floor((wlo + 0.04 * (c - 1)) * SAMPLE_ROWS);
+                ix = ix < 0 ? 0 : (ix >= SAMPLE_ROWS ? SAMPLE_ROWS - 1 : ix);
+                piv[c] = sample_lo(ix);
+              }
+              uint64_t k2 = KEY_NONE;
+              int r2 = -1;
+              bool h2 = false;
+              if (wantm & 1ull)
+                select_one_fp64(s, lk, lr, nwin, lane, SlwA, SlwB, uni_u128(tau), Wd, piv, k2, r2, h2, amb);
+              if (!amb && h2 && lane == 0) {
+                okey = k2;
+                orow = r2;
+                hit = true;
+              }
+              wave_lds_sync();
+              if (!amb) break;
+              use_fast = false;
+              continue;
+            }
+          }
           if (__builtin_popcountll(wantm) == 1 && nwin > 128) {
             // one target: only the quarter of the window that holds it is
             // sorted.  Three sample keys around the target split the list;
