@@ -801,12 +801,70 @@ __device__ __forceinline__ void wave_sort2_kr_x(uint64_t &ka, int &ra, uint64_t 
   }
 }
 
+// The same network over 256 entries, four per lane (entry 4 lane + q in
+// slot q): strides 1 and 2 pair slots of one lane, longer strides pair slot q
+// with slot q of lane (lane ^ stride / 4).
+__device__ __forceinline__ void wave_sort4_kr_x(uint64_t (&k)[4], int (&r)[4], int lane) {
+#pragma unroll
+  for (int size = 2; size <= 256; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride < 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q & stride) continue;
+          const int p = q | stride;
+          const bool up = ((4 * lane + q) & size) == 0;
+          const bool sw = (k[p] < k[q] || (k[p] == k[q] && r[p] < r[q])) == up;
+          const uint64_t tk = k[q];
+          const int tr = r[q];
+          k[q] = sw ? k[p] : k[q];
+          r[q] = sw ? r[p] : r[q];
+          k[p] = sw ? tk : k[p];
+          r[p] = sw ? tr : r[p];
+        }
+      } else {
+        const int ls = stride >> 2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool up = ((4 * lane + q) & size) == 0;
+          const bool keep_min = ((lane & ls) == 0) == up;
+          const uint64_t ok = xswap64(k[q], ls);
+          const int orow = (int)xswap32((uint32_t)r[q], ls);
+          const bool lt = ok < k[q] || (ok == k[q] && orow < r[q]);
+          k[q] = lt == keep_min ? ok : k[q];
+          r[q] = lt == keep_min ? orow : r[q];
+        }
+      }
+    }
+  }
+}
+
 // Sorts the window list lk/lr[0, nlist) ascending in (key, row) and pads it
 // with (KEY_NONE, 0xFFFF) to N = the returned power of two (>= 64).  Lists of
-// up to 128 are sorted in registers (shuffles, no LDS round trips per stage)
-// and written back; longer ones by the LDS network.
+// up to 256 are sorted in registers (VALU lane exchanges, no LDS round trips
+// per stage) and written back; longer ones by the LDS network.
 __device__ __forceinline__ int wave_sort_list(uint64_t *lk, unsigned short *lr, int nlist, int lane) {
-  if (nlist > 128) return wave_sort_lds(lk, lr, nlist, lane);
+  if (nlist > 256) return wave_sort_lds(lk, lr, nlist, lane);
+  if (nlist > 128) {
+    uint64_t k[4];
+    int r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = 4 * lane + q;
+      k[q] = e < nlist ? lk[e] : KEY_NONE;
+      r[q] = e < nlist ? (int)lr[e] : 0xFFFF;
+    }
+    wave_sort4_kr_x(k, r, lane);
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      lk[4 * lane + q] = k[q];
+      lr[4 * lane + q] = (unsigned short)r[q];
+    }
+    wave_lds_sync();
+    return 256;
+  }
   if (nlist <= 64) {
     uint64_t k = lane < nlist ? lk[lane] : KEY_NONE;
     int r = lane < nlist ? (int)lr[lane] : 0xFFFF;
