@@ -627,21 +627,29 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
 #pragma unroll
   for (int r = 0; r < G; ++r) fin = fin && __builtin_isfinite(v[r]);
   if (fin) {
-    // rows past n read 0 from both columns and add |0 - v 0| = +0
+    // rows past n read 0 from both columns and add |0 - v 0| = +0; the
+    // rows in batches of RB slots, every load of a batch issued before the
+    // first is used (the sums still run slot by slot in increasing order)
     const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, s.n), rj = col_rsrc(s.lds ? s.xk : s.sxj, s.n);
-    double an = sxj_pad(s, rj, s.lane), bn = col_ld(rk, s.lane * 8);
-    for (int t = 0; t < s.T; ++t) {
-      const int i = s.lane + 64 * t;
-      const double a = an, b = bn;
-      if (t + 1 < s.T) {
-        an = sxj_pad(s, rj, i + 64);
-        bn = col_ld(rk, (i + 64) * 8);
+    constexpr int RB = 4;
+    for (int t0 = 0; t0 < s.T; t0 += RB) {
+      double av[RB], bv[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        // (slots past T, of the last batch: 0 from both columns)
+        const bool in = t0 + q < s.T;
+        const int i = s.lane + 64 * (t0 + q);
+        av[q] = in ? sxj_pad(s, rj, i) : 0.0;
+        bv[q] = in ? col_ld(rk, i * 8) : 0.0;
       }
 #pragma unroll
-      for (int r = 0; r < G; ++r) {
-        const double prod = v[r] * a;
-        const double d = b - prod;
-        p[r] = p[r] + fabs(d);
+      for (int q = 0; q < RB; ++q) {
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          const double prod = v[r] * av[q];
+          const double d = bv[q] - prod;
+          p[r] = p[r] + fabs(d);
+        }
       }
     }
 #pragma unroll
@@ -668,6 +676,25 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
   }
 #pragma unroll
   for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree_x(p[r]), 0);
+}
+
+// The next RJ residual jobs of mask jm (lanes whose target needs its own
+// e_jk; v_l: the lane's ratio): one pass over the rows scores them all, and
+// each job's lane receives its e in e_l.  Clears the jobs taken from jm.
+template <int RJ>
+__device__ __forceinline__ void run_jobs(const SegIO &s, uint64_t &jm, double v_l, int lane, double &e_l) {
+  int jl[RJ];
+  double jv[RJ], je[RJ];
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    jl[r] = jm ? __builtin_ctzll(jm) : -1;
+    jm &= jm ? jm - 1 : 0;
+    jv[r] = jl[r] >= 0 ? __shfl(v_l, jl[r]) : 0.0;
+  }
+  wave_residual_multi<RJ>(s, jv, je);
+#pragma unroll
+  for (int r = 0; r < RJ; ++r)
+    if (lane == jl[r]) e_l = je[r];
 }
 
 // Bitonic sort of 128 keys held two per lane (element 2*lane + r), ascending.
@@ -1893,21 +1920,10 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         if (lane == jl) e_l = e1;
       } else if constexpr (kMulti) {
         // (one penalty: at most one job)
-        constexpr int RJ = 4;
         uint64_t jm = needm;
         while (jm) {
-          int jl[RJ];
-          double jv[RJ], je[RJ];
-#pragma unroll
-          for (int r = 0; r < RJ; ++r) {
-            jl[r] = jm ? __builtin_ctzll(jm) : -1;
-            jm &= jm ? jm - 1 : 0;
-            jv[r] = jl[r] >= 0 ? __shfl(v_l, jl[r]) : 0.0;
-          }
-          wave_residual_multi<RJ>(s, jv, je);
-#pragma unroll
-          for (int r = 0; r < RJ; ++r)
-            if (lane == jl[r]) e_l = je[r];
+          if (__builtin_popcountll(jm) > 4) run_jobs<8>(s, jm, v_l, lane, e_l);
+          else run_jobs<4>(s, jm, v_l, lane, e_l);
         }
       }
       // each target takes the e of the last job at or before it (or the
