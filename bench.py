@@ -142,11 +142,12 @@ def _pmc_per_dispatch(path, counter):
     return {k: tot[k] / len(disp[k]) for k in tot}
 
 
-def pmc_summary(fetch_csv, write_csv, copyf_csv, copyw_csv, sq_csv=None):
+def pmc_summary(fetch_csv, write_csv, copyf_csv, copyw_csv, sq_csv=None, lds_csv=None):
     """The dominant kernel's counter record: HBM bytes per launch of
     k_seg_batch from the FETCH_SIZE and WRITE_SIZE counters, each scaled by
     what the counter reads for a copy of exactly 512 MiB (bench.py
-    --calibrate-copy), and (optional) SQ_INSTS_VALU / SQ_INSTS_LDS per launch."""
+    --calibrate-copy), (optional) SQ_INSTS_VALU / SQ_INSTS_LDS per launch
+    and (optional) SQ_LDS_IDX_ACTIVE / GRBM_GUI_ACTIVE per launch."""
     nbytes = 512 << 20
     cf = _pmc_per_dispatch(copyf_csv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"] * 1024
     cw = _pmc_per_dispatch(copyw_csv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"] * 1024
@@ -162,6 +163,9 @@ def pmc_summary(fetch_csv, write_csv, copyf_csv, copyw_csv, sq_csv=None):
     if sq_csv:
         rec["sq_insts_valu"] = _pmc_per_dispatch(sq_csv, "SQ_INSTS_VALU")[kern]
         rec["sq_insts_lds"] = _pmc_per_dispatch(sq_csv, "SQ_INSTS_LDS")[kern]
+    if lds_csv:
+        rec["sq_lds_idx_active"] = _pmc_per_dispatch(lds_csv, "SQ_LDS_IDX_ACTIVE")[kern]
+        rec["grbm_gui_active"] = _pmc_per_dispatch(lds_csv, "GRBM_GUI_ACTIVE")[kern]
     out = {"seg_2000x2000": rec}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
@@ -461,6 +465,20 @@ def main():
                          "lds_instructions_per_launch": rec.get("sq_insts_lds"),
                          "valu_busy": busy,
                          "basis": "SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time)"}
+    if rec and rec.get("sq_insts_lds") and rec.get("sq_lds_idx_active") and rec.get("grbm_gui_active"):
+        # the window lists' sort and scan run through the LDS: its index
+        # unit's busy share of the launch (GRBM_GUI_ACTIVE sums the 8 XCDs'
+        # cycles, SQ_LDS_IDX_ACTIVE the 256 CUs'), and the bytes moved if
+        # every LDS instruction moves 8 bytes per lane, against the measured
+        # LDS read peak
+        lds_bytes = rec["sq_insts_lds"] * 64 * 8
+        roof["lds"] = {"instructions_per_launch": rec["sq_insts_lds"],
+                       "busy": rec["sq_lds_idx_active"] / (256 * rec["grbm_gui_active"] / 8),
+                       "bytes_est": lds_bytes, "achieved_GBps_est": lds_bytes / seg_s / 1e9,
+                       "peak_measured_GBps": peaks["lds_GBps"],
+                       "frac_est": lds_bytes / seg_s / 1e9 / peaks["lds_GBps"],
+                       "basis": "busy = SQ_LDS_IDX_ACTIVE / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs); bytes = "
+                                "SQ_INSTS_LDS x 64 lanes x 8 B (the list keys and column j are 8-byte entries)"}
 
     # the sign-sum contraction on the FP64 matrix units: the MFMAs the
     # kernel issues (the Zr product only for 4 x 16 blocks holding a zero)

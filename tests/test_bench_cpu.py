@@ -59,8 +59,11 @@ def test_traffic_summary_and_source_rule(tmp_path, monkeypatch):
                                   (1, "k_signsum_batch(int)", "WRITE_SIZE", 60.0)])
     sq = _csv(tmp_path / "sq.csv", [(1, "void k_seg_batch<true, false>(int)", "SQ_INSTS_VALU", 5.0e9),
                                     (1, "void k_seg_batch<true, false>(int)", "SQ_INSTS_LDS", 7.0e8)])
-    bench.pmc_summary(f, w, cf, cw, sq)
+    lds = _csv(tmp_path / "lds.csv", [(1, "void k_seg_batch<true, false>(int)", "SQ_LDS_IDX_ACTIVE", 8.0e8),
+                                      (1, "void k_seg_batch<true, false>(int)", "GRBM_GUI_ACTIVE", 1.4e8)])
+    bench.pmc_summary(f, w, cf, cw, sq, lds)
     rec = json.load(open(tmp_path / "profiles" / "traffic.json"))["seg_2000x2000"]
+    assert rec["sq_lds_idx_active"] == 8.0e8 and rec["grbm_gui_active"] == 1.4e8
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     # the dominant kernel alone
     assert rec["bytes_per_launch"] == pytest.approx((1000.0 * 2.0 + 300.0) * 1024)
