@@ -221,6 +221,10 @@ __device__ __forceinline__ void take_sample(bool c, int pri, uint64_t key, int t
 // penalties, PATH_CAP for paths when the LDS allows).
 constexpr int WIN_CAP = 512;
 constexpr int PATH_CAP = 1024;
+// (the LDS sort pads a list to the next power of two, which must stay
+// inside the wave's area)
+static_assert((WIN_CAP & (WIN_CAP - 1)) == 0 && (PATH_CAP & (PATH_CAP - 1)) == 0,
+              "window list capacities must be powers of two");
 struct WaveScratch {
   uint64_t ckey[64];
   int crow[64];

@@ -558,9 +558,21 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
   // CU's 160 KB): the path list's larger capacity is taken when it fits
   const size_t lds_max = seg_lds_bytes(4 * SXJ_LDS_MAX, L1LINE_MAX_LAMBDAS, WIN_CAP);
   // column j goes to LDS up to SXJ_LDS_MAX rows; longer ones are read from
-  // global memory, which keeps room for more workgroups per CU
-  const int sxj_rows = Ly.nmax <= SXJ_LDS_MAX ? Ly.nmax : 0;
+  // global memory, which keeps room for more workgroups per CU.  The copy is
+  // also left out where that lets more workgroups share a CU (column j then
+  // comes from L2, where it stays across the item's k): the several-penalty
+  // kernel's 1024-entry lists leave room for two 2000-row workgroups per CU
+  // with the copy and three without (path L = 64 at 2000x2000: 66.8 -> 61.7
+  // ms).  At most four: the waves per SIMD the kernel's registers allow.
+  auto wg_per_cu = [](size_t bytes) {
+    const size_t b = (bytes + 16 + 511) / 512 * 512;   // + static LDS, 512-byte granules
+    return std::min<size_t>(4, (size_t)160 * 1024 / b);
+  };
+  int sxj_rows = Ly.nmax <= SXJ_LDS_MAX ? Ly.nmax : 0;
   const int lcap = (Ly.Lmax > 1 && seg_lds_bytes(sxj_rows, Ly.Lmax, PATH_CAP) <= lds_max) ? PATH_CAP : WIN_CAP;
+  if (sxj_rows > 0 &&
+      wg_per_cu(seg_lds_bytes(0, Ly.Lmax, lcap)) > wg_per_cu(seg_lds_bytes(sxj_rows, Ly.Lmax, lcap)))
+    sxj_rows = 0;
   const size_t lds = seg_lds_bytes(sxj_rows, Ly.Lmax, lcap);
   if (!ctx->attr_seg) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_seg_batch<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
