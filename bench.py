@@ -49,14 +49,17 @@ def algorithmic_work(X):
             "flops": 2.0 * elements + 3.0 * residual_terms}
 
 
+SS_ROWS = 16   # rows per LDS stage of k_signsum_batch
+
+
 def signsum_mfma_issued(X):
     """FP64 MFMAs k_signsum_batch issues on X (column-major n x m): the
-    matrix is staged in 32-row steps and 64-column tiles (zero padded); per
-    64 x 64 output tile, every block of 4 rows x 16 columns k costs one
+    matrix is staged in SS_ROWS-row steps and 64-column tiles (zero padded);
+    per 64 x 64 output tile, every block of 4 rows x 16 columns k costs one
     16x16x4 MFMA per wave (4 waves) for D, and one more for Zr only when the
     block holds an exact zero (padding included)."""
     n, m = X.shape
-    n_pad, m_pad = -(-n // 32) * 32, -(-m // 64) * 64
+    n_pad, m_pad = -(-n // SS_ROWS) * SS_ROWS, -(-m // 64) * 64
     Z = np.ones((n_pad, m_pad), dtype=bool)
     Z[:n, :m] = (X == 0.0)
     blocks_zero = int(Z.reshape(n_pad // 4, 4, m_pad // 16, 16).any(axis=(1, 3)).sum())

@@ -932,7 +932,7 @@ __device__ __forceinline__ int wave_sort_list(uint64_t *lk, unsigned short *lr, 
 // below the decision margin the segment kernel applies.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int SS_TILE = 64;     // 64 (j) x 64 (k) outputs per workgroup, 4 waves of 16 x 64
-constexpr int SS_ROWS = 32;     // rows i per LDS stage
+constexpr int SS_ROWS = 16;     // rows i per LDS stage
 constexpr int SS_LD = SS_TILE + 2;
 
 // Fragment layout of v_mfma_f64_16x16x4f64 (wave64, measured on gfx950):
@@ -964,14 +964,34 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
     accD[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     accZ[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
   }
-  for (int i0 = 0; i0 < n; i0 += SS_ROWS) {
-    for (int e = tid; e < SS_ROWS * SS_TILE; e += 256) {
+  // rows in stages of SS_ROWS: each thread loads its PER + PER elements of
+  // the next stage into registers while the current one is multiplied, and
+  // stores column k's elements as their signs (computed once per element,
+  // not once per wave that reads them)
+  constexpr int PER = SS_ROWS * SS_TILE / 256;
+  double pa[PER], pb[PER];
+  auto load = [&](int i0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
       const int c = e / SS_ROWS, r = e % SS_ROWS, i = i0 + r;
       const int jc = sj[c], kc = k0 + c;
-      sA[r * SS_LD + c] = (i < n && jc >= 0) ? X[(long long)jc * ld + i] : 0.0;
-      sB[r * SS_LD + c] = (i < n && kc < m) ? X[(long long)kc * ld + i] : 0.0;
+      pa[q] = (i < n && jc >= 0) ? X[(long long)jc * ld + i] : 0.0;
+      pb[q] = (i < n && kc < m) ? X[(long long)kc * ld + i] : 0.0;
+    }
+  };
+  load(0);
+  for (int i0 = 0; i0 < n; i0 += SS_ROWS) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int c = e / SS_ROWS, r = e % SS_ROWS;
+      const double x = pb[q];
+      sA[r * SS_LD + c] = pa[q];
+      sB[r * SS_LD + c] = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
     }
     __syncthreads();
+    if (i0 + SS_ROWS < n) load(i0 + SS_ROWS);
 #pragma unroll 2
     for (int kk = 0; kk < SS_ROWS / 4; ++kk) {
       const int r = 4 * kk + (lane >> 4);
@@ -979,12 +999,10 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
       const double aa = fabs(a);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double x = sB[r * SS_LD + 16 * t + (lane & 15)];
-        const double sg = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
-        const double zr = x == 0.0 ? 1.0 : 0.0;
+        const double sg = sB[r * SS_LD + 16 * t + (lane & 15)];
         accD[t] = mfma_f64(a, sg, accD[t]);
         // exact zeros are rare: skip the product when this 4 x 16 block has none
-        if (__ballot(x == 0.0)) accZ[t] = mfma_f64(aa, zr, accZ[t]);
+        if (__ballot(sg == 0.0)) accZ[t] = mfma_f64(aa, sg == 0.0 ? 1.0 : 0.0, accZ[t]);
       }
     }
     __syncthreads();

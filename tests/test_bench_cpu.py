@@ -86,12 +86,14 @@ def test_algorithmic_work_and_issued_mfma_counts():
     assert w["residual_terms"] == 70 * 130 * 129
     assert w["flops"] == 2 * w["ratio_elements"] + 3 * w["residual_terms"]
     mf = bench.signsum_mfma_issued(X)
-    # padded to 96 rows x 192 columns: 24 x 12 blocks, 3 column tiles of 64, 4 waves
-    assert mf["mfma_D"] == 24 * 12 * 3 * 4
-    # zero blocks: the real zero, every block of padded rows (70..95 -> rows
-    # blocks 17..23 hold padding: 7 x 12) and of padded columns (130..191:
-    # column blocks 8..11 -> 4 x 24), without counting twice
-    pad_rows = 7 * 12
-    pad_cols = 4 * 24
-    both = 7 * 4
+    assert bench.SS_ROWS == 16
+    # padded to 80 rows (16-row stages) x 192 columns: 20 x 12 blocks, 3
+    # column tiles of 64, 4 waves
+    assert mf["mfma_D"] == 20 * 12 * 3 * 4
+    # zero blocks: the real zero, every block of padded rows (70..79 -> row
+    # blocks 17..19 hold padding: 3 x 12) and of padded columns (130..191:
+    # column blocks 8..11 -> 4 x 20), without counting twice
+    pad_rows = 3 * 12
+    pad_cols = 4 * 20
+    both = 3 * 4
     assert mf["mfma_Zr"] == (1 + pad_rows + pad_cols - both) * 3 * 4
