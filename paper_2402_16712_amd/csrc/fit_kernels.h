@@ -1063,7 +1063,7 @@ k_signsum_one(const double *__restrict__ X, int n, int m, long long ld, double2 
 constexpr int SEG_WAVES = 4;
 constexpr int SAMPLE_ROWS = 128;
 constexpr int SXJ_LDS_MAX = 4096;   // longest column j copied to LDS (32 KB)
-constexpr int SEG_MASK_WORDS = 64;  // zero-segment mask words an item reads into LDS (4096 k)
+constexpr int SEG_MASK_WORDS = 64;  // zero-segment mask words an item holds (one per lane: 4096 k)
 
 __host__ __device__ constexpr size_t seg_sxj_bytes(int n) {
   return ((size_t)((n + 63) / 64) * 64 * 8 + 15) / 16 * 16;
