@@ -394,6 +394,32 @@ __device__ __forceinline__ u128 wave_incl_scan_u128_x(u128 x, int lane) {
   return x;
 }
 
+// Minimum / maximum over the wave through VALU exchanges (uniform result)
+__device__ __forceinline__ uint64_t wave_min_u64_x(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = xswap64(x, d);
+    x = o < x ? o : x;
+  }
+  return uni_u64(x);
+}
+__device__ __forceinline__ uint64_t wave_max_u64_x(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = xswap64(x, d);
+    x = o > x ? o : x;
+  }
+  return uni_u64(x);
+}
+
+// x of lane l (l uniform), without an LDS round trip
+__device__ __forceinline__ double readlane_dbl(double x, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // FP64 inclusive scan by the same butterfly (each result takes at most six
 // rounded adds of partial sums)
 __device__ __forceinline__ double wave_incl_scan_dbl_x(double x, int lane) {

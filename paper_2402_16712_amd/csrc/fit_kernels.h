@@ -495,7 +495,7 @@ __device__ __forceinline__ void wave_list_sums(const SegIO &s, const uint64_t *l
 __device__ __forceinline__ void wave_resolve(const SegIO &s, const uint64_t *lk, const unsigned short *lr, int E,
                                              u128 Slo, u128 tot, u128 incl, bool active, u128 tau,
                                              uint64_t &okey, int &orow, bool &hit) {
-  const u128 wall = shfl_u128(incl, 63);
+  const u128 wall = readlane_u128(incl, 63);
   const bool inwin = active && tau > Slo && tau <= Slo + wall;
   int lo = 0, hi = 63;
 #pragma unroll
@@ -657,7 +657,7 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
       }
     }
 #pragma unroll
-    for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree_x(p[r]), 0);
+    for (int r = 0; r < G; ++r) e[r] = readlane_dbl(wave_r64_tree_x(p[r]), 0);
     return;
   }
   const int l0 = s.lane < s.n ? s.lane : 0;
@@ -679,7 +679,7 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
     }
   }
 #pragma unroll
-  for (int r = 0; r < G; ++r) e[r] = __shfl(wave_r64_tree_x(p[r]), 0);
+  for (int r = 0; r < G; ++r) e[r] = readlane_dbl(wave_r64_tree_x(p[r]), 0);
 }
 
 // The next RJ residual jobs of mask jm (lanes whose target needs its own
@@ -693,7 +693,7 @@ __device__ __forceinline__ void run_jobs(const SegIO &s, uint64_t &jm, double v_
   for (int r = 0; r < RJ; ++r) {
     jl[r] = jm ? __builtin_ctzll(jm) : -1;
     jm &= jm ? jm - 1 : 0;
-    jv[r] = jl[r] >= 0 ? __shfl(v_l, jl[r]) : 0.0;
+    jv[r] = jl[r] >= 0 ? readlane_dbl(v_l, jl[r]) : 0.0;
   }
   wave_residual_multi<RJ>(s, jv, je);
 #pragma unroll
@@ -1413,7 +1413,7 @@ __device__ __forceinline__ void select_one_fp64(const SegIO &s, uint64_t *lk, un
     const uint64_t owner = __ballot(df >= 0.0);
     if (owner == 0) return false;                  // above the list
     const int lo = __builtin_ctzll(owner);
-    double run = __shfl(incl, lo) - __shfl(tot, lo);
+    double run = readlane_dbl(incl, lo) - readlane_dbl(tot, lo);
     for (int q = 0; q < E; ++q) {
       const int e = E * lo + q;
       const uint64_t key = lk[e];
@@ -1614,7 +1614,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         if (g0 == 0) nz0 = nzm;
         else nz1 = nzm;
         // every nonzero penalty has the same side (A <= B)
-        if (nzm) sd = __shfl(side, __builtin_ctzll(nzm));
+        if (nzm) sd = __builtin_amdgcn_readlane(side, __builtin_ctzll(nzm));
       }
     } else {
       for (int t = 0; t < Lg; ++t) {
@@ -1668,9 +1668,14 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       }
       // window bounds on the targets' weight fractions (positive doubles
       // order as their bit patterns)
-      const double qmin = __longlong_as_double((long long)wave_min_u64((uint64_t)__double_as_longlong(fmax(q, 0.0))));
-      const double qmax =
-          __longlong_as_double((long long)wave_max_u64((uint64_t)__double_as_longlong(act ? fmax(q, 0.0) : 0.0)));
+      double qmin, qmax;
+      if constexpr (!kMulti) {
+        // one penalty: lane 0's target (no cross-lane reduction)
+        qmin = qmax = __longlong_as_double((long long)uni_u64((uint64_t)__double_as_longlong(fmax(q, 0.0))));
+      } else {
+        qmin = __longlong_as_double((long long)wave_min_u64_x((uint64_t)__double_as_longlong(fmax(q, 0.0))));
+        qmax = __longlong_as_double((long long)wave_max_u64_x((uint64_t)__double_as_longlong(act ? fmax(q, 0.0) : 0.0)));
+      }
       uint64_t okey = KEY_NONE;
       int orow = -1;
       bool hit = false;
@@ -1682,8 +1687,8 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         bool mine = act;
         if (pass > 0) {
           const int t = pass - 1;
-          if (!((nzg >> t) & 1ull) || __shfl((int)hit, t)) continue;
-          wlo = whi = __shfl(q, t);
+          if (!((nzg >> t) & 1ull) || __builtin_amdgcn_readlane((int)hit, t)) continue;
+          wlo = whi = readlane_dbl(q, t);
           mine = lane == t;
         }
         constexpr double WDELTA = 0.08;
@@ -1920,6 +1925,19 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         }
       }
 
+      if constexpr (!kMulti) {
+        // one penalty (lane 0): the residual of its row, or the column mass
+        // of k where v_k = 0; values taken from lane 0 without shuffles
+        const int orw0 = __builtin_amdgcn_readfirstlane((nzg & 1ull) ? orow : -1);
+        const double v0 = orw0 >= 0 ? ratio_of_key(uni_u64(okey)) : 0.0;
+        const double e0 = orw0 >= 0 ? wave_residual<true>(s, v0) : Wk;   // (the sum in lane 0)
+        if (lane == 0) {
+          V[base] = v0;
+          E[base] = e0;
+          R[base] = orw0;
+        }
+        continue;
+      }
       // residuals, reused while the selected row repeats: the group's targets
       // whose row differs from the previous target's are the jobs, scored up
       // to RJ at a time in one pass over the rows
@@ -1938,7 +1956,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
       double e_l = 0.0;
       if (__builtin_popcountll(needm) == 1) {
         const int jl = __builtin_ctzll(needm);
-        const double e1 = __shfl(wave_residual<!kMulti>(s, __shfl(v_l, jl)), 0);
+        const double e1 = readlane_dbl(wave_residual<!kMulti>(s, readlane_dbl(v_l, jl)), 0);
         if (lane == jl) e_l = e1;
       } else if constexpr (kMulti) {
         // (one penalty: at most one job)
@@ -1964,8 +1982,8 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         E[t * mm + base] = e_t;
         R[t * mm + base] = orw_l;
       }
-      prev_row = __shfl(orw_l, cnt - 1);
-      prev_e = __shfl(e_t, cnt - 1);
+      prev_row = __builtin_amdgcn_readlane(orw_l, cnt - 1);
+      prev_e = readlane_dbl(e_t, cnt - 1);
     }
   }
   if (err && lane == 0) atomicOr(segflags + j, err);
