@@ -1501,37 +1501,62 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     nlive = uni_int(__shfl(kpre + cnt, 63));
   }
   if (wave == 0) {
-    // systematic sample of SAMPLE_ROWS rows with probability ~ |x_ij|: lane l
-    // owns the contiguous rows [l T, l T + T)
-    const int r0 = lane * T, r1 = min(n, r0 + T);
-    double tot = 0.0;
-    for (int i = r0; i < r1; ++i) tot = tot + fabs(sxj[i]);
-    const double incl = wave_incl_scan_dbl(tot, lane);
-    const double all = __shfl(incl, 63);
+    // systematic sample of SAMPLE_ROWS rows with probability ~ |x_ij|: the
+    // cumulative weight runs over the rows in order, 64 rows (one per lane)
+    // at a time; sample r is the row whose weight interval holds (r + 1/2)
+    // step.  Consecutive lanes read consecutive rows (no LDS bank conflicts).
+    auto wt = [&](int i) {
+      const double a = sxj[i < n ? i : 0];
+      return i < n ? fabs(a) : 0.0;
+    };
+    double part = 0.0;
+    for (int t = 0; t < T; ++t) part = part + wt(lane + 64 * t);
+    const double all = wave_sum_dbl_x(part);
     for (int r = lane; r < SAMPLE_ROWS; r += 64) srow[r] = -1;
     wave_lds_sync();
     if (all > 0.0) {
       const double step = all / SAMPLE_ROWS;
-      double cum = incl - tot;
-      for (int i = r0; i < r1; ++i) {
-        const double nxt = cum + fabs(sxj[i]);
+      double base = 0.0;
+      for (int t = 0; t < T; ++t) {
+        const int i = lane + 64 * t;
+        const double w = wt(i);
+        const double incl = base + wave_incl_scan_dbl_x(w, lane);
+        const double cum = incl - w;
         int r = (int)ceil(cum / step - 0.5);
         r = r < 0 ? 0 : r;
-        for (; r < SAMPLE_ROWS && (r + 0.5) * step < nxt; ++r) srow[r] = i;
-        cum = nxt;
+        for (; w > 0.0 && r < SAMPLE_ROWS && (r + 0.5) * step < incl; ++r) srow[r] = i;
+        base = readlane_dbl(incl, 63);
       }
     }
     wave_lds_sync();
-    if (lane == 0) {
-      int first = 0;
-      while (first < n && sxj[first] == 0.0) ++first;
-      if (first >= n) first = 0;
-      int prev = first;
-      for (int r = 0; r < SAMPLE_ROWS; ++r) {
-        if (srow[r] < 0 || sxj[srow[r]] == 0.0) srow[r] = prev;
-        prev = srow[r];
+    // samples no row took (rounding at the end) repeat the nearest earlier
+    // sample, or the column's first nonzero row; sampled rows increase with
+    // r (an inclusive max-scan over the entries, two per lane, finds that
+    // row), and any row with x_ij != 0 would do
+    int first = 0;
+    for (int t = 0; t < T; ++t) {
+      const uint64_t nzm = __ballot(wt(lane + 64 * t) != 0.0);
+      if (nzm) {
+        first = 64 * t + __builtin_ctzll(nzm);
+        break;
       }
     }
+    const int s0 = srow[2 * lane], s1 = srow[2 * lane + 1];
+    const int c1 = max(s0, s1);
+    int tot = c1, x = c1;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int o = (int)xswap32((uint32_t)tot, d);
+      x = (lane & d) ? max(x, o) : x;
+      tot = max(tot, o);
+    }
+    // (x: the largest row over entries [0, 2 lane + 2); prev: over [0, 2 lane))
+    const int up1 = __shfl_up(x, 1);
+    const int prev = lane > 0 ? up1 : -1;
+    const int e0 = max(prev, s0), e1 = max(e0, s1);
+    wave_lds_sync();
+    srow[2 * lane] = e0 >= 0 ? e0 : first;
+    srow[2 * lane + 1] = e1 >= 0 ? e1 : first;
   }
   __syncthreads();
 
