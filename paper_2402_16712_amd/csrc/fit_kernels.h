@@ -1142,12 +1142,22 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
   constexpr int FB = 4;
   for (int t0 = 0; t0 < T; t0 += FB) {
     double av[FB], bv[FB];
+    if (t0 + FB <= T) {
+      // a whole batch (every one at 2000 rows): no per-slot guard
 #pragma unroll
-    for (int r = 0; r < FB; ++r) {
-      const int i = lane + 64 * (t0 + r);
-      const bool in = t0 + r < T;
-      av[r] = in ? ldj(i) : 0.0;
-      bv[r] = in ? ldk(i) : 0.0;
+      for (int r = 0; r < FB; ++r) {
+        const int i = lane + 64 * (t0 + r);
+        av[r] = ldj(i);
+        bv[r] = ldk(i);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < FB; ++r) {
+        const int i = lane + 64 * (t0 + r);
+        const bool in = t0 + r < T;
+        av[r] = in ? ldj(i) : 0.0;
+        bv[r] = in ? ldk(i) : 0.0;
+      }
     }
 #pragma unroll
     for (int r = 0; r < FB; ++r) {
