@@ -638,13 +638,22 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
     constexpr int RB = 4;
     for (int t0 = 0; t0 < s.T; t0 += RB) {
       double av[RB], bv[RB];
+      if (t0 + RB <= s.T) {
 #pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        // (slots past T, of the last batch: 0 from both columns)
-        const bool in = t0 + q < s.T;
-        const int i = s.lane + 64 * (t0 + q);
-        av[q] = in ? sxj_pad(s, rj, i) : 0.0;
-        bv[q] = in ? col_ld(rk, i * 8) : 0.0;
+        for (int q = 0; q < RB; ++q) {
+          const int i = s.lane + 64 * (t0 + q);
+          av[q] = sxj_pad(s, rj, i);
+          bv[q] = col_ld(rk, i * 8);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          // (slots past T, of the last batch: 0 from both columns)
+          const bool in = t0 + q < s.T;
+          const int i = s.lane + 64 * (t0 + q);
+          av[q] = in ? sxj_pad(s, rj, i) : 0.0;
+          bv[q] = in ? col_ld(rk, i * 8) : 0.0;
+        }
       }
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
