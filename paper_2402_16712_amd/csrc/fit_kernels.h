@@ -1149,8 +1149,8 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
   // rows in batches of FB slots, every load of a batch issued before the
   // first is used (one slot at a time left the wave waiting on L2 latency)
   constexpr int FB = 4;
-  for (int t0 = 0; t0 < T; t0 += FB) {
-    double av[FB], bv[FB];
+  // batch t0's loads are issued while batch t0 - FB is classified
+  auto load_batch = [&](int t0, double *av, double *bv) {
     if (t0 + FB <= T) {
       // a whole batch (every one at 2000 rows): no per-slot guard
 #pragma unroll
@@ -1168,6 +1168,17 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
         bv[r] = in ? ldk(i) : 0.0;
       }
     }
+  };
+  double an[FB], bn[FB];
+  load_batch(0, an, bn);
+  for (int t0 = 0; t0 < T; t0 += FB) {
+    double av[FB], bv[FB];
+#pragma unroll
+    for (int r = 0; r < FB; ++r) {
+      av[r] = an[r];
+      bv[r] = bn[r];
+    }
+    if (t0 + FB < T) load_batch(t0 + FB, an, bn);
 #pragma unroll
     for (int r = 0; r < FB; ++r) {
       const int i = lane + 64 * (t0 + r);
