@@ -636,8 +636,8 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
     // first is used (the sums still run slot by slot in increasing order)
     const __amdgpu_buffer_rsrc_t rk = col_rsrc(s.xk, s.n), rj = col_rsrc(s.lds ? s.xk : s.sxj, s.n);
     constexpr int RB = 4;
-    for (int t0 = 0; t0 < s.T; t0 += RB) {
-      double av[RB], bv[RB];
+    // batch t0's loads are issued while batch t0 - RB is scored
+    auto load_batch = [&](int t0, double *av, double *bv) {
       if (t0 + RB <= s.T) {
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
@@ -655,6 +655,17 @@ __device__ __forceinline__ void wave_residual_multi(const SegIO &s, const double
           bv[q] = in ? col_ld(rk, i * 8) : 0.0;
         }
       }
+    };
+    double an[RB], bn[RB];
+    load_batch(0, an, bn);
+    for (int t0 = 0; t0 < s.T; t0 += RB) {
+      double av[RB], bv[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        av[q] = an[q];
+        bv[q] = bn[q];
+      }
+      if (t0 + RB < s.T) load_batch(t0 + RB, an, bn);
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
 #pragma unroll
