@@ -492,32 +492,41 @@ __device__ __forceinline__ void wave_list_sums(const SegIO &s, const uint64_t *l
 // element below the list), reaches its tau.  A binary search over the lanes'
 // inclusive sums finds the owning lane, a walk over its entries the element.
 // hit = false when tau lies outside (Slo, Slo + weight of the list].
+// The weight below the list is known to lie in [SloA, SloB]; the search runs
+// at SloA, and amb is set where the answer at SloB could differ: the hit
+// status, or an earlier entry reaching tau (the entries before the found one
+// weigh run_prev - SloA; at SloB the found entry is still the first iff
+// run_prev + (SloB - SloA) < tau; it still reaches tau since SloB >= SloA).
 __device__ __forceinline__ void wave_resolve(const SegIO &s, const uint64_t *lk, const unsigned short *lr, int E,
-                                             u128 Slo, u128 tot, u128 incl, bool active, u128 tau,
-                                             uint64_t &okey, int &orow, bool &hit) {
+                                             u128 SloA, u128 SloB, u128 tot, u128 incl, bool active, u128 tau,
+                                             uint64_t &okey, int &orow, bool &hit, bool &amb) {
   const u128 wall = readlane_u128(incl, 63);
-  const bool inwin = active && tau > Slo && tau <= Slo + wall;
+  const bool inwin = active && tau > SloA && tau <= SloA + wall;
+  const bool inwinB = active && tau > SloB && tau <= SloB + wall;
   int lo = 0, hi = 63;
 #pragma unroll
   for (int it = 0; it < 6; ++it) {
     const int mid = (lo + hi) >> 1;
     const u128 im = shfl_u128(incl, mid);
-    if (Slo + im >= tau) hi = mid;
+    if (SloA + im >= tau) hi = mid;
     else lo = mid + 1;
   }
   const u128 totc = shfl_u128(tot, lo), inclc = shfl_u128(incl, lo);
   hit = false;
+  amb = inwin != inwinB;
   if (inwin) {
-    u128 run = Slo + inclc - totc;
+    u128 run = SloA + inclc - totc;
     for (int q = 0; q < E; ++q) {
       const int e = E * lo + q;
       const uint64_t key = lk[e];
       const bool valid = key != KEY_NONE;
+      const u128 before = run;
       run += seg_weight(s, valid ? (int)lr[e] : 0, valid);
       if (valid && run >= tau) {
         okey = key;
         orow = (int)lr[e];
         hit = true;
+        amb = amb || !(before + (SloB - SloA) < tau);
         break;
       }
     }
@@ -1938,16 +1947,11 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
               if (wantm & 1ull) wave_resolve_one(s, lk, lr, N >> 6, SloA, SloB, tot, incl, uni_u128(tau), k2, r2, h2, amb);
               h2 = h2 && lane == 0;
             } else {
-              wave_resolve(s, lk, lr, N >> 6, SloA, tot, incl, want, tau, k2, r2, h2);
-              if (SloA != SloB) {
-                // the answer must not depend on where in [SloA, SloB] the
-                // exact weight below the list lies
-                uint64_t k3 = KEY_NONE;
-                int r3 = -1;
-                bool h3 = false;
-                wave_resolve(s, lk, lr, N >> 6, SloB, tot, incl, want, tau, k3, r3, h3);
-                amb = __ballot(want && (h2 != h3 || k2 != k3 || r2 != r3)) != 0;
-              }
+              // the answer must not depend on where in [SloA, SloB] the
+              // exact weight below the list lies
+              bool amb_l = false;
+              wave_resolve(s, lk, lr, N >> 6, SloA, SloB, tot, incl, want, tau, k2, r2, h2, amb_l);
+              amb = __ballot(want && amb_l) != 0;
             }
             if (!amb && h2) {
               okey = k2;
