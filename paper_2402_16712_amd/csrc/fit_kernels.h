@@ -1456,7 +1456,11 @@ __device__ __forceinline__ void select_one_fp64(const SegIO &s, uint64_t *lk, un
     tot = tot + (valid ? fabs(sxj_at(s, lr[e])) : 0.0);
   }
   const double incl = wave_incl_scan_dbl_x(tot, lane);
-  auto find = [&](double D, uint64_t &k, int &r) -> bool {
+  // the search at the lower end of [SA, SB] (D = DA); the upper end (DB <=
+  // DA) is then checked by one comparison: the found entry stays the first
+  // to reach DB iff the weight before it is below DB, and a miss above the
+  // list stays one iff the list's total is below DB
+  auto find = [&](double D, uint64_t &k, int &r, double &prev) -> bool {
     if (!(D > 0.0)) return false;                  // tau at or below the list
     const double df = incl - D;
     und = und || __ballot(fabs(df) <= tol) != 0;
@@ -1468,6 +1472,7 @@ __device__ __forceinline__ void select_one_fp64(const SegIO &s, uint64_t *lk, un
       const int e = E * lo + q;
       const uint64_t key = lk[e];
       if (key == KEY_NONE) break;
+      prev = run;
       run = run + fabs(sxj_at(s, lr[e]));
       const double d = run - D;
       und = und || fabs(d) <= tol;
@@ -1480,15 +1485,22 @@ __device__ __forceinline__ void select_one_fp64(const SegIO &s, uint64_t *lk, un
     und = true;                                    // (the owner's entries must reach D)
     return false;
   };
-  uint64_t kA = KEY_NONE, kB = KEY_NONE;
-  int rA = -1, rB = -1;
-  const bool hA = find(DA, kA, rA);
-  const bool hB = DB == DA ? hA : find(DB, kB, rB);
-  if (DB == DA) {
-    kB = kA;
-    rB = rA;
+  uint64_t kA = KEY_NONE;
+  int rA = -1;
+  double prevA = 0.0;
+  const bool hA = find(DA, kA, rA, prevA);
+  if (DB != DA) {
+    if (hA) {
+      // (DB > 0 is exactly known: DB = 0 means tau is at or below SB)
+      und = und || (DB > 0.0 && fabs(prevA - DB) <= tol);
+      amb = amb || !(DB > 0.0 && prevA - DB < 0.0);
+    } else if (DA > 0.0) {
+      const double d = readlane_dbl(incl, 63) - DB;
+      und = und || fabs(d) <= tol;
+      amb = amb || d >= 0.0;
+    }
   }
-  amb = amb || und || hA != hB || kA != kB || rA != rB;
+  amb = amb || und;
   okey = kA;
   orow = rA;
   hit = hA;
