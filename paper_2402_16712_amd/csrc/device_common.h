@@ -433,6 +433,9 @@ __device__ __forceinline__ double wave_incl_scan_dbl_x(double x, int lane) {
   return x;
 }
 
+// (A lane keeping the minimum takes its partner's pair when that is less,
+// one keeping the maximum when it is not less: the same result, since two
+// equal pairs are interchangeable, with one comparison instead of two.)
 __device__ __forceinline__ void wave_sort_key_row_x(uint64_t &key, int &row, int lane) {
 #pragma unroll
   for (int size = 2; size <= 64; size <<= 1) {
@@ -440,11 +443,9 @@ __device__ __forceinline__ void wave_sort_key_row_x(uint64_t &key, int &row, int
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       const uint64_t ok = xswap64(key, stride);
       const int orow = (int)xswap32((uint32_t)row, stride);
-      const bool up = (lane & size) == 0;
-      const bool lower = (lane & stride) == 0;
+      const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
       const bool other_less = ok < key || (ok == key && orow < row);
-      const bool other_greater = ok > key || (ok == key && orow > row);
-      const bool take = (lower == up) ? other_less : other_greater;
+      const bool take = other_less == keep_min;
       key = take ? ok : key;
       row = take ? orow : row;
     }
