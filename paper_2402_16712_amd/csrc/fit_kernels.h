@@ -1270,6 +1270,28 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
   SB = fixed_floor(St + dlt, s.e0) + 1;
 }
 
+// Probe point of a window (plo, phi] that holds more elements than the
+// list: the middle one of the sample keys inside it, or with none inside the
+// ratio halfway between its ends (when both are finite).  Any key inside the
+// window serves: it only steers where the next exact listing pass looks.
+// false: no key strictly inside the window was found.
+__device__ __forceinline__ bool window_midpoint(uint32_t sa, uint32_t sb, uint64_t plo, uint64_t phi,
+                                                uint64_t &mid) {
+  // the sorted sample holds index 2 l + c in lane l (c = 0: sa, 1: sb)
+  const uint64_t ka = (uint64_t)sa << 32, kb = (uint64_t)sb << 32;
+  const int i0 = __builtin_popcountll(__ballot(ka <= plo)) + __builtin_popcountll(__ballot(kb <= plo));
+  const int i1 = __builtin_popcountll(__ballot(ka < phi)) + __builtin_popcountll(__ballot(kb < phi));
+  if (i1 > i0) {
+    const int ix = (i0 + i1) >> 1;
+    mid = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((ix & 1) ? sb : sa), ix >> 1)) << 32;
+    return true;
+  }
+  const double glo = ratio_of_key(plo), ghi = ratio_of_key(phi);
+  if (!(glo - glo == 0.0) || !(ghi - ghi == 0.0)) return false;
+  mid = key_of(0.5 * glo + 0.5 * ghi + 0.0);
+  return mid > plo && mid < phi;
+}
+
 // The side of the minimiser of segment (j, k) at penalty lam from the sign
 // sums dz = (D_jk, Zr_jk): 0 when 0 minimises g_jk, 1 negative, 2 positive,
 // 3 undecided (the exact pass decides).  Decision margin 2^-32 (W_j + lam):
@@ -1803,6 +1825,9 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         // known from it only within an interval, leaves the selection open
         bool use_fast = fast_seg;
         bool ovf = false;
+        int nsteer = 0, bcnt = 0;
+        bool probe = false;
+        uint64_t blo = plo;
         while (true) {
           int nwin = 0;
           u128 SlwA, SlwB;
@@ -1854,12 +1879,55 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             nwin = uni_int(nwin);
             wave_lds_sync();
           }
+          const u128 lamf = act ? slam[tl] : (u128)0;
+          const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
+          if (!kMulti && use_fast && (probe || nwin > lcap)) {
+            // one target and division-free classes: a window too full for
+            // the list is bisected.  (blo, phi] holds the target and about
+            // bcnt elements; a probe pass over (plo, phi], plo inside it,
+            // gives the weight at or below plo, which names the half.
+            const uint64_t tm = __ballot(mine && !hit);
+            if (__builtin_popcountll(tm) == 1 && nsteer < 12) {
+              const bool at_or_below = readlane_u128(tau, __builtin_ctzll(tm)) <= SlwA;
+              bool more = true;
+              if (!probe) {
+                // the window itself: the target at or below it is a miss
+                if (at_or_below) {
+                  ovf = true;
+                  break;
+                }
+                blo = plo;
+                bcnt = nwin;
+              } else if (at_or_below) {
+                // at or below the probe point: (blo, plo], not listed yet
+                bcnt -= nwin;
+                phi = plo;
+                plo = blo;
+              } else {
+                blo = plo;
+                bcnt = nwin;
+                more = nwin > lcap;
+              }
+              probe = false;
+              if (more) {
+                ++nsteer;
+                if (bcnt <= lcap) continue;          // list (blo, phi] in one pass
+                uint64_t mid;
+                if (!window_midpoint(sa, sb, plo, phi, mid)) {
+                  ovf = true;
+                  break;
+                }
+                plo = mid;
+                probe = true;
+                continue;
+              }
+            }
+            probe = false;
+          }
           if (nwin > lcap) {
             ovf = true;
             break;
           }
-          const u128 lamf = act ? slam[tl] : (u128)0;
-          const u128 tau = neg ? ((W + lamf) >> 1) + 1 : (W - lamf + 1) >> 1;
           const bool want = mine && !hit;
           const uint64_t wantm = __ballot(want);
           u128 SloA = SlwA, SloB = SlwB;

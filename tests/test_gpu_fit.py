@@ -124,6 +124,33 @@ def test_rows_beyond_16384_structured_and_ties(ctx):
     assert_path_equal(gpu_path(ctx, Y, lams), O.fit_path(Y, lams), "int-40000")
 
 
+@pytest.mark.parametrize("kind,n,m", [("rank1", 10000, 8), ("rank1", 30000, 6), ("int", 40000, 4),
+                                      ("int", 12000, 5)])
+def test_one_penalty_windows_too_full_for_the_list(ctx, kind, n, m):
+    # one penalty at many rows: the sampled key window around the median
+    # holds more elements than the list, so it is bisected before the exact
+    # listing.  Clustered ratios (rank one, outlier rows) and thousands of
+    # tied ratios (small integers), where a bisection can stall on one key.
+    if kind == "rank1":
+        X = wl.rank_one_matrix(n, m, max(2, m // 2), n // 10, 20.0, 0.01, (35, n, m))
+        mass = wl.max_column_mass(X)
+        lams = [0.0, 0.01 * mass, 0.05 * mass]
+    else:
+        # a rounded rank-one matrix: 42 distinct integers, medians on ties
+        X = np.asfortranarray(np.rint(3.0 * wl.rank_one_matrix(n, m, m, n // 10, 2.0, 0.05, (36, n, m),
+                                                             laplace_b=0.2)))
+        lams = [0.0, 10.0, 0.05 * wl.max_column_mass(X)]
+    for lam in lams:
+        _say(f"case one penalty {kind} {n}x{m} lambda={lam!r}")
+        g = gpu_fit(ctx, X, float(lam))
+        r = O.fit(X, float(lam))
+        assert g["status"] == 0, g["status"]
+        assert int(g["j"][0]) == r["j"], (int(g["j"][0]), r["j"])
+        assert g["v"].tobytes() == r["v"].tobytes(), np.argwhere(g["v"] != r["v"])[:5]
+        assert np.array_equal(g["row"], r["row"]), np.argwhere(g["row"] != r["row"])[:5]
+        assert g["z_all"].tobytes() == r["z_all"].tobytes()
+
+
 @pytest.mark.parametrize("seed,span", [(0, 1), (1, 2), (2, 2), (3, 3), (4, 5)])
 def test_integer_ties(ctx, seed, span):
     # integer data: many equal ratios and exact ties of the weighted median
