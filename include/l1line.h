@@ -235,7 +235,8 @@ int l1line_tune_lookup(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
 
 /* Per-column features F [m][32] (FP32, DEVICE).  With D_jk = sum_i x_ij
  * sgn(x_ik) and Zr_jk = sum_i |x_ij| [x_ik == 0] (the weight balance of the
- * ratios x_ik / x_ij, FP64 over all rows), the segment (j, k) has v_k != 0
+ * ratios x_ik / x_ij over all rows, Lemma 1 of Sec. 2; here as computed by
+ * l1line_ranker_signsums), the segment (j, k) has v_k != 0
  * exactly when its initial slope s_jk = |D_jk| - Zr_jk - lambda is > 0, and
  * z_j = sum_k W_k - W_j + lambda - sum_k Delta_jk with Delta_jk >= 0 the
  * segment's improvement over v_k = 0.  Per column j (W = column l1 mass):
@@ -252,6 +253,21 @@ int l1line_tune_lookup(l1line_ctx ctx, const l1line_problem *probs, int64_t B,
 int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n,
                            int64_t m, int64_t ld, double lambda, float *F,
                            void *stream);
+
+/* The sign sums behind the features: DZ [m][m][2] (FP64, DEVICE, caller
+ * owned), DZ[(j m + k) 2] = D_jk, DZ[(j m + k) 2 + 1] = Zr_jk as above (the
+ * weight balance of Lemma 1, Sec. 2).  They only rank the columns, so they run
+ * on the BF16 matrix units: column j scaled by the power of two that brings
+ * its largest magnitude into [1, 2), each value split into BF16 parts h + l
+ * (|x - h - l| <= 2^-15 |x|), FP32 accumulation over the rows.  Bounds, with
+ * W_j = sum_i |x_ij| and u = 2^-24:
+ *   |D_jk - exact|  <= (2^-15 + 2 n u) W_j
+ *   |Zr_jk - exact| <= (2^-8 + 2 n u) Zr_jk(exact)   (h alone; terms >= 0)
+ * (up to magnitudes 2^-126 below the column's largest, flushed to 0).  The
+ * exact solve never uses these: it computes its own in FP64.  Errors as
+ * l1line_ranker_features; m <= L1LINE_RANKER_MAX_M, else ESIZE. */
+int l1line_ranker_signsums(l1line_ctx ctx, const double *X, int64_t n,
+                           int64_t m, int64_t ld, double *DZ, void *stream);
 
 /* MLP forward: out[r] = MLP(F[r]) for N rows (all DEVICE).  Matrix products
  * take BF16 operands (features, weights, hidden activations rounded to

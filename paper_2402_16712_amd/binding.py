@@ -25,7 +25,8 @@ EXPORTS = ["l1line_create", "l1line_destroy", "l1line_strerror", "l1line_last_er
            "l1line_fit", "l1line_fit_noalloc", "l1line_fit_path", "l1line_fit_batch", "l1line_autotune",
            "l1line_tune_get",
            "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
-           "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked", "l1line_ranker_load",
+           "l1line_ranker_signsums", "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam",
+           "l1line_fit_ranked", "l1line_ranker_load",
            "l1line_ranker_save", "l1line_ranker_set_params", "l1line_ranker_get_params", "l1line_ranker_train",
            "l1line_breakpoints", "l1line_components", "l1line_solution_path", "l1line_measure_peaks",
            "l1line_tune_lookup"]
@@ -84,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_tune_lookup.argtypes = [P, P, I64, P, P]
         F32 = ctypes.c_float
         L.l1line_ranker_features.argtypes = [P, P, I64, I64, I64, D, P, P]
+        L.l1line_ranker_signsums.argtypes = [P, P, I64, I64, I64, P, P]
         L.l1line_mlp_forward.argtypes = [P, P, P, I64, P, P]
         L.l1line_mlp_grad.argtypes = [P, P, P, P, I64, P, P, P]
         L.l1line_mlp_adam.argtypes = [P, P, P, P, P, I64, F32, P]
@@ -95,7 +97,8 @@ def lib() -> ctypes.CDLL:
         for f in ("l1line_create", "l1line_destroy", "l1line_column_stats", "l1line_fit", "l1line_fit_noalloc",
                   "l1line_fit_path", "l1line_fit_batch", "l1line_autotune", "l1line_tune_get",
                   "l1line_tune_set", "l1line_profile", "l1line_profile_read", "l1line_ranker_features",
-                  "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam", "l1line_fit_ranked",
+                  "l1line_ranker_signsums", "l1line_mlp_forward", "l1line_mlp_grad", "l1line_mlp_adam",
+                  "l1line_fit_ranked",
                   "l1line_last_error", "l1line_ranker_load", "l1line_ranker_save", "l1line_ranker_set_params",
                   "l1line_ranker_get_params", "l1line_ranker_train", "l1line_breakpoints",
                   "l1line_components", "l1line_measure_peaks", "l1line_tune_lookup"):
@@ -333,6 +336,16 @@ class Context:
         _check(lib().l1line_ranker_features(self._h, _ptr(X), n, m, ld, float(lam), _ptr(F),
                                             self._stream()), "l1line_ranker_features")
         return F
+
+    def feature_signsums(self, X):
+        """[m, m, 2] FP64 (D_jk, Zr_jk) behind the features (device; BF16
+        matrix units, error bounds in the header)."""
+        torch = _torch()
+        n, m, ld = _check_matrix(X)
+        DZ = self._empty((m, m, 2), torch.float64)
+        _check(lib().l1line_ranker_signsums(self._h, _ptr(X), n, m, ld, _ptr(DZ), self._stream()),
+               "l1line_ranker_signsums")
+        return DZ
 
     @staticmethod
     def _f32(t, shape=None):

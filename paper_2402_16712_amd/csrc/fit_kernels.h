@@ -1065,13 +1065,6 @@ k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, 
                DZ + d.pair_off);
 }
 
-// The sign sums of one matrix, all pairs (grid: ceil(m/64)^2 tiles).
-__global__ void __launch_bounds__(256)
-k_signsum_one(const double *__restrict__ X, int n, int m, long long ld, double2 *__restrict__ DZ) {
-  const int tk_count = (m + SS_TILE - 1) / SS_TILE;
-  signsum_tile(X, n, m, ld, nullptr, m, (blockIdx.x / tk_count) * SS_TILE, (blockIdx.x % tk_count) * SS_TILE, DZ);
-}
-
 // ---------------------------------------------------------------- segments
 // Workgroup = (preserved column j, one part of the k range); its waves take
 // the next k from an LDS counter.  For every (j, k) and lambda_t it writes

@@ -1325,15 +1325,19 @@ int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2, const f
 // ranker scratch layout for a matrix of n x m: sign sums, slope aggregates,
 // column info, statistics, features, scores, candidates, mask, flags
 struct RkLayout {
-  size_t o_DZ, o_agg, o_ci, o_stats, o_F, o_score, o_cand, o_mask, o_flag, o_margin, bytes;
+  size_t o_DZ, o_agg, o_ci, o_stats, o_F, o_score, o_cand, o_mask, o_flag, o_margin, o_H, o_L, o_S, bytes;
 };
 
 static RkLayout rk_layout(int64_t n, int64_t m) {
-  (void)n;
   RkLayout R;
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b, 256); return o; };
   R.o_DZ = take(2 * sizeof(double) * m * m);
+  // BF16 planes of the feature sign sums (high and low parts, signs)
+  const size_t plane = sizeof(__bf16) * (size_t)fss_rows(n) * (size_t)m;
+  R.o_H = take(plane);
+  R.o_L = take(plane);
+  R.o_S = take(plane);
   R.o_agg = take(sizeof(double) * 4 * m);
   R.o_ci = take(sizeof(ColInfo) * m);
   R.o_stats = take(sizeof(double) * 3 * FEAT_Q);
@@ -1347,6 +1351,30 @@ static RkLayout rk_layout(int64_t n, int64_t m) {
   return R;
 }
 
+// the feature sign sums into DZ (the ranker scratch's, or the caller's);
+// column info of X into the scratch
+static int feature_signsums(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double2 *DZ,
+                            hipStream_t s) {
+  const RkLayout R = rk_layout(n, m);
+  int st = ensure_rk(ctx, R.bytes, s);
+  if (st) return st;
+  char *b = (char *)ctx->rk;
+  ColInfo *ci = (ColInfo *)(b + R.o_ci);
+  __bf16 *Hp = (__bf16 *)(b + R.o_H), *Lp = (__bf16 *)(b + R.o_L), *Sp = (__bf16 *)(b + R.o_S);
+  const int np = (int)fss_rows(n);
+  const long long tb = (m + FSS_T - 1) / FSS_T;
+  hipLaunchKernelGGL(k_colprep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld, ci);
+  hipLaunchKernelGGL(k_feat_planes, dim3((unsigned)(m * ((np + 255) / 256))), dim3(256), 0, s, X, (int)n, (int)m,
+                     (long long)ld, np, (const ColInfo *)ci, Hp, Lp, Sp);
+  {
+    ProfScope ps(ctx, s, "feat_signsum");
+    hipLaunchKernelGGL(k_feat_signsum, dim3((unsigned)((tb * tb + 3) / 4)), dim3(256), 0, s, (const __bf16 *)Hp,
+                       (const __bf16 *)Lp, (const __bf16 *)Sp, (int)m, np, (const ColInfo *)ci, DZ);
+  }
+  HIP_TRY(hipGetLastError());
+  return L1LINE_OK;
+}
+
 static int ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
                            float *F, hipStream_t s) {
   const RkLayout R = rk_layout(n, m);
@@ -1356,9 +1384,8 @@ static int ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   ColInfo *ci = (ColInfo *)(b + R.o_ci);
   double2 *DZ = (double2 *)(b + R.o_DZ);
   double *agg = (double *)(b + R.o_agg), *stats = (double *)(b + R.o_stats);
-  const int tk = (int)((m + SS_TILE - 1) / SS_TILE);
-  hipLaunchKernelGGL(k_colprep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld, ci);
-  hipLaunchKernelGGL(k_signsum_one, dim3((unsigned)(tk * tk)), dim3(256), 0, s, X, (int)n, (int)m, (long long)ld, DZ);
+  st = feature_signsums(ctx, X, n, m, ld, DZ, s);
+  if (st) return st;
   hipLaunchKernelGGL(k_slope_aggr, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, (const double2 *)DZ, ci, (int)m,
                      lambda, agg);
   hipLaunchKernelGGL(k_feature_stats, dim3(1), dim3(256), 0, s, (const double *)agg, (int)m, ci, stats);
@@ -1383,6 +1410,21 @@ static int ranker_features_impl(l1line_ctx ctx, const double *X, int64_t n, int6
 int l1line_ranker_features(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
                            float *F, void *stream) {
   return note(ctx, ranker_features_impl(ctx, X, n, m, ld, lambda, F, stream));
+}
+
+static int ranker_signsums_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double *DZ,
+                                void *stream) {
+  if (!ctx || !DZ) return L1LINE_EINVAL;
+  int st = check_matrix(X, n, m, ld);
+  if (st) return st;
+  if (m > L1LINE_RANKER_MAX_M) return L1LINE_ESIZE;
+  HIP_TRY(hipSetDevice(ctx->device));
+  return feature_signsums(ctx, X, n, m, ld, (double2 *)DZ, (hipStream_t)stream);
+}
+
+int l1line_ranker_signsums(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double *DZ,
+                           void *stream) {
+  return note(ctx, ranker_signsums_impl(ctx, X, n, m, ld, DZ, stream));
 }
 
 __global__ void k_copy_flag(const int *src, int *dst) {

@@ -248,6 +248,136 @@ __global__ void k_mlp_adam(float *__restrict__ P, float *__restrict__ m1, float 
   P[p] = P[p] - lr * mh / (sqrtf(vh) + eps);
 }
 
+// ------------------------------------------------------ feature sign sums
+// The features need D_jk = sum_i x_ij sgn(x_ik) and Zr_jk = sum_i |x_ij| [x_ik
+// = 0] for every pair only to rank the columns (the exact solve computes its
+// own in FP64), so they run on the BF16 matrix units.  Column j, scaled by the
+// power of two 2^-(E_j) that brings its largest magnitude into [1, 2) (E_j its
+// exponent), is split into BF16 parts h + l that carry 16 significant bits
+// (|x - h - l| <= 2^-15 |x| after the scaling); the signs are exact in BF16.
+//   D_jk  = 2^E_j sum_i (h_ij + l_ij) sgn(x_ik)       two products
+//   Zr_jk = 2^E_j sum_i |h_ij| [x_ik = 0]              one product (terms >= 0:
+//                                                     relative error 2^-8)
+// with FP32 accumulation over the rows (error <= n 2^-24 of the sum of the
+// terms' magnitudes).  Planes: bf16 [m][np], np = n rounded up to 32, rows
+// past n zero in h and l (so they add nothing; their sign entries are +1).
+constexpr int FSS_K = 32;            // rows per MFMA step
+constexpr int FSS_T = 64;            // output block (j and k) of one wave
+
+__host__ __device__ constexpr int64_t fss_rows(int64_t n) { return (n + FSS_K - 1) / FSS_K * FSS_K; }
+
+__device__ __forceinline__ int col_exp(const ColInfo &c) { return c.nnz > 0 ? c.bemax - 1023 : 0; }
+
+__global__ void __launch_bounds__(256)
+k_feat_planes(const double *__restrict__ X, int n, int m, long long ld, int np, const ColInfo *__restrict__ ci,
+              __bf16 *__restrict__ H, __bf16 *__restrict__ Lo, __bf16 *__restrict__ S) {
+  // block b: column b / chunks, rows 256 (b % chunks) ...
+  const int chunks = (np + 255) >> 8;
+  const int j = blockIdx.x / chunks;
+  const int i = (blockIdx.x % chunks) * 256 + threadIdx.x;
+  if (j >= m || i >= np) return;
+  const double x = i < n ? X[(long long)j * ld + i] : 0.0;
+  const double xs = ldexp(x, -col_exp(ci[j]));
+  const __bf16 h = (__bf16)(float)xs;
+  const __bf16 l = (__bf16)(float)(xs - (double)(float)h);
+  const long long o = (long long)j * np + i;
+  H[o] = h;
+  Lo[o] = l;
+  S[o] = (__bf16)(i >= n ? 1.0f : (x > 0.0 ? 1.0f : (x < 0.0 ? -1.0f : 0.0f)));
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 ld_frag(const __bf16 *p) { return *(const bf16x8 *)p; }
+__device__ __forceinline__ bf16x8 bits_and(bf16x8 v, uint32_t mask) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u &= mask;
+  return __builtin_bit_cast(bf16x8, u);
+}
+// [s = 0] from a sign fragment: +-1 -> 0, 0 -> 1 (bit patterns 3F80, BF80, 0)
+__device__ __forceinline__ bf16x8 zero_of_sign(bf16x8 v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u = (u & 0x7FFF7FFFu) ^ 0x3F803F80u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// One wave per 64 x 64 block (j0, k0) of the m x m output; DZ[j m + k] =
+// (D_jk, Zr_jk) in FP64.  Fragments straight from the planes (each lane reads
+// 16 contiguous bytes of one column), the next step's prefetched.
+__global__ void __launch_bounds__(256)
+k_feat_signsum(const __bf16 *__restrict__ H, const __bf16 *__restrict__ Lo, const __bf16 *__restrict__ S, int m,
+               int np, const ColInfo *__restrict__ ci, double2 *__restrict__ DZ) {
+  const int lane = threadIdx.x & 63;
+  const int tb = (m + FSS_T - 1) / FSS_T;
+  const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t >= tb * tb) return;
+  const int j0 = (t / tb) * FSS_T, k0 = (t % tb) * FSS_T;
+  const int r = lane & 15, kq = 8 * (lane >> 4);
+  // columns past m read column m - 1 (their results are not stored)
+  long long oa[4], ob[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    oa[a] = (long long)min(j0 + 16 * a + r, m - 1) * np + kq;
+    ob[a] = (long long)min(k0 + 16 * a + r, m - 1) * np + kq;
+  }
+  f32x4 accD[4][4], accZ[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      accD[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accZ[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  bf16x8 nh[4], nl[4], ns[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    nh[a] = ld_frag(H + oa[a]);
+    nl[a] = ld_frag(Lo + oa[a]);
+    ns[a] = ld_frag(S + ob[a]);
+  }
+  for (int i0 = 0; i0 < np; i0 += FSS_K) {
+    bf16x8 fh[4], fl[4], fs[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      fh[a] = nh[a];
+      fl[a] = nl[a];
+      fs[a] = ns[a];
+    }
+    if (i0 + FSS_K < np) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        nh[a] = ld_frag(H + oa[a] + i0 + FSS_K);
+        nl[a] = ld_frag(Lo + oa[a] + i0 + FSS_K);
+        ns[a] = ld_frag(S + ob[a] + i0 + FSS_K);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const bf16x8 fz = zero_of_sign(fs[b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        accD[a][b] = mfma16(fh[a], fs[b], accD[a][b]);
+        accD[a][b] = mfma16(fl[a], fs[b], accD[a][b]);
+        accZ[a][b] = mfma16(bits_and(fh[a], 0x7FFF7FFFu), fz, accZ[a][b]);
+      }
+    }
+  }
+  // C layout: lane holds rows 4 (lane >> 4) + q (j), column lane & 15 (k)
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + 16 * a + 4 * (lane >> 4) + q;
+      if (j >= m) continue;
+      const int e = col_exp(ci[j]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int k = k0 + 16 * b + r;
+        if (k < m) DZ[(long long)j * m + k] = double2{ldexp((double)accD[a][b][q], e), ldexp((double)accZ[a][b][q], e)};
+      }
+    }
+}
+
 // ----------------------------------------------------------------- features
 // Per column j, aggregates of the initial slopes s_jk = |D_jk| - Zr_jk - lambda
 // of the segments (j, k != j) where 0 is not the minimiser (s_jk > 0): the

@@ -166,13 +166,10 @@ def test_mlp_adam(ctx):
     assert np.all(np.abs(dP.cpu().numpy() - wP) <= 2 * u * np.abs(wP) + 400 * u * step)
 
 
-def _features_ref(X, lam):
-    """The 32 features in FP64 from their definition: sign sums by numpy
-    matrix products, column masses from the oracle."""
-    n, m = X.shape
-    W, zeros = O.column_stats(X)
-    D = X.T @ np.sign(X)                      # D[j, k] = sum_i x_ij sgn(x_ik)
-    Zr = np.abs(X).T @ (X == 0).astype(np.float64)
+def _features_from(W, zeros, D, Zr, lam, n):
+    """The 32 features in FP64 from their definition, given the column
+    masses, zero counts and the sign sums D, Zr."""
+    m = len(W)
     S = np.abs(D) - Zr - lam
     np.fill_diagonal(S, -1.0)
     pos = S > 0
@@ -201,17 +198,73 @@ def _features_ref(X, lam):
     return f
 
 
-@pytest.mark.parametrize("n,m,seed", [(300, 40, 0), (50, 25, 1), (1000, 60, 2), (64, 9, 3)])
+def _signsums_fp64(X):
+    """D[j, k] = sum_i x_ij sgn(x_ik), Zr[j, k] = sum_i |x_ij| [x_ik = 0] by
+    numpy FP64 matrix products."""
+    return X.T @ np.sign(X), np.abs(X).T @ (X == 0).astype(np.float64)
+
+
+FEATURE_CASES = [(300, 40, 0), (50, 25, 1), (1000, 60, 2), (64, 9, 3), (2500, 130, 4)]
+
+
+@pytest.mark.parametrize("n,m,seed", FEATURE_CASES)
+def test_feature_signsums_within_their_bound(ctx, n, m, seed):
+    """The BF16 sign sums against FP64 products, inside the bounds the header
+    states: |dD| <= (2^-15 + 2 n u) W_j, |dZr| <= (2^-8 + 2 n u) Zr, u = 2^-24
+    (plus 1e-12 W_j for the FP64 reference's own rounding)."""
+    from paper_2402_16712_amd import binding as B
+    _say(f"feature sign sums {n}x{m} seed {seed}")
+    X = wl.rank_one_matrix(n, m, max(1, m // 10), n // 10, 20.0, 0.01, (20, seed))
+    DZ = ctx.feature_signsums(B.device_matrix(X)).cpu().numpy()
+    D, Zr = _signsums_fp64(X)
+    W = np.abs(X).sum(0)[:, None]
+    u = 2.0 ** -24
+    assert np.all(np.abs(DZ[:, :, 0] - D) <= (2.0 ** -15 + 2 * n * u) * W + 1e-12 * W)
+    assert np.all(np.abs(DZ[:, :, 1] - Zr) <= (2.0 ** -8 + 2 * n * u) * Zr + 1e-12 * W)
+    # not trivially loose: the high and low parts carry D far below the bound
+    assert np.max(np.abs(DZ[:, :, 0] - D) / W) < 2.0 ** -15
+
+
+def test_feature_signsums_scaled_columns(ctx):
+    """Columns of very different magnitudes (each scaled by its own power of
+    two before the BF16 split) and exact zeros, signs and ties."""
+    from paper_2402_16712_amd import binding as B
+    rng = np.random.default_rng(5)
+    n, m = 700, 23
+    X = rng.standard_normal((n, m)) * np.exp2(rng.integers(-200, 200, m))[None, :]
+    X[rng.random((n, m)) < 0.05] = 0.0
+    X[:, 3] = np.where(np.arange(n) % 3 == 0, 0.0, 2.0 ** 300)
+    X = np.asfortranarray(X)
+    _say("feature sign sums, scaled columns")
+    DZ = ctx.feature_signsums(B.device_matrix(X)).cpu().numpy()
+    D, Zr = _signsums_fp64(X)
+    W = np.abs(X).sum(0)[:, None]
+    u = 2.0 ** -24
+    assert np.all(np.abs(DZ[:, :, 0] - D) <= (2.0 ** -15 + 2 * n * u) * W)
+    assert np.all(np.abs(DZ[:, :, 1] - Zr) <= (2.0 ** -8 + 2 * n * u) * Zr + 1e-12 * W)
+
+
+@pytest.mark.parametrize("n,m,seed", FEATURE_CASES)
 def test_features(ctx, n, m, seed):
+    """The features from their definition on the device's own sign sums, and
+    close to the features of the FP64 sign sums."""
     from paper_2402_16712_amd import binding as B
     _say(f"features {n}x{m} seed {seed}")
     X = wl.rank_one_matrix(n, m, max(1, m // 10), n // 10, 20.0, 0.01, (20, seed))
     lam = 0.05 * wl.max_column_mass(X)
-    F = ctx.features(B.device_matrix(X), lam).cpu().numpy()
-    want = _features_ref(X, lam)
-    # the features are FP32 roundings of FP64 arithmetic (sign sums and
-    # statistics summed in different orders)
+    Xd = B.device_matrix(X)
+    F = ctx.features(Xd, lam).cpu().numpy()
+    DZ = ctx.feature_signsums(Xd).cpu().numpy()
+    W, zeros = O.column_stats(X)
+    want = _features_from(W, zeros, DZ[:, :, 0], DZ[:, :, 1], lam, n)
+    # FP32 roundings of FP64 arithmetic (aggregates and statistics summed in
+    # different orders)
     np.testing.assert_allclose(F, want, rtol=1e-5, atol=2e-6)
+    D, Zr = _signsums_fp64(X)
+    exact = _features_from(W, zeros, D, Zr, lam, n)
+    # the ranking signal is the same: every feature within 1e-3 of its value
+    # on the FP64 sign sums, except where a slope sits at 0 and flips a count
+    assert np.mean(np.abs(F - exact) <= 1e-3 + 1e-3 * np.abs(exact)) > 0.99
 
 
 def _topk_ref(scores, K):
