@@ -975,9 +975,9 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
 // One 64 x 64 output tile of the sign sums of a column-major matrix; rows j of
 // the tile are j0.. j0 + 63 of the candidate list (cand) or of 0..m-1.
 // out[j m + k] = (D_jk, Zr_jk).  Every thread of the 256-wide block calls it.
-__device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n, int m, long long ld,
+__device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int ilo, int ihi, int m, long long ld,
                                              const int *__restrict__ cand, int mj, int j0, int k0,
-                                             double2 *__restrict__ out) {
+                                             double2 *__restrict__ out, bool by_index) {
   __shared__ double sA[SS_ROWS * SS_LD];
   __shared__ double sB[SS_ROWS * SS_LD];
   __shared__ int sj[SS_TILE];
@@ -1005,12 +1005,12 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
       const int e = tid + 256 * q;
       const int c = e / SS_ROWS, r = e % SS_ROWS, i = i0 + r;
       const int jc = sj[c], kc = k0 + c;
-      pa[q] = (i < n && jc >= 0) ? X[(long long)jc * ld + i] : 0.0;
-      pb[q] = (i < n && kc < m) ? X[(long long)kc * ld + i] : 0.0;
+      pa[q] = (i < ihi && jc >= 0) ? X[(long long)jc * ld + i] : 0.0;
+      pb[q] = (i < ihi && kc < m) ? X[(long long)kc * ld + i] : 0.0;
     }
   };
-  load(0);
-  for (int i0 = 0; i0 < n; i0 += SS_ROWS) {
+  load(ilo);
+  for (int i0 = ilo; i0 < ihi; i0 += SS_ROWS) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
       sB[r * SS_LD + c] = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
     }
     __syncthreads();
-    if (i0 + SS_ROWS < n) load(i0 + SS_ROWS);
+    if (i0 + SS_ROWS < ihi) load(i0 + SS_ROWS);
 #pragma unroll 2
     for (int kk = 0; kk < SS_ROWS / 4; ++kk) {
       const int r = 4 * kk + (lane >> 4);
@@ -1041,8 +1041,8 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
     const int k = k0 + 16 * t + (lane & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int j = sj[16 * wave + (lane >> 4) + 4 * q];
-      if (j >= 0 && k < m) out[(long long)j * m + k] = make_double2(accD[t][q], accZ[t][q]);
+      const int jl = 16 * wave + (lane >> 4) + 4 * q, j = sj[jl];
+      if (j >= 0 && k < m) out[(long long)(by_index ? j0 + jl : j) * m + k] = make_double2(accD[t][q], accZ[t][q]);
     }
   }
 }
@@ -1050,19 +1050,49 @@ __device__ __forceinline__ void signsum_tile(const double *__restrict__ X, int n
 // tstart[b] = first tile of problem b; problem b has ceil(mj / 64) x
 // ceil(m / 64) tiles with mj = ncand when cand is given (problem 0 only),
 // else m.  DZ[pair_off + j m + k] = (D_jk, Zr_jk).
+// split > 1 (one problem, a candidate list): block g sums tile g / split over
+// the rows of part g % split into part[(g % split) ncand m + jj m + k] (jj
+// the candidate's index); k_signsum_parts adds the parts.
 __global__ void __launch_bounds__(256)
 k_signsum_batch(const ProbDesc *__restrict__ P, const int *__restrict__ tstart, int B,
                 const int *__restrict__ cand, int ncand, double2 *__restrict__ DZ,
-                const int *__restrict__ gate, int gate_on) {
+                const int *__restrict__ gate, int gate_on, int split, double2 *__restrict__ part) {
   if (gate && *gate != gate_on) return;
+  if (split > 1) {
+    const ProbDesc d = P[0];
+    const int tile = blockIdx.x / split, sp = blockIdx.x % split;
+    const int tk_count = (d.m + SS_TILE - 1) / SS_TILE;
+    const int rows = (d.n + split - 1) / split;
+    const int ilo = min(d.n, sp * rows), ihi = min(d.n, ilo + rows);
+    signsum_tile(d.X, ilo, ihi, d.m, d.ld, cand, ncand, (tile / tk_count) * SS_TILE, (tile % tk_count) * SS_TILE,
+                 part + (long long)sp * ncand * d.m, true);
+    return;
+  }
   const int g = blockIdx.x;
   const int b = find_owner(tstart, B, g);
   const ProbDesc d = P[b];
   const int mj = cand ? ncand : d.m;
   const int tk_count = (d.m + SS_TILE - 1) / SS_TILE;
   const int tloc = g - tstart[b];
-  signsum_tile(d.X, d.n, d.m, d.ld, cand, mj, (tloc / tk_count) * SS_TILE, (tloc % tk_count) * SS_TILE,
-               DZ + d.pair_off);
+  signsum_tile(d.X, 0, d.n, d.m, d.ld, cand, mj, (tloc / tk_count) * SS_TILE, (tloc % tk_count) * SS_TILE,
+               DZ + d.pair_off, false);
+}
+
+// DZ[cand[jj] m + k] = the parts' sums added in part order (one problem)
+__global__ void __launch_bounds__(256)
+k_signsum_parts(const double2 *__restrict__ part, int split, const int *__restrict__ cand, int ncand, int m,
+                double2 *__restrict__ DZ, const int *__restrict__ gate, int gate_on) {
+  if (gate && *gate != gate_on) return;
+  const long long per = (long long)ncand * m;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < per; e += (long long)gridDim.x * blockDim.x) {
+    double2 acc = part[e];
+    for (int sp = 1; sp < split; ++sp) {
+      const double2 x = part[(long long)sp * per + e];
+      acc.x = acc.x + x.x;
+      acc.y = acc.y + x.y;
+    }
+    DZ[(long long)cand[e / m] * m + e % m] = acc;
+  }
 }
 
 // ---------------------------------------------------------------- segments

@@ -298,11 +298,12 @@ static int check_problem(const l1line_problem &p) {
 //   data: ColInfo, segflags, V, E, R, Z, zflag
 struct BatchLayout {
   int B, nitems, ksplit, nmax, Lmax;
+  int ss_split, ss_ncand, ss_m;   // sign sums of a candidate list: row parts, candidates, m
   int xstart[SEG_XCDS + 1];   // explicit items: XCD x owns [xstart[x], xstart[x + 1])
   long long total_cols, total_z, total_out, total_ws, total_lam, total_pairs, total_tiles, total_words;
   size_t o_desc, o_colstart, o_zstart, o_ostart, o_tstart, o_wstart, o_lam, o_items, o_counter, o_xstart,
       meta_bytes;
-  size_t o_ci, o_segflags, o_DZ, o_mask, o_V, o_E, o_R, o_Z, o_zflag, bytes;
+  size_t o_ci, o_segflags, o_DZ, o_DZp, o_mask, o_V, o_E, o_R, o_Z, o_zflag, bytes;
 };
 
 static void layout_sizes(BatchLayout &Ly) {
@@ -322,6 +323,7 @@ static void layout_sizes(BatchLayout &Ly) {
   Ly.o_ci = take(sizeof(ColInfo) * Ly.total_cols);
   Ly.o_segflags = take(sizeof(int) * Ly.total_cols);
   Ly.o_DZ = take(2 * sizeof(double) * Ly.total_pairs);
+  Ly.o_DZp = take(Ly.ss_split > 1 ? 2 * sizeof(double) * Ly.ss_split * (size_t)Ly.ss_ncand * Ly.ss_m : 0);
   Ly.o_mask = take(sizeof(unsigned long long) * Ly.total_words);
   Ly.o_V = take(sizeof(double) * Ly.total_ws);
   Ly.o_E = take(sizeof(double) * Ly.total_ws);
@@ -457,6 +459,17 @@ static int plan_batch(l1line_ctx ctx, const l1line_problem *probs, int64_t B, co
     Ly.xstart[SEG_XCDS] = (int)items.size();
     Ly.ksplit = 0;
     Ly.nitems = (int)items.size();
+  }
+  // a candidate list leaves few sign-sum tiles (32 columns j: one row of
+  // tiles): their rows are cut into parts, summed apart and then added, so
+  // that every compute unit gets work (parts of at least 512 rows)
+  if (B == 1 && ro.cand) {
+    const long long want = 2ll * ctx->num_cu;
+    long long sp = std::min<long long>(16, (want + Ly.total_tiles - 1) / std::max(1ll, Ly.total_tiles));
+    sp = std::min<long long>(sp, std::max<long long>(1, probs[0].n / 512));
+    Ly.ss_split = (int)std::max<long long>(1, sp);
+    Ly.ss_ncand = ro.ncand;
+    Ly.ss_m = (int)probs[0].m;
   }
   layout_sizes(Ly);
   return L1LINE_OK;
@@ -595,8 +608,15 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
   }
   {
     ProfScope ps(pc, ls, "signsum");
-    hipLaunchKernelGGL(k_signsum_batch, dim3((unsigned)Ly.total_tiles), dim3(256), 0, ls, dP, dtile, (int)B,
-                       (B == 1) ? ro.cand : nullptr, ro.ncand, dDZ, ro.gate, ro.gate_on);
+    const int split = Ly.ss_split > 1 ? Ly.ss_split : 1;
+    double2 *dDZp = (double2 *)(d + Ly.o_DZp);
+    hipLaunchKernelGGL(k_signsum_batch, dim3((unsigned)(Ly.total_tiles * split)), dim3(256), 0, ls, dP, dtile,
+                       (int)B, (B == 1) ? ro.cand : nullptr, ro.ncand, dDZ, ro.gate, ro.gate_on, split, dDZp);
+    if (split > 1)
+      hipLaunchKernelGGL(k_signsum_parts,
+                         dim3((unsigned)std::min<long long>(1024, ((long long)Ly.ss_ncand * Ly.ss_m + 255) / 256)),
+                         dim3(256), 0, ls, (const double2 *)dDZp, split, ro.cand, Ly.ss_ncand, Ly.ss_m, dDZ, ro.gate,
+                         ro.gate_on);
   }
   {
     ProfScope ps(pc, ls, "zero_seg");

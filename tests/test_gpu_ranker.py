@@ -273,7 +273,9 @@ def _topk_ref(scores, K):
     return order[:K], (s[order[K]] - s[order[0]]) if K < len(s) else 0.0
 
 
-@pytest.mark.parametrize("n,m,K,seed", [(400, 50, 8, 0), (120, 17, 1, 1), (900, 64, 63, 2)])
+# (the last two: candidate sign sums cut into 5 and 9 row parts)
+@pytest.mark.parametrize("n,m,K,seed", [(400, 50, 8, 0), (120, 17, 1, 1), (900, 64, 63, 2), (3000, 200, 16, 3),
+                                        (5000, 70, 32, 4)])
 def test_fit_ranked_candidates(ctx, n, m, K, seed):
     """Threshold 0: never falls back unless K = m; the answer is the exact
     optimum over the K best-scored columns."""
