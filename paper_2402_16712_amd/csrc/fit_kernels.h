@@ -228,6 +228,11 @@ static_assert((WIN_CAP & (WIN_CAP - 1)) == 0 && (PATH_CAP & (PATH_CAP - 1)) == 0
 struct WaveScratch {
   uint64_t ckey[64];
   int crow[64];
+  // bisection of a window too full for the list: lower end and element
+  // count of the part that holds the target, probe passes so far (kept here,
+  // off the registers of the window pass)
+  uint64_t blo;
+  int bcnt, steps;
 };
 
 // Element sources of the exact selection: every row of the column (ratio
@@ -1295,24 +1300,33 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
 
 // Probe point of a window (plo, phi] that holds more elements than the
 // list: the middle one of the sample keys inside it, or with none inside the
-// ratio halfway between its ends (when both are finite).  Any key inside the
-// window serves: it only steers where the next exact listing pass looks.
+// key halfway between its ends (when both are keys of finite ratios).  Any
+// key inside the window serves: it only steers where the next exact listing
+// pass looks.
+// The sorted sample (128 top-32-bit keys) is read from smp in LDS.
 // false: no key strictly inside the window was found.
-__device__ __forceinline__ bool window_midpoint(uint32_t sa, uint32_t sb, uint64_t plo, uint64_t phi,
-                                                uint64_t &mid) {
-  // the sorted sample holds index 2 l + c in lane l (c = 0: sa, 1: sb)
-  const uint64_t ka = (uint64_t)sa << 32, kb = (uint64_t)sb << 32;
-  const int i0 = __builtin_popcountll(__ballot(ka <= plo)) + __builtin_popcountll(__ballot(kb <= plo));
-  const int i1 = __builtin_popcountll(__ballot(ka < phi)) + __builtin_popcountll(__ballot(kb < phi));
+__device__ __forceinline__ int sample_count(const uint32_t *smp, uint64_t bound, bool strict) {
+  // sample keys (k 2^32) at or below bound (strict: below); the keys ascend
+  int lo = 0;
+#pragma unroll
+  for (int step = 64; step >= 1; step >>= 1) {
+    const uint64_t k = (uint64_t)smp[lo + step - 1] << 32;
+    if (strict ? k < bound : k <= bound) lo += step;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool window_midpoint(const uint32_t *smp, uint64_t plo, uint64_t phi, uint64_t &mid) {
+  const int i0 = sample_count(smp, plo, false), i1 = sample_count(smp, phi, true);
   if (i1 > i0) {
-    const int ix = (i0 + i1) >> 1;
-    mid = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((ix & 1) ? sb : sa), ix >> 1)) << 32;
+    mid = (uint64_t)smp[(i0 + i1) >> 1] << 32;
     return true;
   }
-  const double glo = ratio_of_key(plo), ghi = ratio_of_key(phi);
-  if (!(glo - glo == 0.0) || !(ghi - ghi == 0.0)) return false;
-  mid = key_of(0.5 * glo + 0.5 * ghi + 0.0);
-  return mid > plo && mid < phi;
+  // the keys of the finite doubles form one interval, [key(-inf), key(+inf)]
+  constexpr uint64_t KEY_NEG_INF = 0x000FFFFFFFFFFFFFull, KEY_POS_INF = 0xFFF0000000000000ull;
+  if (plo < KEY_NEG_INF || phi > KEY_POS_INF) return false;
+  mid = plo + ((phi - plo) >> 1);
+  return mid > plo;
 }
 
 // The side of the minimiser of segment (j, k) at penalty lam from the sign
@@ -1780,8 +1794,14 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     // the sample's keys (top 32 bits), sorted across the wave
     uint32_t sa = sample_key32(s, srow[lane]), sb = sample_key32(s, srow[lane + 64]);
     wave_sort2_u32_x(sa, sb, lane);
+    // one penalty: the sorted sample (index 2 l + c in lane l) goes to the
+    // wave's LDS scratch, free until the rounds after the window (several:
+    // the rounds between groups reuse that area, so it stays in registers)
+    const uint32_t *smp = (const uint32_t *)ws->ckey;
+    if constexpr (!kMulti) ws->ckey[lane] = ((uint64_t)sb << 32) | sa;
     // sample position ix as a lower or upper key bound
     auto sample_lo = [&](int ix) {
+      if constexpr (!kMulti) return (uint64_t)smp[ix] << 32;
       return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((ix & 1) ? sb : sa), ix >> 1)) << 32;
     };
     auto sample_hi = [&](int ix) { return sample_lo(ix) | 0xFFFFFFFFull; };
@@ -1848,9 +1868,8 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
         // known from it only within an interval, leaves the selection open
         bool use_fast = fast_seg;
         bool ovf = false;
-        int nsteer = 0, bcnt = 0;
         bool probe = false;
-        uint64_t blo = plo;
+        ws->steps = 0;
         while (true) {
           int nwin = 0;
           u128 SlwA, SlwB;
@@ -1910,7 +1929,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
             // bcnt elements; a probe pass over (plo, phi], plo inside it,
             // gives the weight at or below plo, which names the half.
             const uint64_t tm = __ballot(mine && !hit);
-            if (__builtin_popcountll(tm) == 1 && nsteer < 12) {
+            if (__builtin_popcountll(tm) == 1 && ws->steps < 12) {
               const bool at_or_below = readlane_u128(tau, __builtin_ctzll(tm)) <= SlwA;
               bool more = true;
               if (!probe) {
@@ -1919,24 +1938,24 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
                   ovf = true;
                   break;
                 }
-                blo = plo;
-                bcnt = nwin;
+                ws->blo = plo;
+                ws->bcnt = nwin;
               } else if (at_or_below) {
                 // at or below the probe point: (blo, plo], not listed yet
-                bcnt -= nwin;
+                ws->bcnt -= nwin;
                 phi = plo;
-                plo = blo;
+                plo = ws->blo;
               } else {
-                blo = plo;
-                bcnt = nwin;
+                ws->blo = plo;
+                ws->bcnt = nwin;
                 more = nwin > lcap;
               }
               probe = false;
               if (more) {
-                ++nsteer;
-                if (bcnt <= lcap) continue;          // list (blo, phi] in one pass
+                ws->steps += 1;
+                if (ws->bcnt <= lcap) continue;      // list (blo, phi] in one pass
                 uint64_t mid;
-                if (!window_midpoint(sa, sb, plo, phi, mid)) {
+                if (!window_midpoint(smp, plo, phi, mid)) {
                   ovf = true;
                   break;
                 }
