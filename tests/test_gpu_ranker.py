@@ -234,6 +234,8 @@ def test_feature_signsums_scaled_columns(ctx):
     X = rng.standard_normal((n, m)) * np.exp2(rng.integers(-200, 200, m))[None, :]
     X[rng.random((n, m)) < 0.05] = 0.0
     X[:, 3] = np.where(np.arange(n) % 3 == 0, 0.0, 2.0 ** 300)
+    X[:, 5] = 0.0                                    # an all-zero column
+    X[::2, 6] = 2.0 ** -1060                         # subnormal magnitudes
     X = np.asfortranarray(X)
     _say("feature sign sums, scaled columns")
     DZ = ctx.feature_signsums(B.device_matrix(X)).cpu().numpy()
