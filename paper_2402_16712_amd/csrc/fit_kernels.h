@@ -1303,23 +1303,31 @@ __device__ __forceinline__ void fast_window_pass(const SegIO &s, LdJ ldj, LdK ld
 // key halfway between its ends (when both are keys of finite ratios).  Any
 // key inside the window serves: it only steers where the next exact listing
 // pass looks.
-// The sorted sample (128 top-32-bit keys) is read from smp in LDS.
+// The sorted sample (128 top-32-bit keys, packed in pairs) is read from smp
+// in LDS.
 // false: no key strictly inside the window was found.
-__device__ __forceinline__ int sample_count(const uint32_t *smp, uint64_t bound, bool strict) {
-  // sample keys (k 2^32) at or below bound (strict: below); the keys ascend
+// sample key ix (top 32 bits, times 2^32) of a sorted sample stored as
+// packed pairs: entry l holds keys 2 l (low half) and 2 l + 1 (high half)
+__device__ __forceinline__ uint64_t sample_key(const uint64_t *smp, int ix) {
+  const uint64_t w = smp[ix >> 1];
+  return (ix & 1) ? (w & 0xFFFFFFFF00000000ull) : (w << 32);
+}
+
+__device__ __forceinline__ int sample_count(const uint64_t *smp, uint64_t bound, bool strict) {
+  // sample keys at or below bound (strict: below); the keys ascend
   int lo = 0;
 #pragma unroll
   for (int step = 64; step >= 1; step >>= 1) {
-    const uint64_t k = (uint64_t)smp[lo + step - 1] << 32;
+    const uint64_t k = sample_key(smp, lo + step - 1);
     if (strict ? k < bound : k <= bound) lo += step;
   }
   return lo;
 }
 
-__device__ __forceinline__ bool window_midpoint(const uint32_t *smp, uint64_t plo, uint64_t phi, uint64_t &mid) {
+__device__ __forceinline__ bool window_midpoint(const uint64_t *smp, uint64_t plo, uint64_t phi, uint64_t &mid) {
   const int i0 = sample_count(smp, plo, false), i1 = sample_count(smp, phi, true);
   if (i1 > i0) {
-    mid = (uint64_t)smp[(i0 + i1) >> 1] << 32;
+    mid = sample_key(smp, (i0 + i1) >> 1);
     return true;
   }
   // the keys of the finite doubles form one interval, [key(-inf), key(+inf)]
@@ -1797,11 +1805,13 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
     // one penalty: the sorted sample (index 2 l + c in lane l) goes to the
     // wave's LDS scratch, free until the rounds after the window (several:
     // the rounds between groups reuse that area, so it stays in registers)
-    const uint32_t *smp = (const uint32_t *)ws->ckey;
-    if constexpr (!kMulti) ws->ckey[lane] = ((uint64_t)sb << 32) | sa;
+    if constexpr (!kMulti) {
+      ws->ckey[lane] = ((uint64_t)sb << 32) | sa;
+      wave_lds_sync();
+    }
     // sample position ix as a lower or upper key bound
     auto sample_lo = [&](int ix) {
-      if constexpr (!kMulti) return (uint64_t)smp[ix] << 32;
+      if constexpr (!kMulti) return sample_key(ws->ckey, ix);
       return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((ix & 1) ? sb : sa), ix >> 1)) << 32;
     };
     auto sample_hi = [&](int ix) { return sample_lo(ix) | 0xFFFFFFFFull; };
@@ -1955,7 +1965,7 @@ __device__ __forceinline__ void seg_item(const double *__restrict__ X, int n, in
                 ws->steps += 1;
                 if (ws->bcnt <= lcap) continue;      // list (blo, phi] in one pass
                 uint64_t mid;
-                if (!window_midpoint(smp, plo, phi, mid)) {
+                if (!window_midpoint(ws->ckey, plo, phi, mid)) {
                   ovf = true;
                   break;
                 }
