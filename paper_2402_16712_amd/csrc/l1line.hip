@@ -1480,8 +1480,12 @@ static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   }
   st = mlp_forward(ctx, ctx->rk_w, F, m, sc, nullptr, nullptr, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, s, sc, (int)m, (int)K, margin_threshold, cand, mask, flag,
-                     margin);
+  if (m <= TOPK_LDS_MAX)
+    hipLaunchKernelGGL(k_topk_lds, dim3(1), dim3(1024), 0, s, sc, (int)m, (int)K, margin_threshold, cand, mask, flag,
+                       margin);
+  else
+    hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, s, sc, (int)m, (int)K, margin_threshold, cand, mask, flag,
+                       margin);
   HIP_TRY(hipGetLastError());
   const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, nullptr, status);
   // exact solve of the K candidates

@@ -544,6 +544,59 @@ __global__ void k_topk(const float *__restrict__ score, int m, int K, float thre
   }
 }
 
+// The same selection for m <= TOPK_LDS_MAX by one sort in LDS (one workgroup
+// of 1024): key = order-preserving bits of the score (NaN as +inf, -0 as +0)
+// above the column index, so ascending keys are ascending scores with the
+// lower index first on ties, as above; the candidates are the first K keys
+// and the margin is score K minus score 0.
+constexpr int TOPK_LDS_MAX = 8192;
+
+__global__ void __launch_bounds__(1024)
+k_topk_lds(const float *__restrict__ score, int m, int K, float threshold, int *__restrict__ cand,
+           int *__restrict__ mask, int *__restrict__ fallback, float *__restrict__ margin_out) {
+  __shared__ unsigned long long key[TOPK_LDS_MAX];
+  const int tid = threadIdx.x;
+  int N = 2;
+  while (N < m) N <<= 1;
+  auto score_key = [](float v) {
+    v = isnan(v) ? INFINITY : v + 0.0f;
+    const uint32_t u = __float_as_uint(v);
+    return (uint32_t)((u >> 31) ? ~u : (u | 0x80000000u));
+  };
+  auto key_score = [](uint32_t k) { return __uint_as_float((k >> 31) ? (k & 0x7FFFFFFFu) : ~k); };
+  for (int j = tid; j < N; j += blockDim.x) {
+    key[j] = j < m ? ((unsigned long long)score_key(score[j]) << 32) | (uint32_t)j : ~0ull;
+    if (j < m) mask[j] = 0;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1)
+    for (int h = k >> 1; h > 0; h >>= 1) {
+      for (int i = tid; i < N; i += blockDim.x) {
+        const int o = i ^ h;
+        if (o > i) {
+          const unsigned long long a = key[i], b = key[o];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[o] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const int kk = K < m ? K : m;
+  for (int r = tid; r < kk; r += blockDim.x) {
+    const int j = (int)(uint32_t)key[r];
+    cand[r] = j;
+    mask[j] = 1;
+  }
+  if (tid == 0) {
+    const float best0 = key_score((uint32_t)(key[0] >> 32));
+    const float mg = (K < m) ? key_score((uint32_t)(key[K] >> 32)) - best0 : 0.f;
+    *margin_out = mg;
+    *fallback = (K >= m || !(mg >= threshold) || !isfinite(best0)) ? 1 : 0;
+  }
+}
+
 // ------------------------------------------------------- training matrices
 // Counter-based generator: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw,
 // "Parallel random numbers: as easy as 1, 2, 3", SC 2011), written from its

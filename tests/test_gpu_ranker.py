@@ -301,6 +301,32 @@ def test_fit_ranked_candidates(ctx, n, m, K, seed):
     assert np.array_equal(r["row"].cpu().numpy(), one["ROW"][0])
 
 
+@pytest.mark.parametrize("m,K", [(8200, 32), (300, 7)])
+def test_fit_ranked_candidate_selection(ctx, m, K):
+    """The K best scores for m above (per-round reductions) and below (one
+    LDS sort) 8192 columns, with trained-like and with all-zero weights
+    (every score tied: the K lowest indices).  The answer must be the best
+    exact z over those candidates, judged by the exhaustive GPU fit (itself
+    bit-exact against the oracle in test_gpu_fit)."""
+    from paper_2402_16712_amd import binding as B
+    n = 40
+    _say(f"fit_ranked candidate selection m={m} K={K}")
+    X = wl.rank_one_matrix(n, m, max(1, m // 10), 4, 20.0, 0.01, (22, m))
+    lam = 0.05 * wl.max_column_mass(X)
+    Xd = B.device_matrix(X)
+    z = ctx.fit(Xd, lam)["z_all"].cpu().numpy()
+    for params in (_params(5), np.zeros_like(_params(5))):
+        ctx.ranker_set_params(_dev(params))
+        r = ctx.fit_ranked(Xd, lam, K, 0.0)
+        assert int(r["status"].item()) == 0 and int(r["used_fallback"].item()) == 0
+        cand, _ = _topk_ref(r["scores"].cpu().numpy(), K)
+        if not params.any():
+            assert np.array_equal(np.sort(cand), np.arange(K))
+        jbest = int(cand[np.lexsort((cand, z[cand]))[0]])
+        assert int(r["j"].item()) == jbest
+        assert np.float64(r["obj"].item()).tobytes() == np.float64(z[jbest]).tobytes()
+
+
 @pytest.mark.parametrize("K", [5, 30])
 def test_fit_ranked_fallback(ctx, K):
     """A threshold no margin reaches (or K = m) runs the exhaustive search:
