@@ -350,15 +350,18 @@ static uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
 
 // Optional restrictions of a one-problem run (device pointers): cand / ncand
 // restrict the preserved columns to a list, jmask marks them for the
-// reduction, gate / gate_on make every kernel a no-op unless *gate == gate_on.
+// reduction, gate / gate_on make every kernel a no-op unless *gate == gate_on,
+// ci (ungated runs) is the problem's column info computed by an earlier
+// kernel on the same stream.
 struct RunOpts {
   const int *cand;
   int ncand;
   const int *jmask;
   const int *gate;
   int gate_on;
+  const ColInfo *ci;
 };
-static const RunOpts kNoOpts = {nullptr, 0, nullptr, nullptr, 0};
+static const RunOpts kNoOpts = {nullptr, 0, nullptr, nullptr, 0, nullptr};
 
 // Build the layout, stage the metadata, launch (or replay) the sequence.
 // `only_seg_ms` (autotuner): time the segment kernel alone.
@@ -603,8 +606,14 @@ static int launch_seq(l1line_ctx ctx, hipStream_t ls, const BatchLayout &Ly, cha
   {
     ProfScope ps(pc, ls, "colprep");
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ls, dcounter, 16ll, 0);
-    hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
-                       (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
+    if (ro.ci && B == 1 && !ro.gate) {
+      HIP_TRY(hipMemcpyAsync(dci, ro.ci, sizeof(ColInfo) * Ly.total_cols, hipMemcpyDeviceToDevice, ls));
+      hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((Ly.total_cols + 255) / 256)), dim3(256), 0, ls, dsegflags,
+                         (long long)Ly.total_cols, 0);
+    } else {
+      hipLaunchKernelGGL(k_colprep_batch, dim3((unsigned)((Ly.total_cols + 3) / 4)), dim3(256), 0, ls, dP, dcol,
+                         (int)B, (int)Ly.total_cols, dci, dsegflags, ro.gate, ro.gate_on);
+    }
   }
   {
     ProfScope ps(pc, ls, "signsum");
@@ -1489,11 +1498,12 @@ static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   HIP_TRY(hipGetLastError());
   const l1line_problem p = single(X, n, m, ld, &lambda, 1, v, j, obj, median_row, nullptr, status);
   // exact solve of the K candidates
-  const RunOpts rc{cand, (int)K, mask, nullptr, 0};
+  // (the column info the features computed)
+  const RunOpts rc{cand, (int)K, mask, nullptr, 0, (const ColInfo *)(b + R.o_ci)};
   st = run_batch(ctx, &p, 1, 0, s, tune_for(ctx, &p, 1), nullptr, rc);
   if (st) return st;
   // exhaustive solve, which does nothing unless the margin test failed
-  const RunOpts rf{nullptr, 0, nullptr, flag, 1};
+  const RunOpts rf{nullptr, 0, nullptr, flag, 1, nullptr};
   st = run_batch(ctx, &p, 1, 0, s, tune_for(ctx, &p, 1), nullptr, rf);
   if (st) return st;
   if (used_fallback) hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, s, flag, used_fallback);
