@@ -125,7 +125,7 @@ def test_rows_beyond_16384_structured_and_ties(ctx):
 
 
 @pytest.mark.parametrize("kind,n,m", [("rank1", 10000, 8), ("rank1", 30000, 6), ("int", 40000, 4),
-                                      ("int", 12000, 5)])
+                                      ("int", 12000, 5), ("cauchy", 15000, 7), ("mix", 25000, 6)])
 def test_one_penalty_windows_too_full_for_the_list(ctx, kind, n, m):
     # one penalty at many rows: the sampled key window around the median
     # holds more elements than the list, so it is bisected before the exact
@@ -135,11 +135,25 @@ def test_one_penalty_windows_too_full_for_the_list(ctx, kind, n, m):
         X = wl.rank_one_matrix(n, m, max(2, m // 2), n // 10, 20.0, 0.01, (35, n, m))
         mass = wl.max_column_mass(X)
         lams = [0.0, 0.01 * mass, 0.05 * mass]
-    else:
+    elif kind == "int":
         # a rounded rank-one matrix: 42 distinct integers, medians on ties
         X = np.asfortranarray(np.rint(3.0 * wl.rank_one_matrix(n, m, m, n // 10, 2.0, 0.05, (36, n, m),
                                                              laplace_b=0.2)))
         lams = [0.0, 10.0, 0.05 * wl.max_column_mass(X)]
+    else:
+        # heavy-tailed noise (Cauchy), or a fifth of the rows replaced by
+        # large outliers: ratio clusters with far tails
+        rng = np.random.default_rng(n + m)
+        X = np.outer(rng.standard_normal(n), rng.uniform(-1.0, 1.0, m))
+        if kind == "cauchy":
+            X = X + 0.05 * rng.standard_cauchy((n, m))
+        else:
+            X = X + 0.1 * rng.laplace(size=(n, m))
+            rows = rng.choice(n, n // 5, replace=False)
+            X[rows] = 50.0 * rng.standard_normal((n // 5, m))
+        X = np.asfortranarray(X)
+        mass = wl.max_column_mass(X)
+        lams = [0.0, 0.02 * mass, 0.08 * mass]
     for lam in lams:
         _say(f"case one penalty {kind} {n}x{m} lambda={lam!r}")
         g = gpu_fit(ctx, X, float(lam))
