@@ -293,7 +293,8 @@ int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2,
  * = better candidate), the K best columns solved exactly by Algorithm 1
  * restricted to them; if the score gap between the best column and the
  * first one left out is below margin_threshold (or K = m) the exhaustive
- * search runs instead (decided on the device, no host synchronisation).
+ * search runs instead (decided on the device, no host synchronisation; the
+ * FP32 score gap is compared with the threshold in double).
  *   v, j, obj, median_row, status  as l1line_fit (DEVICE)
  *   used_fallback  [1] 1 when the exhaustive search ran (DEVICE, nullable)
  *   scores         [m] the MLP scores (DEVICE, nullable)
@@ -302,7 +303,7 @@ int l1line_mlp_adam(l1line_ctx ctx, float *params, float *m1, float *m2,
  * weights were loaded, set or trained. */
 int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m,
                       int64_t ld, double lambda, int32_t K,
-                      float margin_threshold, double *v, int64_t *j,
+                      double margin_threshold, double *v, int64_t *j,
                       double *obj, int32_t *median_row,
                       int32_t *used_fallback, float *scores, int32_t *status,
                       void *stream);

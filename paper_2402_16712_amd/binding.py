@@ -89,7 +89,7 @@ def lib() -> ctypes.CDLL:
         L.l1line_mlp_forward.argtypes = [P, P, P, I64, P, P]
         L.l1line_mlp_grad.argtypes = [P, P, P, P, I64, P, P, P]
         L.l1line_mlp_adam.argtypes = [P, P, P, P, P, I64, F32, P]
-        L.l1line_fit_ranked.argtypes = [P, P, I64, I64, I64, D, I32, F32, P, P, P, P, P, P, P, P]
+        L.l1line_fit_ranked.argtypes = [P, P, I64, I64, I64, D, I32, D, P, P, P, P, P, P, P, P]
         L.l1line_profile.argtypes = [P, I32]
         L.l1line_measure_peaks.argtypes = [P, P]
         L.l1line_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D),

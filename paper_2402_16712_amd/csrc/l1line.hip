@@ -1461,7 +1461,7 @@ __global__ void k_copy_flag(const int *src, int *dst) {
 }
 
 static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda,
-                           int32_t K, float margin_threshold, double *v, int64_t *j, double *obj,
+                           int32_t K, double margin_threshold, double *v, int64_t *j, double *obj,
                            int32_t *median_row, int32_t *used_fallback, float *scores, int32_t *status,
                            void *stream) {
   if (!ctx || !v || !j || !obj) return L1LINE_EINVAL;
@@ -1469,7 +1469,7 @@ static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
   if (st) return st;
   st = check_lambdas(&lambda, 1);
   if (st) return st;
-  if (K < 1 || K > m || !(margin_threshold >= 0.0f) || isinf(margin_threshold)) return L1LINE_EINVAL;
+  if (K < 1 || K > m || !(margin_threshold >= 0.0) || isinf(margin_threshold)) return L1LINE_EINVAL;
   if (m > L1LINE_RANKER_MAX_M) return L1LINE_ESIZE;
   if (!ctx->rk_have_w) return L1LINE_ENOMODEL;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1512,7 +1512,7 @@ static int fit_ranked_impl(l1line_ctx ctx, const double *X, int64_t n, int64_t m
 }
 
 int l1line_fit_ranked(l1line_ctx ctx, const double *X, int64_t n, int64_t m, int64_t ld, double lambda, int32_t K,
-                      float margin_threshold, double *v, int64_t *j, double *obj, int32_t *median_row,
+                      double margin_threshold, double *v, int64_t *j, double *obj, int32_t *median_row,
                       int32_t *used_fallback, float *scores, int32_t *status, void *stream) {
   return note(ctx, fit_ranked_impl(ctx, X, n, m, ld, lambda, K, margin_threshold, v, j, obj, median_row,
                                    used_fallback, scores, status, stream));

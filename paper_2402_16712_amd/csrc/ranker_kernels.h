@@ -491,7 +491,7 @@ __global__ void k_features(const double *__restrict__ agg, int m, int n, double 
 // K smallest scores (lowest index on ties), their list in increasing score,
 // a candidate mask, and the margin between the first score left out and the
 // best; fallback = (margin < threshold) or K >= m.
-__global__ void k_topk(const float *__restrict__ score, int m, int K, float threshold, int *__restrict__ cand,
+__global__ void k_topk(const float *__restrict__ score, int m, int K, double threshold, int *__restrict__ cand,
                        int *__restrict__ mask, int *__restrict__ fallback, float *__restrict__ margin_out) {
   __shared__ float sv[256];
   __shared__ int si[256];
@@ -540,7 +540,7 @@ __global__ void k_topk(const float *__restrict__ score, int m, int K, float thre
     *margin_out = mg;
     // a NaN margin (every score non-finite: inf - inf) or a non-finite best
     // score separates nothing: the exhaustive search decides
-    *fallback = (K >= m || !(mg >= threshold) || !isfinite(best0)) ? 1 : 0;
+    *fallback = (K >= m || !((double)mg >= threshold) || !isfinite(best0)) ? 1 : 0;
   }
 }
 
@@ -552,7 +552,7 @@ __global__ void k_topk(const float *__restrict__ score, int m, int K, float thre
 constexpr int TOPK_LDS_MAX = 8192;
 
 __global__ void __launch_bounds__(1024)
-k_topk_lds(const float *__restrict__ score, int m, int K, float threshold, int *__restrict__ cand,
+k_topk_lds(const float *__restrict__ score, int m, int K, double threshold, int *__restrict__ cand,
            int *__restrict__ mask, int *__restrict__ fallback, float *__restrict__ margin_out) {
   __shared__ unsigned long long key[TOPK_LDS_MAX];
   const int tid = threadIdx.x;
@@ -593,7 +593,7 @@ k_topk_lds(const float *__restrict__ score, int m, int K, float threshold, int *
     const float best0 = key_score((uint32_t)(key[0] >> 32));
     const float mg = (K < m) ? key_score((uint32_t)(key[K] >> 32)) - best0 : 0.f;
     *margin_out = mg;
-    *fallback = (K >= m || !(mg >= threshold) || !isfinite(best0)) ? 1 : 0;
+    *fallback = (K >= m || !((double)mg >= threshold) || !isfinite(best0)) ? 1 : 0;
   }
 }
 
